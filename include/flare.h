@@ -1,0 +1,205 @@
+/*
+ * flare.h - C ABI of the MI355X (gfx950) evaluator for the FLARE B2 Bayesian force field.
+ *
+ * What it computes (paper: Section V.B and Eqs. 1-2). For every atom i of one or more
+ * periodic orthorhombic cells:
+ *   rho_i      all neighbours j (and periodic images) closer than r_cut         (Sec. V.B)
+ *   c_i        c_{(s,n),l,m} = sum_{j in rho_i, s_j = s} T_n(2r/r_c - 1) (r_c - r)^2 Y_lm(r^)
+ *   d~_i       B2: d~_{(a,b),l} = sum_m c_{a,l,m} c_{b,l,m}, a <= b            (Sec. V.B, Fig. 3)
+ *   d_i        d~_i / |d~_i|
+ *   e_i        d_i^T beta_{s_i} d_i      (mapped posterior mean, Eq. 1)
+ *   V_i        d_i^T Sigma_{s_i} d_i     (mapped posterior variance, Eq. 2; sigma_i = sqrt V_i)
+ *   F_k        -dE/dr_k, E = sum_i e_i  (by the reordered adjoint sum of Sec. V.B: no
+ *              descriptor gradient is ever formed)
+ * Atoms whose neighbours within the list radius are all of one species use only that
+ * species-pair block of d and of beta/Sigma (the reduction of Sec. V.B); the result
+ * is identical because the other components are exactly zero.
+ *
+ * Conventions shared by every call:
+ *   - Units: Angstrom, eV, eV/A, amu, fs. Species are 0 .. n_species-1 (H = 0, Pt = 1).
+ *   - Pointers documented as DEVICE must point to memory the caller allocated on the
+ *     current HIP device (for example torch tensors); the caller owns them and keeps
+ *     them alive until the enqueued work completes. HOST pointers are read during the call.
+ *   - Every call enqueues on the stream given at flare_state_create and returns without
+ *     waiting, unless documented as SYNCHRONISING.
+ *   - Atom arrays are in the caller's order. Structures (cells) occupy consecutive atom
+ *     ranges struct_offsets[k] .. struct_offsets[k+1]-1; each has its own box.
+ *   - Return value: FLARE_OK (0) or a negative FLARE_E_* code. Nothing throws across the
+ *     ABI. flare_last_error() gives a human-readable detail of the last failure on the
+ *     calling thread.
+ *   - Conditions found on the device (non-finite input, list overflow, atoms moved more
+ *     than half the skin since the last list build) set bits of a status word that only
+ *     flare_status reads, so the per-step calls stay asynchronous.
+ */
+#ifndef FLARE_H
+#define FLARE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define FLARE_OK             0
+#define FLARE_E_ARG         -1  /* null pointer, bad size or out-of-range parameter            */
+#define FLARE_E_SPECIES     -2  /* a species index outside [0, n_species)                       */
+#define FLARE_E_BOX         -3  /* a box side <= 0 or not finite                                */
+#define FLARE_E_CAPACITY    -4  /* more atoms or pairs than the state was created for           */
+#define FLARE_E_NONFINITE   -5  /* a position is NaN or infinite                                */
+#define FLARE_E_STALE       -6  /* call order: no neighbour list / no descriptors for this step */
+#define FLARE_E_OOM         -7  /* device allocation failed                                     */
+#define FLARE_E_HIP         -8  /* HIP runtime error (detail in flare_last_error)                */
+#define FLARE_E_UNSUPPORTED -9  /* model sizes this build has no kernels for                    */
+
+/* ---- arithmetic of the quadratic forms ---- */
+#define FLARE_FP32        0  /* FP32 matrix cores, FP32 accumulation                          */
+#define FLARE_BF16_SPLIT  1  /* beta = beta_hi + beta_lo in BF16 (reserved)                     */
+#define FLARE_FP8_SPLIT   2  /* beta = beta_hi + beta_lo in FP8 e4m3 (reserved)                 */
+
+/* ---- device status bits (flare_status) ---- */
+#define FLARE_FLAG_NONFINITE  1  /* a position was NaN/inf                                     */
+#define FLARE_FLAG_SPECIES    2  /* a species index was out of range                            */
+#define FLARE_FLAG_DISPLACED  4  /* some atom moved more than skin/2 since the list was built    */
+
+typedef struct flare_model flare_model;
+typedef struct flare_state flare_state;
+
+/* Last error detail of the calling thread (static storage, never NULL). */
+const char* flare_last_error(void);
+/* Short name of a status code. */
+const char* flare_strerror(int code);
+
+/*
+ * Create a model: one mapped pair (beta_s, Sigma_s) per central species s (Eqs. 1-2).
+ *   beta_host, sigma_host: HOST, FP64, [n_species][n_d][n_d] row-major, symmetric,
+ *   indexed in the packed B2 order: species-pair blocks (s1 <= s2) in order, inside a
+ *   block the radial pairs (n_a, n_b) row-major (n_a <= n_b when s1 == s2), l fastest.
+ *   n_d = n_species*n_rad*(n_species*n_rad+1)/2 * (l_max+1).
+ * This build has kernels for n_species = 2, n_rad = 8, l_max = 3 (n_d = 544); other
+ * sizes return FLARE_E_UNSUPPORTED. precision: FLARE_FP32.
+ * The library copies the matrices to device memory it owns. Runs on the current device.
+ */
+int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, double r_cut,
+                       const double* beta_host, const double* sigma_host, int precision);
+int flare_model_destroy(flare_model* model);
+/* n_d of the model (544 for the supported sizes). */
+int flare_descriptor_dim(const flare_model* model, int* n_d);
+
+/*
+ * Create evaluation state for up to max_atoms atoms and max_pairs directed list pairs.
+ * stream: a hipStream_t (passed as void*; NULL = the default stream). The state keeps
+ * the neighbour list, the descriptors and the gradients on the device between calls,
+ * and grows its descriptor buffers at list builds when the environment mix needs it.
+ * One state serves one stream; calls on one state must not overlap.
+ */
+int flare_state_create(flare_state** out, const flare_model* model, int max_atoms,
+                       long long max_pairs, void* stream);
+int flare_state_destroy(flare_state* state);
+
+/*
+ * Build the neighbour list (SYNCHRONISING: waits for the stream once to size buffers).
+ *   x, y, z       DEVICE FP64 [n_atoms] positions (any periodic image)
+ *   species       DEVICE int32 [n_atoms]
+ *   n_struct      number of cells; struct_offsets_host HOST int32 [n_struct+1]
+ *                 (offsets[0] = 0, offsets[n_struct] = n_atoms, non-decreasing)
+ *   boxes_host    HOST FP64 [n_struct][3] orthorhombic sides, periodic on every axis
+ *   skin          list radius = r_cut + skin (skin >= 0)
+ * A pair (i, j, s) is listed when |w_j - w_i + s*L|^2 < (r_cut+skin)^2, with
+ * w = x - L*floor(x/L) and the squared distance evaluated in FP64 as
+ * (dx*dx + dy*dy) + dz*dz without fused multiply-add; (i, i, 0) is excluded.
+ * Errors: FLARE_E_ARG, FLARE_E_BOX, FLARE_E_SPECIES, FLARE_E_NONFINITE,
+ * FLARE_E_CAPACITY (n_atoms > max_atoms or pairs > max_pairs: the list is not usable;
+ * create a larger state), FLARE_E_OOM, FLARE_E_HIP.
+ */
+int flare_neighbors(flare_state* state, int n_atoms, const double* x, const double* y,
+                    const double* z, const int32_t* species, int n_struct,
+                    const int32_t* struct_offsets_host, const double* boxes_host, double skin);
+
+/* Number of directed pairs in the current list and the atom count per environment
+ * class (HOST outputs; counts[6] in the order (H centre, H-only), (Pt, H-only),
+ * (H, Pt-only), (Pt, Pt-only), (H, mixed), (Pt, mixed); atoms with no neighbour are
+ * not counted). Either pointer may be NULL. Needs a list. Not synchronising. */
+int flare_list_info(const flare_state* state, long long* n_pairs, int* counts);
+
+/*
+ * Copy the list out in the caller's atom order and canonical per-atom order
+ * (j, sx, sy, sz) ascending (SYNCHRONISING). HOST outputs:
+ *   offsets [n_atoms+1] int64, j [n_pairs] int32, shifts [n_pairs][3] int32 (image s).
+ */
+int flare_neighbors_export(flare_state* state, long long* offsets, int32_t* j, int32_t* shifts);
+
+/*
+ * Descriptors for the current positions (same atoms, order and cells as the last list).
+ *   x, y, z   DEVICE FP64 [n_atoms]; the positions may have moved since the list build
+ *             (the status bit FLARE_FLAG_DISPLACED is set if any atom moved > skin/2).
+ *   d_out     optional DEVICE FP32 [n_atoms][n_d] normalised descriptors in the packed
+ *             order, zeros outside an atom's block (NULL = not written)
+ *   norm_out  optional DEVICE FP32 [n_atoms] |d~_i| (NULL = not written)
+ * The descriptors stay resident in the state for flare_energy_forces / flare_variance.
+ */
+int flare_descriptors(flare_state* state, const double* x, const double* y, const double* z,
+                      float* d_out, float* norm_out);
+
+/*
+ * Energies and forces from the resident descriptors (needs flare_descriptors first).
+ *   e_atom         DEVICE FP32 [n_atoms] e_i                         (NULL = not written)
+ *   fx, fy, fz     DEVICE FP32 [n_atoms] forces, eV/A                 (all three required)
+ *   e_struct       DEVICE FP64 [n_struct] sum of e_i per cell, compensated (NULL = skip)
+ *   var_atom, sigma_atom  DEVICE FP32 [n_atoms]: when either is non-NULL the variance
+ *                  quadratic form is evaluated in the same pass over the descriptors.
+ * Forces are accumulated with device atomics: they are reproducible to rounding, not
+ * bitwise.
+ */
+int flare_energy_forces(flare_state* state, float* e_atom, float* fx, float* fy, float* fz,
+                        double* e_struct, float* var_atom, float* sigma_atom);
+
+/*
+ * Variance and uncertainty only (Eq. 2), from the resident descriptors.
+ *   var_atom, sigma_atom  DEVICE FP32 [n_atoms] (either may be NULL)
+ *   sigma_max             DEVICE FP32 [n_struct] largest sigma per cell (NULL = skip)
+ */
+int flare_variance(flare_state* state, float* var_atom, float* sigma_atom, float* sigma_max);
+
+/*
+ * Velocity-Verlet halves on caller arrays (DEVICE FP64 [n_atoms] each; forces FP32).
+ *   first:  v += dt/2 * KAPPA * F / m ;  x += dt * v
+ *   second: v += dt/2 * KAPPA * F / m
+ * KAPPA = 9.648533212e-3 A^2 fs^-2 per eV/amu; masses_host HOST FP64 [n_species].
+ */
+int flare_md_first_half(flare_state* state, double* x, double* y, double* z, double* vx,
+                        double* vy, double* vz, const float* fx, const float* fy,
+                        const float* fz, const int32_t* species, const double* masses_host,
+                        double dt);
+int flare_md_second_half(flare_state* state, double* vx, double* vy, double* vz,
+                         const float* fx, const float* fy, const float* fz,
+                         const int32_t* species, const double* masses_host, double dt);
+
+/*
+ * Stage timers. When enabled, the library records a pair of HIP events on the state's
+ * stream around each stage it launches; flare_timers_read (SYNCHRONISING) returns the
+ * accumulated milliseconds and launch counts per stage (HOST outputs, FLARE_NTIMERS
+ * entries each; either may be NULL) and clears them when reset != 0.
+ */
+#define FLARE_NTIMERS 9
+#define FLARE_T_LIST      0  /* flare_neighbors device work                    */
+#define FLARE_T_DESC1     1  /* position gather + descriptors, 144-wide rows    */
+#define FLARE_T_DESCX     2  /* descriptors, 544-wide (mixed) rows              */
+#define FLARE_T_QFORM1    3  /* quadratic forms on the matrix cores, 144 rows   */
+#define FLARE_T_QFORMX    4  /* quadratic forms, 544 rows (GEMM + finish)       */
+#define FLARE_T_FORCE1    5  /* adjoint forces, 144 rows (incl. force clear)    */
+#define FLARE_T_FORCEX    6  /* adjoint forces, 544 rows                        */
+#define FLARE_T_OUT       7  /* caller-order outputs and per-cell reductions    */
+#define FLARE_T_MD        8  /* integrator halves                              */
+int flare_timers_enable(flare_state* state, int on);
+int flare_timers_read(flare_state* state, double* ms, long long* counts, int reset);
+
+/* Read and clear the device status word (SYNCHRONISING). flags_host: HOST int32.
+ * flare_neighbors starts a new interval: it clears the word before its own checks. */
+int flare_status(flare_state* state, int32_t* flags_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLARE_H */

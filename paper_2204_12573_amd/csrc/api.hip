@@ -1,0 +1,508 @@
+// C ABI: model and state objects, argument checks, call sequencing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "state.h"
+
+namespace flare {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+PairView pair_view(const flare_state* s) {
+  PairView v;
+  v.n = s->n_atoms;
+  v.pos = s->pos;
+  v.sp = s->sp;
+  v.sid = s->sid;
+  v.grids = s->d_grids.p;
+  v.nl_off = s->nl_off;
+  v.nl_j = s->nl_j;
+  v.nl_s = s->nl_s;
+  v.rc = (float)s->model->r_cut;
+  v.rc2 = s->model->r_cut * s->model->r_cut;
+  return v;
+}
+
+namespace {
+hipEvent_t take_event(flare_state* s) {
+  if (!s->timers.pool.empty()) {
+    hipEvent_t e = s->timers.pool.back();
+    s->timers.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+StageTimer::StageTimer(flare_state* st, int stg) : s(st), stage(stg) {
+  if (!s->timers.on) return;
+  hipEvent_t start = take_event(s);
+  stop = take_event(s);
+  if (!start || !stop) {
+    stop = nullptr;
+    return;
+  }
+  (void)hipEventRecord(start, s->stream);
+  s->timers.pending.push_back({stage, {start, stop}});
+}
+
+StageTimer::~StageTimer() {
+  if (stop) (void)hipEventRecord(stop, s->stream);
+}
+
+}  // namespace flare
+
+using namespace flare;
+
+#define CHK(call)                                                        \
+  do {                                                                   \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess) {                                              \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));      \
+      return e_ == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;      \
+    }                                                                    \
+  } while (0)
+
+#define ARG(cond, msg)          \
+  do {                          \
+    if (!(cond)) {              \
+      set_error(msg);           \
+      return FLARE_E_ARG;       \
+    }                           \
+  } while (0)
+
+extern "C" {
+
+const char* flare_last_error(void) { return g_last_error.c_str(); }
+
+const char* flare_strerror(int code) {
+  switch (code) {
+    case FLARE_OK: return "ok";
+    case FLARE_E_ARG: return "invalid argument";
+    case FLARE_E_SPECIES: return "species index out of range";
+    case FLARE_E_BOX: return "invalid box";
+    case FLARE_E_CAPACITY: return "capacity exceeded";
+    case FLARE_E_NONFINITE: return "non-finite position";
+    case FLARE_E_STALE: return "call order: missing neighbour list or descriptors";
+    case FLARE_E_OOM: return "device out of memory";
+    case FLARE_E_HIP: return "HIP runtime error";
+    case FLARE_E_UNSUPPORTED: return "unsupported model size or precision";
+    default: return "unknown status";
+  }
+}
+
+int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, double r_cut,
+                       const double* beta_host, const double* sigma_host, int precision) {
+  ARG(out && beta_host && sigma_host, "null pointer");
+  *out = nullptr;
+  ARG(std::isfinite(r_cut) && r_cut > 0.0, "r_cut must be positive");
+  if (n_species != NS || n_rad != NR || l_max != LMAX) {
+    set_error("this build has kernels for n_species=2, n_rad=8, l_max=3 only");
+    return FLARE_E_UNSUPPORTED;
+  }
+  if (precision != FLARE_FP32) {
+    set_error("only FLARE_FP32 is available");
+    return FLARE_E_UNSUPPORTED;
+  }
+  flare_model* m = new (std::nothrow) flare_model();
+  if (!m) return FLARE_E_OOM;
+  m->precision = precision;
+  m->r_cut = r_cut;
+  CHK(hipGetDevice(&m->device));
+  // descriptor block of each bucket inside the packed 544 vector
+  const int start[NBUCKET] = {0, 0, ND - ND1, ND - ND1, 0, 0};
+  for (int b = 0; b < NBUCKET; ++b) {
+    const int nb = bucket_width(b);
+    const int s = b < 4 ? (b & 1) : (b - 4);    // central species
+    std::vector<float> w((size_t)2 * nb * nb);
+    const double* parts[2] = {beta_host + (size_t)s * ND * ND, sigma_host + (size_t)s * ND * ND};
+    for (int part = 0; part < 2; ++part)
+      for (int n = 0; n < nb; ++n)
+        for (int k = 0; k < nb; ++k)    // row n of the stored part = column n of the matrix
+          w[(size_t)part * nb * nb + (size_t)n * nb + k] =
+              (float)parts[part][(size_t)(start[b] + k) * ND + (start[b] + n)];
+    hipError_t e = hipMalloc((void**)&m->W[b], w.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(m->W[b], w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      set_error(std::string("model upload: ") + hipGetErrorString(e));
+      flare_model_destroy(m);
+      return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
+    }
+  }
+  *out = m;
+  return FLARE_OK;
+}
+
+int flare_model_destroy(flare_model* m) {
+  if (!m) return FLARE_OK;
+  for (int b = 0; b < NBUCKET; ++b)
+    if (m->W[b]) (void)hipFree(m->W[b]);
+  delete m;
+  return FLARE_OK;
+}
+
+int flare_descriptor_dim(const flare_model* m, int* n_d) {
+  ARG(m && n_d, "null pointer");
+  *n_d = ND;
+  return FLARE_OK;
+}
+
+static void free_state(flare_state* s) {
+  void* ptrs[] = {s->perm, s->sp,  s->sid, s->bin,   s->envmask, s->bucket, s->row_of, s->nl_cnt,
+                  s->nl_off, s->w, s->off, s->pos,   s->nrm,     s->e_int,  s->v_int,  s->f_int,
+                  s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->d_status,
+                  s->d_info};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (s->h_info) (void)hipHostFree(s->h_info);
+  s->d_grids.release();
+  s->d_struct_off.release();
+  s->bin_count.release();
+  s->bin_start.release();
+  s->bin_fill.release();
+  s->blk_bucket.release();
+  s->blk_bucket_scan.release();
+  s->scan_scratch.release();
+  s->atom_of_row1.release();
+  s->atom_of_rowx.release();
+  s->D1.release();
+  s->G1.release();
+  s->Dx.release();
+  s->Gx.release();
+  s->Yx.release();
+  s->Px.release();
+  s->d_tasks.release();
+  s->d_first_task.release();
+  s->red_e.release();
+  s->red_s.release();
+}
+
+int flare_state_create(flare_state** out, const flare_model* model, int max_atoms,
+                       long long max_pairs, void* stream) {
+  ARG(out && model, "null pointer");
+  *out = nullptr;
+  ARG(max_atoms > 0 && max_pairs > 0, "capacities must be positive");
+  ARG(max_pairs <= 0x7fffffffLL, "max_pairs must fit in int32");
+  flare_state* s = new (std::nothrow) flare_state();
+  if (!s) return FLARE_E_OOM;
+  s->model = model;
+  s->stream = (hipStream_t)stream;
+  s->max_atoms = max_atoms;
+  s->max_pairs = max_pairs;
+  hipError_t e = hipGetDevice(&s->device);
+  const size_t n = (size_t)max_atoms;
+  auto al = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 4);
+  };
+  al((void**)&s->perm, n * 4);
+  al((void**)&s->sp, n * 4);
+  al((void**)&s->sid, n * 4);
+  al((void**)&s->bin, n * 4);
+  al((void**)&s->envmask, n * 4);
+  al((void**)&s->bucket, n * 4);
+  al((void**)&s->row_of, n * 4);
+  al((void**)&s->nl_cnt, n * 4);
+  al((void**)&s->nl_off, (n + 1) * 4);
+  al((void**)&s->w, 3 * n * 8);
+  al((void**)&s->off, 3 * n * 8);
+  al((void**)&s->pos, 3 * n * 8);
+  al((void**)&s->nrm, n * 4);
+  al((void**)&s->e_int, n * 4);
+  al((void**)&s->v_int, n * 4);
+  al((void**)&s->f_int, 3 * n * 4);
+  al((void**)&s->o_bin, n * 4);
+  al((void**)&s->o_sid, n * 4);
+  al((void**)&s->o_w, 3 * n * 8);
+  al((void**)&s->o_off, 3 * n * 8);
+  al((void**)&s->sorted, n * 4);
+  al((void**)&s->nl_j, (size_t)max_pairs * 4);
+  al((void**)&s->nl_s, (size_t)max_pairs * 4);
+  al((void**)&s->d_status, 64);
+  al((void**)&s->d_info, 64);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_info, 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(s->d_status, 0, 64, s->stream);
+  if (e != hipSuccess) {
+    set_error(std::string("state allocation: ") + hipGetErrorString(e));
+    free_state(s);
+    delete s;
+    return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
+  }
+  *out = s;
+  return FLARE_OK;
+}
+
+int flare_state_destroy(flare_state* s) {
+  if (!s) return FLARE_OK;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& pe : s->timers.pending) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (hipEvent_t e : s->timers.pool) (void)hipEventDestroy(e);
+  free_state(s);
+  delete s;
+  return FLARE_OK;
+}
+
+int flare_neighbors(flare_state* s, int n_atoms, const double* x, const double* y, const double* z,
+                    const int32_t* species, int n_struct, const int32_t* struct_offsets_host,
+                    const double* boxes_host, double skin) {
+  ARG(s, "null state");
+  s->have_list = false;
+  s->have_desc = false;
+  ARG(n_atoms >= 0, "n_atoms < 0");
+  ARG(n_struct >= 1, "n_struct must be >= 1");
+  ARG(struct_offsets_host && boxes_host, "null host array");
+  ARG(n_atoms == 0 || (x && y && z && species), "null device array");
+  ARG(std::isfinite(skin) && skin >= 0.0, "skin must be >= 0");
+  if (n_atoms > s->max_atoms) {
+    set_error("n_atoms exceeds max_atoms");
+    return FLARE_E_CAPACITY;
+  }
+  ARG(struct_offsets_host[0] == 0 && struct_offsets_host[n_struct] == n_atoms,
+      "struct offsets must start at 0 and end at n_atoms");
+  for (int c = 0; c < n_struct; ++c)
+    ARG(struct_offsets_host[c + 1] >= struct_offsets_host[c], "struct offsets must be non-decreasing");
+  const double rl = s->model->r_cut + skin;
+  s->grids.resize(n_struct);
+  s->struct_off.assign(struct_offsets_host, struct_offsets_host + n_struct + 1);
+  long long nbins = 0;
+  for (int c = 0; c < n_struct; ++c) {
+    CellGrid& g = s->grids[c];
+    for (int ax = 0; ax < 3; ++ax) {
+      const double L = boxes_host[3 * c + ax];
+      if (!(std::isfinite(L) && L > 0.0)) {
+        set_error("box side must be positive and finite");
+        return FLARE_E_BOX;
+      }
+      // bins at least r_list (with a relative margin far above rounding) wide
+      long long nb = (long long)std::floor(L / (rl * (1.0 + 1e-9)));
+      nb = std::max(1LL, std::min(nb, 4096LL));
+      const double h = L / (double)nb;
+      g.L[ax] = L;
+      g.nb[ax] = (int)nb;
+      g.inv_h[ax] = (double)nb / L;
+      g.K[ax] = (int)std::ceil(rl / h);
+      if (g.K[ax] > 100) {
+        set_error("box side too small for the list radius");
+        return FLARE_E_BOX;
+      }
+    }
+    g.bin_base = (int)nbins;
+    g.atom_base = struct_offsets_host[c];
+    nbins += (long long)g.nb[0] * g.nb[1] * g.nb[2];
+    if (nbins > (1LL << 30)) {
+      set_error("too many bins");
+      return FLARE_E_CAPACITY;
+    }
+  }
+  s->n_atoms = n_atoms;
+  s->n_struct = n_struct;
+  s->n_bins = (int)nbins;
+  s->skin = skin;
+  s->r_list = rl;
+  int rc;
+  {
+    StageTimer tm(s, FLARE_T_LIST);
+    rc = build_list(s, x, y, z, species);
+  }
+  if (rc != FLARE_OK) return rc;
+  s->have_list = true;
+  return FLARE_OK;
+}
+
+int flare_list_info(const flare_state* s, long long* n_pairs, int* counts) {
+  ARG(s, "null state");
+  if (!s->have_list) {
+    set_error("no neighbour list");
+    return FLARE_E_STALE;
+  }
+  if (n_pairs) *n_pairs = s->n_pairs;
+  if (counts)
+    for (int b = 0; b < NBUCKET; ++b) counts[b] = s->bucket_count[b];
+  return FLARE_OK;
+}
+
+int flare_neighbors_export(flare_state* s, long long* offsets, int32_t* j_out, int32_t* shifts) {
+  ARG(s && offsets && j_out && shifts, "null pointer");
+  if (!s->have_list) {
+    set_error("no neighbour list");
+    return FLARE_E_STALE;
+  }
+  const int n = s->n_atoms;
+  const long long P = s->n_pairs;
+  std::vector<int> perm(n), off(n + 1), jj(P), ss(P);
+  CHK(hipStreamSynchronize(s->stream));
+  CHK(hipMemcpy(perm.data(), s->perm, n * sizeof(int), hipMemcpyDeviceToHost));
+  CHK(hipMemcpy(off.data(), s->nl_off, (n + 1) * sizeof(int), hipMemcpyDeviceToHost));
+  CHK(hipMemcpy(jj.data(), s->nl_j, P * sizeof(int), hipMemcpyDeviceToHost));
+  CHK(hipMemcpy(ss.data(), s->nl_s, P * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<int> inv(n);
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  struct E {
+    int j, sx, sy, sz;
+  };
+  std::vector<E> row;
+  long long k = 0;
+  for (int a = 0; a < n; ++a) {
+    offsets[a] = k;
+    const int i = inv[a];
+    row.clear();
+    for (int p = off[i]; p < off[i + 1]; ++p) {
+      E e;
+      e.j = perm[jj[p]];
+      unpack_shift(ss[p], e.sx, e.sy, e.sz);
+      row.push_back(e);
+    }
+    std::sort(row.begin(), row.end(), [](const E& u, const E& v) {
+      if (u.j != v.j) return u.j < v.j;
+      if (u.sx != v.sx) return u.sx < v.sx;
+      if (u.sy != v.sy) return u.sy < v.sy;
+      return u.sz < v.sz;
+    });
+    for (const E& e : row) {
+      j_out[k] = e.j;
+      shifts[3 * k] = e.sx;
+      shifts[3 * k + 1] = e.sy;
+      shifts[3 * k + 2] = e.sz;
+      ++k;
+    }
+  }
+  offsets[n] = k;
+  return FLARE_OK;
+}
+
+int flare_descriptors(flare_state* s, const double* x, const double* y, const double* z, float* d_out,
+                      float* norm_out) {
+  ARG(s, "null state");
+  if (!s->have_list) {
+    set_error("flare_descriptors before flare_neighbors");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (x && y && z), "null positions");
+  gather_positions(s, x, y, z);
+  compute_descriptors(s);
+  export_descriptors(s, d_out, norm_out);
+  CHK(hipGetLastError());
+  s->have_desc = true;
+  return FLARE_OK;
+}
+
+int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, float* fz, double* e_struct,
+                        float* var_atom, float* sigma_atom) {
+  ARG(s, "null state");
+  if (!s->have_desc) {
+    set_error("flare_energy_forces before flare_descriptors");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (fx && fy && fz), "force outputs are required");
+  const bool want_v = var_atom || sigma_atom;
+  quadratic_forms(s, true, want_v);
+  compute_forces(s);
+  {
+    StageTimer tm(s, FLARE_T_OUT);
+    finalize_outputs(s, e_atom, fx, fy, fz, var_atom, sigma_atom);
+    reduce_cells(s, e_struct, nullptr);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_variance(flare_state* s, float* var_atom, float* sigma_atom, float* sigma_max) {
+  ARG(s, "null state");
+  if (!s->have_desc) {
+    set_error("flare_variance before flare_descriptors");
+    return FLARE_E_STALE;
+  }
+  quadratic_forms(s, false, true);
+  {
+    StageTimer tm(s, FLARE_T_OUT);
+    finalize_outputs(s, nullptr, nullptr, nullptr, nullptr, var_atom, sigma_atom);
+    reduce_cells(s, nullptr, sigma_max);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_md_first_half(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                        const float* fx, const float* fy, const float* fz, const int32_t* species,
+                        const double* masses_host, double dt) {
+  ARG(s && masses_host, "null pointer");
+  if (!s->have_list) {
+    set_error("integrator needs the atom count of a neighbour list");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (x && y && z && vx && vy && vz && fx && fy && fz && species), "null device array");
+  ARG(masses_host[0] > 0 && masses_host[1] > 0, "masses must be positive");
+  {
+    StageTimer tm(s, FLARE_T_MD);
+    md_first(s, x, y, z, vx, vy, vz, fx, fy, fz, species, 1.0 / masses_host[0], 1.0 / masses_host[1], dt);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_md_second_half(flare_state* s, double* vx, double* vy, double* vz, const float* fx, const float* fy,
+                         const float* fz, const int32_t* species, const double* masses_host, double dt) {
+  ARG(s && masses_host, "null pointer");
+  if (!s->have_list) {
+    set_error("integrator needs the atom count of a neighbour list");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (vx && vy && vz && fx && fy && fz && species), "null device array");
+  ARG(masses_host[0] > 0 && masses_host[1] > 0, "masses must be positive");
+  {
+    StageTimer tm(s, FLARE_T_MD);
+    md_second(s, vx, vy, vz, fx, fy, fz, species, 1.0 / masses_host[0], 1.0 / masses_host[1], dt);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_timers_enable(flare_state* s, int on) {
+  ARG(s, "null state");
+  s->timers.on = on != 0;
+  return FLARE_OK;
+}
+
+int flare_timers_read(flare_state* s, double* ms, long long* counts, int reset) {
+  ARG(s, "null state");
+  CHK(hipStreamSynchronize(s->stream));
+  for (auto& pe : s->timers.pending) {
+    float t = 0.f;
+    CHK(hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+    s->timers.ms[pe.first] += t;
+    s->timers.cnt[pe.first] += 1;
+    s->timers.pool.push_back(pe.second.first);
+    s->timers.pool.push_back(pe.second.second);
+  }
+  s->timers.pending.clear();
+  for (int k = 0; k < FLARE_NTIMERS; ++k) {
+    if (ms) ms[k] = s->timers.ms[k];
+    if (counts) counts[k] = s->timers.cnt[k];
+    if (reset) {
+      s->timers.ms[k] = 0.0;
+      s->timers.cnt[k] = 0;
+    }
+  }
+  return FLARE_OK;
+}
+
+int flare_status(flare_state* s, int32_t* flags_host) {
+  ARG(s && flags_host, "null pointer");
+  CHK(hipMemcpyAsync(s->h_info + 8, s->d_status, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  CHK(hipMemsetAsync(s->d_status, 0, sizeof(int), s->stream));
+  CHK(hipStreamSynchronize(s->stream));
+  *flags_host = s->h_info[8];
+  return FLARE_OK;
+}
+
+}  // extern "C"

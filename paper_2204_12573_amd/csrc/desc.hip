@@ -1,0 +1,234 @@
+// Per-atom densities, B2 contraction over m and normalisation (paper, Section V.B).
+//
+//   c_{(s,n),l,m} = sum_{j in rho_i, s_j = s, r_ij < r_c} R_n(r_ij) Y_lm(r^_ij)
+//   d~_{(a,b),l}  = sum_m c_{a,l,m} c_{b,l,m}    (a <= b, packed)
+//   d             = d~ / |d~|
+//
+// One thread per descriptor row; rows are grouped by environment bucket, so a wave
+// sees atoms of one kind (similar pair counts). A single-species atom keeps its 8x16
+// densities in registers and writes only its 144-component block. A mixed atom keeps
+// the H half in LDS (one column per thread) and the Pt half in registers.
+// Pair geometry: positions are FP64; Delta = (x_j - x_i) + s*L is formed in FP64 and
+// rounded to FP32 before the basis is evaluated.
+#include "basis.h"
+#include "pair.h"
+#include "state.h"
+
+namespace flare {
+namespace {
+
+constexpr int NT = 128;
+constexpr int NTX = 64;
+
+// 36 packed radial pairs (na <= nb) of a single-species block: 4 l-values each.
+// nrm2 accumulates sum d~^2; out (optional) receives scale * d~ as float4 per pair.
+__device__ __forceinline__ void b2_same(const float (*c)[NLM], float4* out, float scale,
+                                        float& nrm2) {
+  int k = 0;
+#pragma unroll
+  for (int na = 0; na < NR; ++na) {
+#pragma unroll
+    for (int nb = na; nb < NR; ++nb) {
+      float d0 = c[na][0] * c[nb][0];
+      float d1 = c[na][1] * c[nb][1] + c[na][2] * c[nb][2] + c[na][3] * c[nb][3];
+      float d2 = 0.f, d3 = 0.f;
+#pragma unroll
+      for (int lm = 4; lm < 9; ++lm) d2 += c[na][lm] * c[nb][lm];
+#pragma unroll
+      for (int lm = 9; lm < 16; ++lm) d3 += c[na][lm] * c[nb][lm];
+      nrm2 += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+      if (out) out[k] = make_float4(d0 * scale, d1 * scale, d2 * scale, d3 * scale);
+      ++k;
+    }
+  }
+}
+
+__device__ __forceinline__ float4 b2_pair(const float* a, const float* b) {
+  float d0 = a[0] * b[0];
+  float d1 = a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+  float d2 = 0.f, d3 = 0.f;
+#pragma unroll
+  for (int lm = 4; lm < 9; ++lm) d2 += a[lm] * b[lm];
+#pragma unroll
+  for (int lm = 9; lm < 16; ++lm) d3 += a[lm] * b[lm];
+  return make_float4(d0, d1, d2, d3);
+}
+
+__global__ __launch_bounds__(NT) void k_desc_single(PairView v, int rows,
+                                                    const int* __restrict__ atom_of_row,
+                                                    float* __restrict__ D,
+                                                    float* __restrict__ nrm_out) {
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  if (row >= rows) return;
+  float4* out = reinterpret_cast<float4*>(D + (size_t)row * ND1);
+  const int i = atom_of_row[row];
+  if (i < 0) {
+    for (int k = 0; k < NP1; ++k) out[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  float c[NR][NLM];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
+  accumulate_densities(v, i, -1, c);
+  float nrm2 = 0.f;
+  b2_same(c, nullptr, 1.f, nrm2);
+  const float nrm = sqrtf(nrm2);
+  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+  float dummy = 0.f;
+  b2_same(c, out, inv, dummy);
+  nrm_out[i] = nrm;
+}
+
+__global__ __launch_bounds__(NTX) void k_desc_mixed(PairView v, int rows,
+                                                    const int* __restrict__ atom_of_row,
+                                                    float* __restrict__ D,
+                                                    float* __restrict__ nrm_out) {
+  __shared__ float ch[NR * NLM][NTX];     // H-channel densities, one column per thread
+  const int t = threadIdx.x;
+  const int row = blockIdx.x * NTX + t;
+  if (row >= rows) return;
+  float4* out = reinterpret_cast<float4*>(D + (size_t)row * ND);
+  const int i = atom_of_row[row];
+  if (i < 0) {
+    for (int k = 0; k < ND / 4; ++k) out[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  float c[NR][NLM];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
+  accumulate_densities(v, i, 0, c);
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int lm = 0; lm < NLM; ++lm) {
+      ch[n * NLM + lm][t] = c[n][lm];
+      c[n][lm] = 0.f;
+    }
+  accumulate_densities(v, i, 1, c);     // c now holds the Pt channels
+  float a[NLM], b[NLM];
+  float scale = 1.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    float nrm2 = 0.f;
+    int k = 0;
+    // (H, H) block
+    for (int na = 0; na < NR; ++na) {
+#pragma unroll
+      for (int lm = 0; lm < NLM; ++lm) a[lm] = ch[na * NLM + lm][t];
+      for (int nb = na; nb < NR; ++nb) {
+#pragma unroll
+        for (int lm = 0; lm < NLM; ++lm) b[lm] = ch[nb * NLM + lm][t];
+        float4 d = b2_pair(a, b);
+        nrm2 += d.x * d.x + d.y * d.y + d.z * d.z + d.w * d.w;
+        if (pass) out[k] = make_float4(d.x * scale, d.y * scale, d.z * scale, d.w * scale);
+        ++k;
+      }
+    }
+    // (H, Pt) block
+    for (int na = 0; na < NR; ++na) {
+#pragma unroll
+      for (int lm = 0; lm < NLM; ++lm) a[lm] = ch[na * NLM + lm][t];
+#pragma unroll
+      for (int nb = 0; nb < NR; ++nb) {
+        float4 d = b2_pair(a, c[nb]);
+        nrm2 += d.x * d.x + d.y * d.y + d.z * d.z + d.w * d.w;
+        if (pass) out[k] = make_float4(d.x * scale, d.y * scale, d.z * scale, d.w * scale);
+        ++k;
+      }
+    }
+    // (Pt, Pt) block
+    b2_same(c, pass ? out + k : nullptr, scale, nrm2);
+    if (pass == 0) {
+      const float nrm = sqrtf(nrm2);
+      nrm_out[i] = nrm;
+      scale = nrm > 0.f ? 1.f / nrm : 0.f;
+    }
+  }
+}
+
+constexpr int NTG = 256;
+
+__global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict__ perm,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ off,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ pos, double lim2,
+                                                    int* __restrict__ status) {
+  const int i = blockIdx.x * NTG + threadIdx.x;
+  if (i >= n) return;
+  const int a = perm[i];
+  const double p0 = x[a] + off[i];
+  const double p1 = y[a] + off[(size_t)n + i];
+  const double p2 = z[a] + off[2 * (size_t)n + i];
+  pos[i] = p0;
+  pos[(size_t)n + i] = p1;
+  pos[2 * (size_t)n + i] = p2;
+  const double d0 = p0 - w[i], d1 = p1 - w[(size_t)n + i], d2 = p2 - w[2 * (size_t)n + i];
+  const double d2s = d0 * d0 + d1 * d1 + d2 * d2;
+  if (!(d2s <= lim2)) {
+    if (!isfinite(d2s)) atomicOr(status, FLARE_FLAG_NONFINITE);
+    else atomicOr(status, FLARE_FLAG_DISPLACED);
+  }
+}
+
+__global__ __launch_bounds__(NTG) void k_export_desc(int n, const int* __restrict__ perm,
+                                                     const int* __restrict__ bucket,
+                                                     const int* __restrict__ row_of,
+                                                     const float* __restrict__ D1,
+                                                     const float* __restrict__ Dx,
+                                                     const float* __restrict__ nrm,
+                                                     float* __restrict__ d_out,
+                                                     float* __restrict__ norm_out) {
+  const int i = blockIdx.x * NTG + threadIdx.x;
+  if (i >= n) return;
+  const int a = perm[i];
+  const int b = bucket[i];
+  if (norm_out) norm_out[a] = b < 0 ? 0.f : nrm[i];
+  if (!d_out) return;
+  float* o = d_out + (size_t)a * ND;
+  for (int k = 0; k < ND; ++k) o[k] = 0.f;
+  if (b < 0) return;
+  const int r = row_of[i];
+  if (b < 4) {
+    const int start = bucket_env(b) == 0 ? 0 : ND - ND1;
+    for (int k = 0; k < ND1; ++k) o[start + k] = D1[(size_t)r * ND1 + k];
+  } else {
+    for (int k = 0; k < ND; ++k) o[k] = Dx[(size_t)r * ND + k];
+  }
+}
+
+}  // namespace
+
+void gather_positions(flare_state* s, const double* x, const double* y, const double* z) {
+  const int n = s->n_atoms;
+  if (n == 0) return;
+  const double lim = 0.5 * s->skin;
+  k_gather_pos<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, x, y, z, s->off, s->w, s->pos,
+                                                           lim * lim, s->d_status);
+}
+
+void compute_descriptors(flare_state* s) {
+  const PairView v = pair_view(s);
+  StageTimer tm(s, FLARE_T_DESC1);
+  if (s->rows1 > 0)
+    k_desc_single<<<(s->rows1 + NT - 1) / NT, NT, 0, s->stream>>>(v, s->rows1, s->atom_of_row1.p, s->D1.p,
+                                                                  s->nrm);
+  StageTimer tm2(s, FLARE_T_DESCX);
+  if (s->rowsx > 0)
+    k_desc_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rowsx, s->atom_of_rowx.p,
+                                                                    s->Dx.p, s->nrm);
+}
+
+void export_descriptors(flare_state* s, float* d_out, float* norm_out) {
+  const int n = s->n_atoms;
+  if (n == 0 || (!d_out && !norm_out)) return;
+  k_export_desc<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, s->bucket, s->row_of, s->D1.p,
+                                                            s->Dx.p, s->nrm, d_out, norm_out);
+}
+
+}  // namespace flare

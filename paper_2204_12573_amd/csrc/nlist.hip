@@ -1,0 +1,380 @@
+// Cell-binned neighbour list and environment classification.
+//
+// The local environment rho_i is every atom (and periodic image) within the cutoff
+// (paper, Section V.B). The list is built with radius r_list = r_cut + skin:
+//   1. wrap every position into its cell, w = x - L*floor(x/L), and bin it on a grid
+//      of cells >= r_list per axis;
+//   2. counting sort by (cell, bin) with a deterministic order inside each bin, which
+//      also defines the internal atom order (spatially local);
+//   3. per atom, scan the (2K+1)^3 bins around it on the unwrapped bin lattice, so a
+//      box with fewer than three bins per axis (or narrower than r_list) visits each
+//      (bin, image shift) once; keep (j, s) with |w_j - w_i + s*L|^2 < r_list^2,
+//      evaluated in FP64 without fused multiply-add;
+//   4. OR the species bits of the neighbours: atoms that see one species only use that
+//      species-pair block of the descriptor (the reduction of Section V.B).
+#include "state.h"
+
+namespace flare {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline int floor_div(int u, int n) { return u >= 0 ? u / n : -((-u + n - 1) / n); }
+
+__global__ __launch_bounds__(NT) void k_wrap_bin(int n, const double* __restrict__ x,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ z,
+                                                 const int32_t* __restrict__ species,
+                                                 const int* __restrict__ cell_off, int n_cell,
+                                                 const CellGrid* __restrict__ grids,
+                                                 int* __restrict__ o_bin, int* __restrict__ o_sid,
+                                                 double* __restrict__ o_w,
+                                                 double* __restrict__ o_off,
+                                                 int* __restrict__ status) {
+#pragma clang fp contract(off)
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n) return;
+  int lo = 0, hi = n_cell - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (cell_off[mid] <= a) lo = mid;
+    else hi = mid - 1;
+  }
+  const CellGrid g = grids[lo];
+  int s = species[a];
+  if (s < 0 || s >= NS) atomicOr(status, FLARE_FLAG_SPECIES);
+  double p[3] = {x[a], y[a], z[a]};
+  int b[3];
+  bool finite = true;
+  for (int ax = 0; ax < 3; ++ax) finite = finite && isfinite(p[ax]);
+  if (!finite) {
+    atomicOr(status, FLARE_FLAG_NONFINITE);
+    p[0] = p[1] = p[2] = 0.0;
+  }
+  for (int ax = 0; ax < 3; ++ax) {
+    const double L = g.L[ax];
+    const double k = floor(p[ax] / L);
+    const double kl = L * k;
+    const double wv = p[ax] - kl;
+    int bi = (int)floor(wv * g.inv_h[ax]);
+    bi = bi < 0 ? 0 : (bi >= g.nb[ax] ? g.nb[ax] - 1 : bi);
+    b[ax] = bi;
+    o_w[(size_t)ax * n + a] = wv;
+    o_off[(size_t)ax * n + a] = -kl;
+  }
+  o_bin[a] = g.bin_base + (b[2] * g.nb[1] + b[1]) * g.nb[0] + b[0];
+  o_sid[a] = lo;
+}
+
+__global__ __launch_bounds__(NT) void k_bin_count(int n, const int* __restrict__ o_bin,
+                                                  int* __restrict__ cnt) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a < n) atomicAdd(&cnt[o_bin[a]], 1);
+}
+
+__global__ __launch_bounds__(NT) void k_bin_scatter(int n, const int* __restrict__ o_bin,
+                                                    const int* __restrict__ start,
+                                                    int* __restrict__ fill,
+                                                    int* __restrict__ sorted) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n) return;
+  const int b = o_bin[a];
+  sorted[start[b] + atomicAdd(&fill[b], 1)] = a;
+}
+
+// Inside each bin, order atoms by caller index (the scatter order is racy).
+__global__ __launch_bounds__(NT) void k_bin_sort(int nbins, const int* __restrict__ start,
+                                                 int* __restrict__ sorted) {
+  const int b = blockIdx.x * NT + threadIdx.x;
+  if (b >= nbins) return;
+  const int lo = start[b], hi = start[b + 1];
+  for (int k = lo + 1; k < hi; ++k) {
+    int v = sorted[k];
+    int m = k - 1;
+    while (m >= lo && sorted[m] > v) {
+      sorted[m + 1] = sorted[m];
+      --m;
+    }
+    sorted[m + 1] = v;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_to_internal(int n, const int* __restrict__ sorted,
+                                                    const int* __restrict__ o_bin,
+                                                    const int* __restrict__ o_sid,
+                                                    const double* __restrict__ o_w,
+                                                    const double* __restrict__ o_off,
+                                                    const int32_t* __restrict__ species,
+                                                    int* __restrict__ perm, int* __restrict__ sp,
+                                                    int* __restrict__ sid, int* __restrict__ bin,
+                                                    double* __restrict__ w,
+                                                    double* __restrict__ off) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int a = sorted[i];
+  perm[i] = a;
+  int s = species[a];
+  sp[i] = (s < 0 || s >= NS) ? 0 : s;
+  sid[i] = o_sid[a];
+  bin[i] = o_bin[a];
+  for (int ax = 0; ax < 3; ++ax) {
+    w[(size_t)ax * n + i] = o_w[(size_t)ax * n + a];
+    off[(size_t)ax * n + i] = o_off[(size_t)ax * n + a];
+  }
+}
+
+// Per-wave ballot counts of each bucket, combined per block into blk[b * nblk + block].
+__device__ inline void block_bucket_counts(int b, int* __restrict__ blk, int nblk) {
+  __shared__ int cnt[NBUCKET];
+  if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < NBUCKET; ++k) {
+    unsigned long long m = __ballot(b == k);
+    if (lane == 0 && m) atomicAdd(&cnt[k], __popcll(m));
+  }
+  __syncthreads();
+  if (threadIdx.x < NBUCKET) blk[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict__ grids,
+                                              const int* __restrict__ sid,
+                                              const int* __restrict__ bin,
+                                              const double* __restrict__ w,
+                                              const int* __restrict__ sp,
+                                              const int* __restrict__ bstart, double rl2,
+                                              int* __restrict__ cnt_out,
+                                              int* __restrict__ envmask,
+                                              int* __restrict__ bucket, int* __restrict__ blk,
+                                              int nblk, const int* __restrict__ nl_off,
+                                              int* __restrict__ nl_j, int32_t* __restrict__ nl_s) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * NT + threadIdx.x;
+  int b_out = -1;
+  if (i < n) {
+    const CellGrid g = grids[sid[i]];
+    const int local = bin[i] - g.bin_base;
+    const int bx = local % g.nb[0];
+    const int by = (local / g.nb[0]) % g.nb[1];
+    const int bz = local / (g.nb[0] * g.nb[1]);
+    const double wx = w[i], wy = w[(size_t)n + i], wz = w[2 * (size_t)n + i];
+    int cnt = 0, mask = 0;
+    long long o = FILL ? nl_off[i] : 0;
+    for (int oz = -g.K[2]; oz <= g.K[2]; ++oz) {
+      const int uz = bz + oz;
+      const int sz = floor_div(uz, g.nb[2]);
+      const int cz = uz - sz * g.nb[2];
+      const double tz = (double)sz * g.L[2];
+      for (int oy = -g.K[1]; oy <= g.K[1]; ++oy) {
+        const int uy = by + oy;
+        const int sy = floor_div(uy, g.nb[1]);
+        const int cy = uy - sy * g.nb[1];
+        const double ty = (double)sy * g.L[1];
+        for (int ox = -g.K[0]; ox <= g.K[0]; ++ox) {
+          const int ux = bx + ox;
+          const int sx = floor_div(ux, g.nb[0]);
+          const int cx = ux - sx * g.nb[0];
+          const double tx = (double)sx * g.L[0];
+          const int bb = g.bin_base + (cz * g.nb[1] + cy) * g.nb[0] + cx;
+          const int j0 = bstart[bb], j1 = bstart[bb + 1];
+          const bool zero_shift = (sx == 0) && (sy == 0) && (sz == 0);
+          for (int j = j0; j < j1; ++j) {
+            const double dx = (w[j] - wx) + tx;
+            const double dy = (w[(size_t)n + j] - wy) + ty;
+            const double dz = (w[2 * (size_t)n + j] - wz) + tz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rl2 && !(zero_shift && j == i)) {
+              if (FILL) {
+                nl_j[o + cnt] = j;
+                nl_s[o + cnt] = pack_shift(sx, sy, sz);
+              }
+              mask |= 1 << sp[j];
+              ++cnt;
+            }
+          }
+        }
+      }
+    }
+    if (!FILL) {
+      cnt_out[i] = cnt;
+      envmask[i] = mask;
+      b_out = bucket_of(sp[i], mask);
+      bucket[i] = b_out;
+    }
+  }
+  if (!FILL) block_bucket_counts(b_out, blk, nblk);
+}
+
+struct Row0 {
+  int r[NBUCKET];
+};
+
+__global__ __launch_bounds__(NT) void k_assign_rows(int n, const int* __restrict__ bucket,
+                                                    const int* __restrict__ blk_scan, int nblk,
+                                                    Row0 row0, int* __restrict__ row_of,
+                                                    int* __restrict__ aor1,
+                                                    int* __restrict__ aorx) {
+  __shared__ int wcnt[NT / 64][NBUCKET];
+  const int i = blockIdx.x * NT + threadIdx.x;
+  const int b = i < n ? bucket[i] : -1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int rank = 0;
+  for (int k = 0; k < NBUCKET; ++k) {
+    unsigned long long m = __ballot(b == k);
+    if (b == k) rank = __popcll(m & lt);
+    if (lane == 0) wcnt[wv][k] = __popcll(m);
+  }
+  __syncthreads();
+  if (i >= n) return;
+  if (b < 0) {
+    row_of[i] = -1;
+    return;
+  }
+  for (int v = 0; v < wv; ++v) rank += wcnt[v][b];
+  const int row = row0.r[b] + (blk_scan[b * nblk + blockIdx.x] - blk_scan[b * nblk]) + rank;
+  row_of[i] = row;
+  if (b < 4) aor1[row] = i;
+  else aorx[row] = i;
+}
+
+// info[0] = total pairs, info[1..6] = bucket totals, info[7] = status
+__global__ void k_info(int n, const int* __restrict__ nl_off, const int* __restrict__ blk_scan,
+                       int nblk, const int* __restrict__ status, int* __restrict__ info) {
+  if (threadIdx.x == 0) {
+    info[0] = nl_off[n];
+    for (int b = 0; b < NBUCKET; ++b) info[1 + b] = blk_scan[(b + 1) * nblk] - blk_scan[b * nblk];
+    info[7] = *status;
+  }
+}
+
+inline int grid_of(long long n) { return (int)((n + NT - 1) / NT); }
+
+#define HIPCHK(call)                                                     \
+  do {                                                                   \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess) {                                              \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));      \
+      return e_ == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;      \
+    }                                                                    \
+  } while (0)
+
+}  // namespace
+
+int build_list(flare_state* s, const double* x, const double* y, const double* z,
+               const int32_t* species) {
+  const int n = s->n_atoms;
+  hipStream_t st = s->stream;
+  const int nc = s->n_struct;
+  HIPCHK(s->d_grids.reserve(nc));
+  HIPCHK(s->d_struct_off.reserve(nc + 1));
+  HIPCHK(hipMemcpyAsync(s->d_grids.p, s->grids.data(), nc * sizeof(CellGrid), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->d_struct_off.p, s->struct_off.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  const int nbins = s->n_bins;
+  HIPCHK(s->bin_count.reserve(nbins + 1));
+  HIPCHK(s->bin_start.reserve(nbins + 1));
+  HIPCHK(s->bin_fill.reserve(nbins + 1));
+  const int nblk = grid_of(n);
+  HIPCHK(s->blk_bucket.reserve((size_t)NBUCKET * nblk + 1));
+  HIPCHK(s->blk_bucket_scan.reserve((size_t)NBUCKET * nblk + 1));
+  long long scan_n = std::max<long long>({(long long)nbins, (long long)n, (long long)NBUCKET * nblk});
+  HIPCHK(s->scan_scratch.reserve(scan_scratch_ints(scan_n)));
+  HIPCHK(hipMemsetAsync(s->d_status, 0, sizeof(int), st));
+  if (n > 0) {
+    k_wrap_bin<<<grid_of(n), NT, 0, st>>>(n, x, y, z, species, s->d_struct_off.p, nc, s->d_grids.p,
+                                          s->o_bin, s->o_sid, s->o_w, s->o_off, s->d_status);
+  }
+  HIPCHK(hipMemsetAsync(s->bin_count.p, 0, (nbins + 1) * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(s->bin_fill.p, 0, (nbins + 1) * sizeof(int), st));
+  if (n > 0) k_bin_count<<<grid_of(n), NT, 0, st>>>(n, s->o_bin, s->bin_count.p);
+  scan_exclusive(s->bin_count.p, s->bin_start.p, nbins, s->scan_scratch.p, st);
+  if (n > 0) {
+    k_bin_scatter<<<grid_of(n), NT, 0, st>>>(n, s->o_bin, s->bin_start.p, s->bin_fill.p, s->sorted);
+    k_bin_sort<<<grid_of(nbins), NT, 0, st>>>(nbins, s->bin_start.p, s->sorted);
+    k_to_internal<<<grid_of(n), NT, 0, st>>>(n, s->sorted, s->o_bin, s->o_sid, s->o_w, s->o_off,
+                                             species, s->perm, s->sp, s->sid, s->bin, s->w, s->off);
+  }
+  const double rl2 = s->r_list * s->r_list;
+  if (n > 0) {
+    k_pairs<false><<<nblk, NT, 0, st>>>(n, s->d_grids.p, s->sid, s->bin, s->w, s->sp, s->bin_start.p,
+                                         rl2, s->nl_cnt, s->envmask, s->bucket, s->blk_bucket.p, nblk,
+                                         nullptr, nullptr, nullptr);
+  }
+  scan_exclusive(s->nl_cnt, s->nl_off, n, s->scan_scratch.p, st);
+  scan_exclusive(s->blk_bucket.p, s->blk_bucket_scan.p, NBUCKET * nblk, s->scan_scratch.p, st);
+  k_info<<<1, 64, 0, st>>>(n, s->nl_off, s->blk_bucket_scan.p, nblk, s->d_status, s->d_info);
+  HIPCHK(hipMemcpyAsync(s->h_info, s->d_info, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int flags = s->h_info[7];
+  if (flags & FLARE_FLAG_SPECIES) {
+    set_error("species index outside [0, n_species)");
+    return FLARE_E_SPECIES;
+  }
+  if (flags & FLARE_FLAG_NONFINITE) {
+    set_error("non-finite position");
+    return FLARE_E_NONFINITE;
+  }
+  const long long pairs = (long long)(unsigned)s->h_info[0];
+  if (pairs > s->max_pairs) {
+    set_error("list needs " + std::to_string(pairs) + " pairs, state holds " + std::to_string(s->max_pairs));
+    return FLARE_E_CAPACITY;
+  }
+  s->n_pairs = pairs;
+  Row0 row0;
+  int r1 = 0, rx = 0;
+  for (int b = 0; b < NBUCKET; ++b) {
+    s->bucket_count[b] = s->h_info[1 + b];
+    const int padded = (s->bucket_count[b] + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+    if (b < 4) {
+      row0.r[b] = r1;
+      r1 += padded;
+    } else {
+      row0.r[b] = rx;
+      rx += padded;
+    }
+    s->bucket_row0[b] = row0.r[b];
+  }
+  s->rows1 = r1;
+  s->rowsx = rx;
+  HIPCHK(s->atom_of_row1.reserve(r1 + 1));
+  HIPCHK(s->atom_of_rowx.reserve(rx + 1));
+  HIPCHK(s->D1.reserve((size_t)r1 * ND1 + 64));
+  HIPCHK(s->G1.reserve((size_t)r1 * ND1 + 64));
+  HIPCHK(s->Dx.reserve((size_t)rx * ND + 64));
+  HIPCHK(s->Gx.reserve((size_t)rx * ND + 64));
+  HIPCHK(s->Yx.reserve((size_t)rx * ND + 64));
+  HIPCHK(s->Px.reserve((size_t)rx * 4 + 64));
+  HIPCHK(hipMemsetAsync(s->atom_of_row1.p, 0xff, (r1 + 1) * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(s->atom_of_rowx.p, 0xff, (rx + 1) * sizeof(int), st));
+  if (n > 0) {
+    k_pairs<true><<<nblk, NT, 0, st>>>(n, s->d_grids.p, s->sid, s->bin, s->w, s->sp, s->bin_start.p,
+                                        rl2, nullptr, nullptr, nullptr, nullptr, nblk, s->nl_off,
+                                        s->nl_j, s->nl_s);
+    k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->blk_bucket_scan.p, nblk, row0, s->row_of,
+                                        s->atom_of_row1.p, s->atom_of_rowx.p);
+  }
+  // reduction tasks: contiguous internal ranges of one cell, at most 16384 atoms each
+  s->tasks.clear();
+  for (int c = 0; c < nc; ++c) {
+    int a = s->struct_off[c], b = s->struct_off[c + 1];
+    if (a == b) s->tasks.push_back({c, a, a});
+    for (int k = a; k < b; k += 16384) s->tasks.push_back({c, k, std::min(b, k + 16384)});
+  }
+  s->first_task.assign(nc, 0);
+  for (int k = (int)s->tasks.size() - 1; k >= 0; --k) s->first_task[s->tasks[k].cell] = k;
+  HIPCHK(s->d_tasks.reserve(s->tasks.size()));
+  HIPCHK(s->d_first_task.reserve(nc));
+  HIPCHK(hipMemcpyAsync(s->d_first_task.p, s->first_task.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(s->red_e.reserve(2 * s->tasks.size()));
+  HIPCHK(s->red_s.reserve(s->tasks.size()));
+  HIPCHK(hipMemcpyAsync(s->d_tasks.p, s->tasks.data(), s->tasks.size() * sizeof(RedTask),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(s->e_int, 0, (size_t)n * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(s->v_int, 0, (size_t)n * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(s->nrm, 0, (size_t)n * sizeof(float), st));
+  HIPCHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+}  // namespace flare

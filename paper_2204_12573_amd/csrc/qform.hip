@@ -1,0 +1,294 @@
+// Mapped quadratic forms over atoms (paper, Eq. 1 and Eq. 2 after the exact mapping of
+// Section V.B): for the descriptor rows D of one environment bucket,
+//   Y = D [beta_b | Sigma_b]        (dense GEMM on the FP32 matrix cores, FP32 accumulate)
+//   e_i = sum_k Y_ik D_ik  over the beta columns,   V_i = the same over the Sigma columns
+//   g_i = (2/|d~_i|) (Y_i - e_i d_i)               (de_i/dd~_i, used by the adjoint)
+// beta_b / Sigma_b are the central species' matrices restricted to the bucket's
+// descriptor block (144 x 144 for single-species environments, 544 x 544 otherwise).
+//
+// Tiling: a work-group of 4 waves owns 128 rows; each wave owns 32 rows (two 16-row
+// blocks) x CB 16-column blocks, accumulated by v_mfma_f32_16x16x4_f32. K advances in
+// chunks of 16 staged in LDS (double-buffered). Inside a chunk the four k-steps are
+// interleaved so that each lane reads its four k-values of A and of B with one
+// 128-bit LDS load: k-step t, lane group g uses k = 4g + t (the same map for A and B,
+// which is all a sum over k requires). LDS rows are padded to 20 floats, which spreads
+// the eight 16-byte reads of each lane octet over distinct banks.
+#include "state.h"
+
+namespace flare {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int NTQ = 256;
+constexpr int KC = 16;          // K chunk
+constexpr int LDSW = KC + 4;    // padded LDS row (floats)
+constexpr int RB = 2;           // 16-row blocks per wave
+constexpr int TM = 4 * RB * 16; // rows per work-group (128)
+
+struct QArgs {
+  const float* D;        // [rows][KD]
+  float* G;              // [rows][KD]      gradient (beta part), fused path
+  const int* aor;        // atom of row (-1 padding)
+  const float* nrm;      // |d~| per atom
+  float* e_int;          // per atom
+  float* v_int;          // per atom
+  float* Y;              // [rows][KD]      beta-part products, split path
+  float* P;              // [rows][4]       partial row-dots, split path
+  int mode;              // bit 0: beta part, bit 1: Sigma part
+  int nbk;               // buckets in this launch
+  int row0[4];           // first row of each bucket (padded to TM)
+  int row1[4];           // one past its last padded row
+  const float* W[4];     // [(parts)*KD][KD] row n = column n of [beta | Sigma]
+};
+
+template <int KD, int CB, bool FUSED>
+__global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
+  constexpr int NC = CB * 16;                  // columns per work-group
+  constexpr int NCHUNK = KD / KC;
+  static_assert(KD % KC == 0, "K must be a multiple of the chunk");
+  __shared__ __attribute__((aligned(16))) float As[2][TM * LDSW];
+  __shared__ __attribute__((aligned(16))) float Bs[2][NC * LDSW];
+
+  const int tile = blockIdx.x;
+  const int ntile = blockIdx.y;
+  const int row0 = tile * TM;
+  // bucket of this tile (static indexing keeps the argument arrays out of scratch)
+  const float* Wb = q.W[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k)
+    if (k < q.nbk && row0 >= q.row0[k] && row0 < q.row1[k]) Wb = q.W[k];
+  const float* __restrict__ W = Wb + (size_t)ntile * NC * KD;
+  const float* __restrict__ D = q.D;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, grp = lane >> 4;
+
+  // global -> register staging: A 512 float4 (2 per thread), B NC*4 float4
+  constexpr int A_F4 = TM * KC / 4;
+  constexpr int B_F4 = NC * KC / 4;
+  constexpr int A_PER = A_F4 / NTQ;
+  constexpr int B_PER = (B_F4 + NTQ - 1) / NTQ;
+  float4 ra[A_PER], rb[B_PER];
+
+#define QF_GLOAD(chunk)                                                                       \
+  do {                                                                                        \
+    const int k0_ = (chunk) * KC;                                                             \
+    _Pragma("unroll") for (int u = 0; u < A_PER; ++u) {                                       \
+      const int idx = t + u * NTQ;                                                            \
+      ra[u] = *reinterpret_cast<const float4*>(D + (size_t)(row0 + (idx >> 2)) * KD + k0_ +   \
+                                               (idx & 3) * 4);                                \
+    }                                                                                         \
+    _Pragma("unroll") for (int u = 0; u < B_PER; ++u) {                                       \
+      int idx = t + u * NTQ;                                                                  \
+      idx = idx < B_F4 ? idx : B_F4 - 1;                                                      \
+      rb[u] = *reinterpret_cast<const float4*>(W + (size_t)(idx >> 2) * KD + k0_ + (idx & 3) * 4); \
+    }                                                                                         \
+  } while (0)
+
+#define QF_LSTORE(buf)                                                                        \
+  do {                                                                                        \
+    _Pragma("unroll") for (int u = 0; u < A_PER; ++u) {                                       \
+      const int idx = t + u * NTQ;                                                            \
+      *reinterpret_cast<float4*>(&As[buf][(idx >> 2) * LDSW + (idx & 3) * 4]) = ra[u];        \
+    }                                                                                         \
+    _Pragma("unroll") for (int u = 0; u < B_PER; ++u) {                                       \
+      const int idx = t + u * NTQ;                                                            \
+      if (idx < B_F4) *reinterpret_cast<float4*>(&Bs[buf][(idx >> 2) * LDSW + (idx & 3) * 4]) = rb[u]; \
+    }                                                                                         \
+  } while (0)
+
+  f4 acc[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  QF_GLOAD(0);
+  QF_LSTORE(0);
+  __syncthreads();
+  for (int c = 0; c < NCHUNK; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < NCHUNK) QF_GLOAD(c + 1);
+    float4 a[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      a[i] = *reinterpret_cast<const float4*>(&As[buf][(wave * 32 + i * 16 + l16) * LDSW + 4 * grp]);
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const float4 bv = *reinterpret_cast<const float4*>(&Bs[buf][(j * 16 + l16) * LDSW + 4 * grp]);
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, bv.x, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, bv.y, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, bv.z, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, bv.w, acc[i][j], 0, 0, 0);
+      }
+    }
+    if (c + 1 < NCHUNK) QF_LSTORE(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: lane holds Y[row = 4*grp + r][col = 16*j + l16] of each block ----
+  const bool has_e = q.mode & 1;
+  const int col_base = ntile * NC;
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    float pe[4] = {0.f, 0.f, 0.f, 0.f}, pv[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + wave * 32 + i * 16 + 4 * grp + r;
+      const float* drow = D + (size_t)row * KD;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int col = col_base + j * 16 + l16;
+        const bool beta_col = has_e && col < KD;
+        const int kcol = beta_col ? col : (has_e ? col - KD : col);
+        const float prod = acc[i][j][r] * drow[kcol];
+        if (beta_col) pe[r] += prod;
+        else pv[r] += prod;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int m = 1; m < 16; m <<= 1) {
+        pe[r] += __shfl_xor(pe[r], m, 64);
+        pv[r] += __shfl_xor(pv[r], m, 64);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + wave * 32 + i * 16 + 4 * grp + r;
+      const int atom = q.aor[row];
+      if (FUSED) {
+        if (atom >= 0 && l16 == 0) {
+          if (has_e) q.e_int[atom] = pe[r];
+          if (q.mode & 2) q.v_int[atom] = pv[r];
+        }
+        if (has_e) {
+          const float nv = atom >= 0 ? q.nrm[atom] : 0.f;
+          const float s2 = nv > 0.f ? 2.f / nv : 0.f;
+          const float* drow = D + (size_t)row * KD;
+          float* grow = q.G + (size_t)row * KD;
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            const int col = j * 16 + l16;
+            if (col < KD) grow[col] = s2 * (acc[i][j][r] - pe[r] * drow[col]);
+          }
+        }
+      } else {
+        if (l16 == 0) q.P[(size_t)row * 4 + ntile] = has_e && col_base < KD ? pe[r] : pv[r];
+        if (has_e && col_base < KD) {
+          float* yrow = q.Y + (size_t)row * KD;
+#pragma unroll
+          for (int j = 0; j < CB; ++j) yrow[col_base + j * 16 + l16] = acc[i][j][r];
+        }
+      }
+    }
+  }
+}
+
+#undef QF_GLOAD
+#undef QF_LSTORE
+
+// Finish the split path (544-wide rows): sum the partial row-dots, form g.
+__global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int ntiles,
+                                                      const float* __restrict__ D,
+                                                      const float* __restrict__ Y,
+                                                      const float* __restrict__ P,
+                                                      const int* __restrict__ aor,
+                                                      const float* __restrict__ nrm,
+                                                      float* __restrict__ G,
+                                                      float* __restrict__ e_int,
+                                                      float* __restrict__ v_int) {
+  // one wave per row
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int atom = aor[row];
+  if (atom < 0) return;
+  const float* p = P + (size_t)row * 4;
+  const bool has_e = mode & 1, has_v = mode & 2;
+  const int half = ntiles / ((has_e && has_v) ? 2 : 1);
+  float e = 0.f, v = 0.f;
+  if (has_e) {
+    for (int k = 0; k < half; ++k) e += p[k];
+  }
+  if (has_v) {
+    const int first = has_e ? half : 0;
+    for (int k = first; k < first + half; ++k) v += p[k];
+  }
+  if (lane == 0) {
+    if (has_e) e_int[atom] = e;
+    if (has_v) v_int[atom] = v;
+  }
+  if (!has_e) return;
+  const float nv = nrm[atom];
+  const float s2 = nv > 0.f ? 2.f / nv : 0.f;
+  const float* d = D + (size_t)row * ND;
+  const float* y = Y + (size_t)row * ND;
+  float* g = G + (size_t)row * ND;
+  for (int k = lane; k < ND; k += 64) g[k] = s2 * (y[k] - e * d[k]);
+}
+
+void launch_class(flare_state* s, bool single, int mode) {
+  const flare_model* m = s->model;
+  QArgs q{};
+  q.mode = mode;
+  q.nrm = s->nrm;
+  q.e_int = s->e_int;
+  q.v_int = s->v_int;
+  const int first = single ? 0 : 4, nb = single ? 4 : 2;
+  const int kd = single ? ND1 : ND;
+  q.nbk = nb;
+  for (int k = 0; k < nb; ++k) {
+    const int bk = first + k;
+    const int padded = (s->bucket_count[bk] + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+    q.row0[k] = s->bucket_row0[bk];
+    q.row1[k] = s->bucket_row0[bk] + padded;
+    q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)kd * kd);
+  }
+  const int rows = single ? s->rows1 : s->rowsx;
+  if (rows == 0) return;
+  const int tiles = rows / TM;
+  const int parts = ((mode & 1) ? 1 : 0) + ((mode & 2) ? 1 : 0);
+  if (single) {
+    q.D = s->D1.p;
+    q.G = s->G1.p;
+    q.aor = s->atom_of_row1.p;
+    if (parts == 2)
+      k_qform<ND1, 18, true><<<dim3(tiles, 1), NTQ, 0, s->stream>>>(q);
+    else
+      k_qform<ND1, 9, true><<<dim3(tiles, 1), NTQ, 0, s->stream>>>(q);
+  } else {
+    q.D = s->Dx.p;
+    q.G = s->Gx.p;
+    q.aor = s->atom_of_rowx.p;
+    q.Y = s->Yx.p;
+    q.P = s->Px.p;
+    const int ntiles = 2 * parts;   // 272 columns per tile
+    k_qform<ND, 17, false><<<dim3(tiles, ntiles), NTQ, 0, s->stream>>>(q);
+    k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
+                                                          s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int,
+                                                          s->v_int);
+  }
+}
+
+}  // namespace
+
+void quadratic_forms(flare_state* s, bool want_e, bool want_v) {
+  const int mode = (want_e ? 1 : 0) | (want_v ? 2 : 0);
+  if (!mode) return;
+  {
+    StageTimer tm(s, FLARE_T_QFORM1);
+    launch_class(s, true, mode);
+  }
+  {
+    StageTimer tm(s, FLARE_T_QFORMX);
+    launch_class(s, false, mode);
+  }
+}
+
+}  // namespace flare

@@ -1,0 +1,176 @@
+// Library-owned model and evaluation state (device buffers and host-side bookkeeping).
+#pragma once
+
+#include "common.h"
+#include "flare.h"
+
+namespace flare {
+
+// Small device array that grows at list builds (never on the per-step path).
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipError_t reserve(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    size_t want = n + n / 4 + 64;
+    hipError_t e = hipMalloc((void**)&p, want * sizeof(T));
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// Read-only view of the per-step pair data, passed to kernels by value.
+struct PairView {
+  int n;                              // atoms
+  const double* pos;                  // [3][n] internal positions
+  const int* sp;                      // species
+  const int* sid;                     // cell of each atom
+  const CellGrid* grids;              // per cell
+  const int* nl_off;                  // [n+1]
+  const int* nl_j;                    // neighbour (internal index)
+  const int32_t* nl_s;                // packed image shift
+  float rc;
+  double rc2;
+};
+
+// HIP-event stage timers (enabled on demand; see flare_timers_enable).
+struct Timers {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[FLARE_NTIMERS] = {};
+  long long cnt[FLARE_NTIMERS] = {};
+};
+
+// Reduction task: a contiguous internal atom range of one cell.
+struct RedTask {
+  int cell;
+  int begin;
+  int end;
+};
+
+}  // namespace flare
+
+struct flare_model {
+  int device = 0;
+  int precision = FLARE_FP32;
+  double r_cut = 0.0;
+  // Per bucket: [2*nb][nb] row-major; rows 0..nb-1 hold the beta sub-block and rows
+  // nb..2nb-1 the Sigma sub-block of the central species, restricted to the bucket's
+  // descriptor block (nb = 144 for single-species buckets, 544 for mixed).
+  float* W[flare::NBUCKET] = {};
+};
+
+struct flare_state {
+  const flare_model* model = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int max_atoms = 0;
+  long long max_pairs = 0;
+
+  // ---- current list ----
+  bool have_list = false;
+  bool have_desc = false;
+  int n_atoms = 0;
+  int n_struct = 0;
+  int n_bins = 0;
+  double skin = 0.0;
+  double r_list = 0.0;
+  long long n_pairs = 0;
+  int bucket_count[flare::NBUCKET] = {};
+  int bucket_row0[flare::NBUCKET] = {};   // first row of each bucket inside its class
+  int rows1 = 0;                           // padded rows of the 144-wide class
+  int rowsx = 0;                           // padded rows of the 544-wide class
+  std::vector<flare::CellGrid> grids;
+  std::vector<int> struct_off;
+  std::vector<flare::RedTask> tasks;
+  std::vector<int> first_task;
+
+  // ---- per-atom device arrays (capacity max_atoms) ----
+  int* perm = nullptr;       // internal -> caller index
+  int* sp = nullptr;         // species, internal order
+  int* sid = nullptr;        // cell id, internal order
+  int* bin = nullptr;        // global bin id, internal order
+  int* envmask = nullptr;    // species bits of listed neighbours
+  int* bucket = nullptr;
+  int* row_of = nullptr;     // row of each internal atom inside its width class (-1: none)
+  int* nl_cnt = nullptr;
+  int* nl_off = nullptr;     // [max_atoms + 1]
+  double* w = nullptr;       // [3][N] wrapped positions at the list build
+  double* off = nullptr;     // [3][N] image offset: internal position = x + off
+  double* pos = nullptr;     // [3][N] internal positions of the current step
+  float* nrm = nullptr;      // |d~| per internal atom
+  float* e_int = nullptr;
+  float* v_int = nullptr;
+  float* f_int = nullptr;    // [3][N]
+  // caller-order temporaries of the list build
+  int* o_bin = nullptr;
+  int* o_sid = nullptr;
+  double* o_w = nullptr;     // [3][N]
+  double* o_off = nullptr;   // [3][N]
+  int* sorted = nullptr;     // bin-sorted caller indices
+
+  // ---- per-pair ----
+  int* nl_j = nullptr;       // internal index of the neighbour
+  int32_t* nl_s = nullptr;   // packed image shift
+
+  // ---- grow-at-build buffers ----
+  flare::DevBuf<flare::CellGrid> d_grids;
+  flare::DevBuf<int> d_struct_off;
+  flare::DevBuf<int> bin_count, bin_start, bin_fill;
+  flare::DevBuf<int> blk_bucket, blk_bucket_scan;   // [6][nblk]
+  flare::DevBuf<int> scan_scratch;
+  flare::DevBuf<int> atom_of_row1, atom_of_rowx;
+  flare::DevBuf<float> D1, G1, Dx, Gx, Yx, Px;       // descriptors, gradients, mixed Y, partials
+  flare::DevBuf<flare::RedTask> d_tasks;
+  flare::DevBuf<int> d_first_task;                   // [n_struct] first task of each cell
+  flare::DevBuf<double> red_e;                       // [tasks][2] (sum, compensation)
+  flare::DevBuf<float> red_s;                        // [tasks]
+
+  flare::Timers timers;
+
+  // ---- status ----
+  int* d_status = nullptr;   // device status word
+  int* d_info = nullptr;     // small device results read at list builds
+  int* h_info = nullptr;     // pinned host copy
+};
+
+namespace flare {
+PairView pair_view(const flare_state* s);
+
+// Records the stage's start event on construction and its stop event on destruction.
+struct StageTimer {
+  flare_state* s;
+  int stage;
+  hipEvent_t stop = nullptr;
+  StageTimer(flare_state* st, int stg);
+  ~StageTimer();
+};
+// launchers (nlist.hip, desc.hip, qform.hip, adjoint.hip, reduce.hip)
+int build_list(flare_state* s, const double* x, const double* y, const double* z,
+               const int32_t* species);
+void gather_positions(flare_state* s, const double* x, const double* y, const double* z);
+void compute_descriptors(flare_state* s);
+void export_descriptors(flare_state* s, float* d_out, float* norm_out);
+void quadratic_forms(flare_state* s, bool want_e, bool want_v);
+void compute_forces(flare_state* s);
+void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
+                      float* var_atom, float* sigma_atom);
+void reduce_cells(flare_state* s, double* e_struct, float* sigma_max);
+void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy,
+              double* vz, const float* fx, const float* fy, const float* fz,
+              const int32_t* species, double inv_m0, double inv_m1, double dt);
+void md_second(flare_state* s, double* vx, double* vy, double* vz, const float* fx,
+               const float* fy, const float* fz, const int32_t* species, double inv_m0,
+               double inv_m1, double dt);
+void set_error(const std::string& msg);
+}  // namespace flare

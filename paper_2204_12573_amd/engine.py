@@ -1,0 +1,195 @@
+"""Device-resident evaluator and MD driver over the C ABI.
+
+Every step of the force-field evaluation runs in the HIP library; this module only
+owns torch tensors (device memory), orders the calls and converts arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+MASSES = np.array([1.008, 195.084])   # amu, H and Pt
+
+
+class Model:
+    """Mapped per-species (beta_s, Sigma_s), FP64 host arrays [S, n_d, n_d] (Eqs. 1-2)."""
+
+    def __init__(self, beta, sigma, r_cut=4.5, n_rad=8, l_max=3, precision=B.FP32):
+        lib = B.load()
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        h = ctypes.c_void_p()
+        B.check(lib.flare_model_create(ctypes.byref(h), beta.shape[0], n_rad, l_max, float(r_cut),
+                                       B.ptr(beta), B.ptr(sigma), precision))
+        self.handle = h
+        self.r_cut = r_cut
+        d = ctypes.c_int()
+        B.check(lib.flare_descriptor_dim(h, ctypes.byref(d)))
+        self.n_desc = d.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            B.load().flare_model_destroy(self.handle)
+            self.handle = None
+
+
+class Evaluator:
+    """One flare_state: neighbour list, resident descriptors, outputs in caller order."""
+
+    def __init__(self, model: Model, max_atoms: int, max_pairs: int, stream=None,
+                 device="cuda"):
+        self.lib = B.load()
+        self.model = model
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        B.check(self.lib.flare_state_create(ctypes.byref(h), model.handle, int(max_atoms),
+                                            int(max_pairs), ctypes.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+        self.max_atoms = max_atoms
+        self.max_pairs = max_pairs
+        self.n = 0
+        self.n_struct = 0
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self.lib.flare_state_destroy(self.handle)
+            self.handle = None
+
+    # ---- list ----
+    def neighbors(self, pos, species, offsets, boxes, skin=0.2):
+        """pos: device FP64 [3, N]; species: device int32 [N]; offsets/boxes: host arrays."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+        boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+        n = pos.shape[1]
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_neighbors(self.handle, n, B.ptr(pos[0]), B.ptr(pos[1]), B.ptr(pos[2]),
+                                             B.ptr(species), len(boxes), B.ptr(offsets), B.ptr(boxes),
+                                             float(skin)))
+        self.n = n
+        self.n_struct = len(boxes)
+        self.species = species
+
+    def list_info(self):
+        npairs = ctypes.c_longlong()
+        counts = np.zeros(6, np.int32)
+        B.check(self.lib.flare_list_info(self.handle, ctypes.byref(npairs), B.ptr(counts)))
+        return npairs.value, counts
+
+    def export_list(self):
+        npairs, _ = self.list_info()
+        off = np.zeros(self.n + 1, np.int64)
+        j = np.zeros(max(npairs, 1), np.int32)
+        s = np.zeros((max(npairs, 1), 3), np.int32)
+        B.check(self.lib.flare_neighbors_export(self.handle, B.ptr(off), B.ptr(j), B.ptr(s)))
+        return off, j[:npairs], s[:npairs]
+
+    # ---- per step ----
+    def descriptors(self, pos, want_d=False, want_norm=False):
+        d = torch.empty((self.n, self.model.n_desc), dtype=torch.float32, device=self.device) if want_d else None
+        nrm = torch.empty(self.n, dtype=torch.float32, device=self.device) if want_norm else None
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_descriptors(self.handle, B.ptr(pos[0]), B.ptr(pos[1]), B.ptr(pos[2]),
+                                               B.ptr(d), B.ptr(nrm)))
+        return d, nrm
+
+    def energy_forces(self, out=None, want_var=False):
+        out = self._outputs(out, want_var)
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_energy_forces(self.handle, B.ptr(out["e"]), B.ptr(out["f"][0]),
+                                                 B.ptr(out["f"][1]), B.ptr(out["f"][2]), B.ptr(out["E"]),
+                                                 B.ptr(out.get("var")), B.ptr(out.get("sigma"))))
+        return out
+
+    def variance(self, out=None):
+        out = out or {}
+        dev = self.device
+        out.setdefault("var", torch.empty(self.n, dtype=torch.float32, device=dev))
+        out.setdefault("sigma", torch.empty(self.n, dtype=torch.float32, device=dev))
+        out.setdefault("sigma_max", torch.empty(self.n_struct, dtype=torch.float32, device=dev))
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_variance(self.handle, B.ptr(out["var"]), B.ptr(out["sigma"]),
+                                            B.ptr(out["sigma_max"])))
+        return out
+
+    def compute(self, pos, want_var=True, out=None):
+        self.descriptors(pos)
+        return self.energy_forces(out, want_var)
+
+    def timers(self, on=True):
+        B.check(self.lib.flare_timers_enable(self.handle, 1 if on else 0))
+
+    def read_timers(self, reset=True):
+        ms = np.zeros(len(B.TIMER_NAMES), np.float64)
+        cnt = np.zeros(len(B.TIMER_NAMES), np.int64)
+        B.check(self.lib.flare_timers_read(self.handle, B.ptr(ms), B.ptr(cnt), 1 if reset else 0))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(B.TIMER_NAMES)}
+
+    def status(self):
+        f = np.zeros(1, np.int32)
+        B.check(self.lib.flare_status(self.handle, B.ptr(f)))
+        return int(f[0])
+
+    def _outputs(self, out, want_var):
+        out = {} if out is None else out
+        dev = self.device
+        out.setdefault("e", torch.empty(self.n, dtype=torch.float32, device=dev))
+        out.setdefault("f", torch.empty((3, self.n), dtype=torch.float32, device=dev))
+        out.setdefault("E", torch.empty(self.n_struct, dtype=torch.float64, device=dev))
+        if want_var:
+            out.setdefault("var", torch.empty(self.n, dtype=torch.float32, device=dev))
+            out.setdefault("sigma", torch.empty(self.n, dtype=torch.float32, device=dev))
+        return out
+
+    # ---- integrator ----
+    def md_first_half(self, pos, vel, f, dt):
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_md_first_half(self.handle, B.ptr(pos[0]), B.ptr(pos[1]), B.ptr(pos[2]),
+                                                 B.ptr(vel[0]), B.ptr(vel[1]), B.ptr(vel[2]), B.ptr(f[0]),
+                                                 B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species),
+                                                 B.ptr(MASSES), float(dt)))
+
+    def md_second_half(self, vel, f, dt):
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_md_second_half(self.handle, B.ptr(vel[0]), B.ptr(vel[1]), B.ptr(vel[2]),
+                                                  B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species),
+                                                  B.ptr(MASSES), float(dt)))
+
+
+def to_device(pos, species, device="cuda"):
+    """numpy [N,3] FP64 + [N] int -> device SoA [3,N] FP64 and int32 [N]."""
+    p = torch.from_numpy(np.ascontiguousarray(np.asarray(pos, np.float64).T)).to(device)
+    s = torch.from_numpy(np.asarray(species, np.int32)).to(device)
+    return p, s
+
+
+class MD:
+    """Velocity-Verlet NVE with a neighbour-list rebuild every `rebuild` steps.
+
+    One step: half kick + drift, list rebuild when due, descriptors, energies, forces
+    (and variances), half kick. State (x, v) stays FP64 on the device.
+    """
+
+    def __init__(self, ev: Evaluator, pos, vel, species, offsets, boxes, dt=0.5, skin=0.2,
+                 rebuild=10, want_var=True):
+        self.ev, self.pos, self.vel = ev, pos, vel
+        self.species, self.offsets, self.boxes = species, offsets, boxes
+        self.dt, self.skin, self.rebuild, self.want_var = dt, skin, rebuild, want_var
+        self.nstep = 0
+        ev.neighbors(pos, species, offsets, boxes, skin)
+        self.out = ev.compute(pos, want_var)
+
+    def step(self):
+        ev = self.ev
+        ev.md_first_half(self.pos, self.vel, self.out["f"], self.dt)
+        self.nstep += 1
+        if self.nstep % self.rebuild == 0:
+            ev.neighbors(self.pos, self.species, self.offsets, self.boxes, self.skin)
+        ev.descriptors(self.pos)
+        ev.energy_forces(self.out, self.want_var)
+        ev.md_second_half(self.vel, self.out["f"], self.dt)
+        return self.out

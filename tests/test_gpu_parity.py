@@ -1,0 +1,164 @@
+"""HIP path vs the FP64 oracle through the C ABI: neighbour lists bit-exact, descriptors,
+energies, variances, uncertainties and forces within the FP32 bound."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import evaluate as oev, neighbors as onl
+from oracle.hyper import DEFAULT
+from paper_2204_12573_amd import structures as S
+
+from .gpu_util import TOL, gpu_eval, rel_max, rel_vec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def model():
+    return S.random_model(DEFAULT.n_desc)
+
+
+def _list_equal(res, pos, box, r_list, rows=None):
+    off, j, s = res["ev"].export_list()
+    if rows is None:
+        i0, j0, s0 = onl.brute_force(pos, box, r_list)
+        n = len(pos)
+        off0 = np.concatenate([[0], np.cumsum(np.bincount(i0, minlength=n))])
+        np.testing.assert_array_equal(off, off0)
+        np.testing.assert_array_equal(j, j0)
+        np.testing.assert_array_equal(s, s0)
+    else:
+        i0, j0, s0 = onl.brute_force_rows(pos, box, r_list, rows)
+        for a in rows:
+            m = i0 == a
+            np.testing.assert_array_equal(j[off[a]:off[a + 1]], j0[m], err_msg=f"atom {a}")
+            np.testing.assert_array_equal(s[off[a]:off[a + 1]], s0[m], err_msg=f"atom {a}")
+
+
+def _compare(res, ref, atoms=None, tol=TOL):
+    atoms = np.arange(len(res["e"])) if atoms is None else np.asarray(atoms)
+    rows = ref.row_of(atoms)
+    errs = {
+        "e": rel_max(res["e"][atoms], ref.e[rows]),
+        "sigma": rel_max(res["sigma"][atoms], ref.sigma[rows]),
+        "var": rel_max(res["var"][atoms], ref.v[rows]),
+        "f": rel_vec(res["f"][atoms], ref.f),
+        "norm": rel_max(res["norm"][atoms], ref.norm[rows]),
+    }
+    for k, v in errs.items():
+        assert v <= tol, (k, v, errs)
+    return errs
+
+
+def test_tiny_cell_list_descriptors_energy_forces(model):
+    beta, sigma = model
+    st = S.config_tiny()
+    print("case: tiny cell, 80 atoms", flush=True)
+    res = gpu_eval(st.pos, st.species, st.box, beta, sigma, want_d=True)
+    assert res["status"] == 0
+    _list_equal(res, st.pos, st.box, 4.7)
+    ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
+    assert np.abs(res["d"] - ref.d).max() <= 1e-6
+    _compare(res, ref)
+    assert abs(res["E"][0] - ref.energy) <= TOL * abs(ref.energy)
+    np.testing.assert_allclose(res["var2"], res["var"], rtol=1e-6, atol=0)
+    assert abs(res["sigma_max"][0] - ref.sigma.max()) <= TOL * ref.sigma.max()
+    # net force vanishes (translation invariance) to FP32 rounding of the pair terms
+    assert np.abs(res["f"].sum(0)).max() <= 1e-6 * np.abs(res["f"]).sum(0).max()
+
+
+def test_small_box_repeated_images(model):
+    # Ly = 4.8 A < 2 r_list: the same neighbour appears with several image shifts
+    beta, sigma = model
+    st = S.h2_over_pt111(3, 2, 3, vacuum=8.0, n_mol=2, seed=1)
+    print("case: small box 3x2x3", flush=True)
+    res = gpu_eval(st.pos, st.species, st.box, beta, sigma)
+    _list_equal(res, st.pos, st.box, 4.7)
+    ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
+    _compare(res, ref)
+
+
+def test_tiny_box_below_list_radius(model):
+    # a box side shorter than r_list (2.9 A < 4.7 A): stencil wider than one bin
+    beta, sigma = model
+    rng = np.random.default_rng(4)
+    box = np.array([2.9, 6.0, 7.5])
+    pos = rng.uniform(0, 1, (5, 3)) * box
+    species = np.array([1, 0, 1, 0, 0], np.int32)
+    print("case: box below list radius", flush=True)
+    res = gpu_eval(pos, species, box, beta, sigma)
+    _list_equal(res, pos, box, 4.7)
+    ref = oev.evaluate(pos, species, box, beta, sigma)
+    _compare(res, ref)
+
+
+def test_batch_of_cells(model):
+    beta, sigma = model
+    b = S.config_cells(n_cells=12, seed=2)
+    print("case: 12 cells", flush=True)
+    res = gpu_eval(b.pos, b.species, b.boxes, beta, sigma, offsets=b.offsets)
+    off, j, s = res["ev"].export_list()
+    for k in range(12):
+        st = b.structure(k)
+        lo, hi = b.offsets[k], b.offsets[k + 1]
+        i0, j0, s0 = onl.brute_force(st.pos, st.box, 4.7)
+        np.testing.assert_array_equal(j[off[lo]:off[hi]], j0 + lo)
+        np.testing.assert_array_equal(s[off[lo]:off[hi]], s0)
+        ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
+        sub = {key: (res[key][lo:hi] if isinstance(res[key], np.ndarray) and res[key].ndim >= 1
+                     and len(res[key]) == len(b.species) else res[key]) for key in res}
+        _compare(sub, ref)
+        assert abs(res["E"][k] - ref.energy) <= TOL * abs(ref.energy)
+
+
+def test_isolated_atom_and_empty_environment(model):
+    beta, sigma = model
+    box = np.array([30.0, 30.0, 30.0])
+    pos = np.array([[5.0, 5, 5], [6.0, 5, 5], [20.0, 20, 20], [15.0, 15.0, 9.55]])
+    species = np.array([1, 0, 1, 0], np.int32)   # atom 3 has a neighbour only beyond r_c
+    pos[3] = pos[2] + np.array([0.0, 0.0, -4.6])
+    print("case: isolated atoms", flush=True)
+    res = gpu_eval(pos, species, box, beta, sigma)
+    ref = oev.evaluate(pos, species, box, beta, sigma)
+    _compare(res, ref)
+    assert res["e"][2] == 0.0 and res["e"][3] == 0.0
+    assert np.all(res["f"][2:] == 0.0)
+
+
+def test_error_paths(model):
+    from paper_2204_12573_amd import binding as Bd, engine
+    beta, sigma = model
+    st = S.config_tiny()
+    m = engine.Model(beta, sigma)
+    ev = engine.Evaluator(m, max_atoms=st.n, max_pairs=100)
+    p, s = engine.to_device(st.pos, st.species)
+    with pytest.raises(Bd.FlareError) as e:
+        ev.descriptors(p)
+    assert e.value.code == Bd.E_STALE
+    with pytest.raises(Bd.FlareError) as e:
+        ev.neighbors(p, s, [0, st.n], st.box, 0.2)
+    assert e.value.code == Bd.E_CAPACITY
+    ev2 = engine.Evaluator(m, max_atoms=st.n, max_pairs=10 * st.n * 64)
+    bad = s.clone()
+    bad[3] = 7
+    with pytest.raises(Bd.FlareError) as e:
+        ev2.neighbors(p, bad, [0, st.n], st.box, 0.2)
+    assert e.value.code == Bd.E_SPECIES
+    pn = p.clone()
+    pn[1, 5] = float("nan")
+    with pytest.raises(Bd.FlareError) as e:
+        ev2.neighbors(pn, s, [0, st.n], st.box, 0.2)
+    assert e.value.code == Bd.E_NONFINITE
+    with pytest.raises(Bd.FlareError) as e:
+        ev2.neighbors(p, s, [0, st.n], np.array([st.box[0], -1.0, st.box[2]]), 0.2)
+    assert e.value.code == Bd.E_BOX
+    # a later good call still works, and a large move sets the displacement flag
+    ev2.neighbors(p, s, [0, st.n], st.box, 0.2)
+    ev2.descriptors(p)
+    assert ev2.status() == 0
+    p2 = p.clone()
+    p2[0, 0] += 0.15
+    ev2.descriptors(p2)
+    assert ev2.status() & Bd.FLAG_DISPLACED
