@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy, a kernel of known traffic for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
@@ -69,6 +71,14 @@ def main():
 
     from paper_2204_12573_amd import engine, structures as S
 
+    if args.copy_calibration:
+        a = torch.empty(64 * 2**20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB device-to-device copies")
     log("generating workload ...")
     st = S.config_large()
     beta, sigma = S.random_model(544)

@@ -4,13 +4,16 @@
 // With g_i = de_i/dd~_i from the quadratic-form pass and d~_{(a,b),l} = sum_m c_a c_b:
 //   u_{a,l,m} = de_i/dc_{a,l,m} = sum_b G^_{ab,l} c_{b,l,m},
 //               G^_{ab,l} = g_{(min,max),l}, doubled on the diagonal a = b.
-// For each listed pair (i, j) inside the cutoff, with Delta = r_j - r_i (+ image):
-//   w_ij = de_i/dDelta = sum_{n,l,m} u_{(s_j,n),l,m} grad_Delta [R_n(r) Y_lm(Delta/r)]
-//        = u^ sum_n (R_n' Z_n - R_n Zl_n / r) + (1/r) sum_lm A_lm grad P_lm(u^)
-//   with Z_n = sum_lm u_{n,lm} Y_lm, Zl_n = sum_lm l u_{n,lm} Y_lm, A_lm = sum_n u_{n,lm} R_n.
-//   F_i += w_ij and F_j -= w_ij (device atomics).
-// The densities c are recomputed from the pair list instead of being stored.
+// For each listed pair p = (i, j, s) inside the cutoff, with Delta = r_j + s L - r_i:
+//   w_p = de_i/dDelta = sum_{n,l,m} u_{(s_j,n),l,m} grad_Delta [R_n(r) Y_lm(Delta/r)]
+//       = u^ sum_n (R_n' Z_n - R_n Zl_n / r) + (1/r) sum_lm A_lm grad P_lm(u^)
+//   with Z_n = sum_lm u_{n,lm} Y_lm, Zl_n = sum_lm l u_{n,lm} Y_lm, A_lm = sum_n u_{n,lm} R_n,
+// and w_p = 0 outside the cutoff. The densities c are recomputed from the pair list.
+// Forces follow without atomics: F_i = sum_{p in list(i)} (w_p - w_rev(p)), rev(p) being
+// the pair (j, i, -s) (reduce.hip), so they are deterministic and independent of how
+// cells are batched.
 #include "basis.h"
+#include "half.h"
 #include "pair.h"
 #include "state.h"
 
@@ -19,6 +22,7 @@ namespace {
 
 constexpr int NT = 128;
 constexpr int NTX = 64;
+constexpr int TA = 256;   // threads of the 144-row adjoint kernel (128 rows, 2 lanes each)
 
 // sum_lm A_lm grad P_lm(x, y, z)
 __device__ __forceinline__ void poly_grad_dot(const float* A, float x, float y, float z,
@@ -38,7 +42,7 @@ __device__ __forceinline__ void poly_grad_dot(const float* A, float x, float y, 
 }
 
 // w = de_i/dDelta for one pair from the adjoint densities u[n][lm] of the neighbour's
-// species.
+// species (all 16 (l, m) in one thread).
 template <class U>
 __device__ __forceinline__ void pair_force(const PairGeom& pg, float rc, U u, float& wx, float& wy,
                                            float& wz) {
@@ -75,76 +79,113 @@ __device__ __forceinline__ int pair_index_same(int na, int nb) {
   return na * NR - na * (na - 1) / 2 + (nb - na);
 }
 
-__global__ __launch_bounds__(NT) void k_force_single(PairView v, int rows,
-                                                     const int* __restrict__ atom_of_row,
-                                                     const float* __restrict__ G,
-                                                     float* __restrict__ F) {
-  const int row = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-  if (row >= rows) return;
-  const int i = atom_of_row[row];
+// Two lanes per row (see half.h). Lane h holds u[n][q] for (l, m) = 8h + q; its q fall in
+// three groups of constant l: {0}, {1,2,3}, {4..7} with l = (0,1,2) for h = 0 and
+// (2,3,3) for h = 1. Each lane forms its partial w over its own (l, m); the xor-1
+// partner adds the rest.
+__global__ __launch_bounds__(TA) void k_adjoint144(PairView v, const int* __restrict__ atom_of_row,
+                                                   const float* __restrict__ G, float* __restrict__ w,
+                                                   long long P) {
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = threadIdx.x, rl = t >> 1, h = t & 1;
+  const int i = atom_of_row[tile * 128 + rl];
   if (i < 0) return;
-  float c[NR][NLM];
+  float c[NR][NQ];
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
-    for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
-  accumulate_densities(v, i, -1, c);
-  // u = G^ c, in place, one (l, m) column at a time
-  const float* g = G + (size_t)row * ND1;
+    for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
+  accumulate_half(v, i, h, c);
+  // u = G^ c, group by group
+  const float* g = G + (size_t)tile * ND1 * 128 + rl;
+  const int lg0 = h ? 2 : 0, lg1 = h ? 3 : 1, lg2 = h ? 3 : 2;
 #pragma unroll
-  for (int l = 0; l <= LMAX; ++l) {
+  for (int grp = 0; grp < 3; ++grp) {
+    const int l = grp == 0 ? lg0 : (grp == 1 ? lg1 : lg2);
+    const int q0 = grp == 0 ? 0 : (grp == 1 ? 1 : 4);
+    const int q1 = grp == 0 ? 1 : (grp == 1 ? 4 : 8);
     float gh[NR][NR];
 #pragma unroll
     for (int na = 0; na < NR; ++na)
 #pragma unroll
       for (int nb = na; nb < NR; ++nb) {
-        const float val = g[pair_index_same(na, nb) * 4 + l];
+        const float val = g[(size_t)(pair_index_same(na, nb) * 4 + l) * 128];
         gh[na][nb] = na == nb ? 2.f * val : val;
         gh[nb][na] = gh[na][nb];
       }
 #pragma unroll
-    for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) {
+    for (int q = q0; q < q1; ++q) {
       float col[NR];
 #pragma unroll
-      for (int n = 0; n < NR; ++n) col[n] = c[n][lm];
+      for (int n = 0; n < NR; ++n) col[n] = c[n][q];
 #pragma unroll
       for (int n = 0; n < NR; ++n) {
         float acc = 0.f;
 #pragma unroll
         for (int m = 0; m < NR; ++m) acc += gh[n][m] * col[m];
-        c[n][lm] = acc;
+        c[n][q] = acc;
       }
     }
   }
-  // pair loop
+  const float fl0 = (float)lg0, fl1 = (float)lg1, fl2 = (float)lg2;
   const size_t nn = (size_t)v.n;
   const double xi = v.pos[i], yi = v.pos[nn + i], zi = v.pos[2 * nn + i];
   const CellGrid* cg = v.grids + v.sid[i];
   const double L[3] = {cg->L[0], cg->L[1], cg->L[2]};
-  float fx = 0.f, fy = 0.f, fz = 0.f;
   const int p0 = v.nl_off[i], p1 = v.nl_off[i + 1];
   for (int p = p0; p < p1; ++p) {
-    const int j = v.nl_j[p];
     PairGeom pg;
-    if (!pair_geom(v, j, xi, yi, zi, L, v.nl_s[p], pg)) continue;
-    float wx, wy, wz;
-    pair_force(pg, v.rc, [&](int n, int lm) { return c[n][lm]; }, wx, wy, wz);
-    fx += wx;
-    fy += wy;
-    fz += wz;
-    unsafeAtomicAdd(&F[j], -wx);
-    unsafeAtomicAdd(&F[nn + j], -wy);
-    unsafeAtomicAdd(&F[2 * nn + j], -wz);
+    float wx = 0.f, wy = 0.f, wz = 0.f;
+    if (pair_geom(v, v.nl_j[p], xi, yi, zi, L, v.nl_s[p], pg)) {
+      float R[NR], dR[NR], Y[NLM];
+      radial_d(pg.r, v.rc, R, dR);
+      sph_harm(pg.ux, pg.uy, pg.uz, Y);
+      float ys[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) ys[q] = h ? Y[NQ + q] : Y[q];
+      const float inv_r = 1.f / pg.r;
+      float s1 = 0.f;
+      float Aq[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) Aq[q] = 0.f;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) {
+        const float z0 = c[n][0] * ys[0];
+        const float z1 = c[n][1] * ys[1] + c[n][2] * ys[2] + c[n][3] * ys[3];
+        const float z2 = c[n][4] * ys[4] + c[n][5] * ys[5] + c[n][6] * ys[6] + c[n][7] * ys[7];
+        const float z = z0 + z1 + z2;
+        const float zl = fl0 * z0 + fl1 * z1 + fl2 * z2;
+        s1 += dR[n] * z - R[n] * zl * inv_r;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Aq[q] += c[n][q] * R[n];
+      }
+      float A[NLM];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        A[q] = h ? 0.f : Aq[q];
+        A[NQ + q] = h ? Aq[q] : 0.f;
+      }
+      float gx, gy, gz;
+      poly_grad_dot(A, pg.ux, pg.uy, pg.uz, gx, gy, gz);
+      wx = pg.ux * s1 + gx * inv_r;
+      wy = pg.uy * s1 + gy * inv_r;
+      wz = pg.uz * s1 + gz * inv_r;
+    }
+    wx += __shfl_xor(wx, 1, 64);
+    wy += __shfl_xor(wy, 1, 64);
+    wz += __shfl_xor(wz, 1, 64);
+    if (h == 0) {
+      w[p] = wx;
+      w[P + p] = wy;
+      w[2 * P + p] = wz;
+    }
   }
-  unsafeAtomicAdd(&F[i], fx);
-  unsafeAtomicAdd(&F[nn + i], fy);
-  unsafeAtomicAdd(&F[2 * nn + i], fz);
 }
 
-__global__ __launch_bounds__(NTX) void k_force_mixed(PairView v, int rows,
-                                                     const int* __restrict__ atom_of_row,
-                                                     const float* __restrict__ G,
-                                                     float* __restrict__ F) {
+__global__ __launch_bounds__(NTX) void k_adjoint_mixed(PairView v, int rows,
+                                                       const int* __restrict__ atom_of_row,
+                                                       const float* __restrict__ G,
+                                                       float* __restrict__ w, long long P) {
   // densities, then adjoints, of both species halves; one column per thread
   __shared__ float uh[NR * NLM][NTX];
   __shared__ float up[NR * NLM][NTX];
@@ -201,40 +242,37 @@ __global__ __launch_bounds__(NTX) void k_force_mixed(PairView v, int rows,
   const double xi = v.pos[i], yi = v.pos[nn + i], zi = v.pos[2 * nn + i];
   const CellGrid* cg = v.grids + v.sid[i];
   const double L[3] = {cg->L[0], cg->L[1], cg->L[2]};
-  float fx = 0.f, fy = 0.f, fz = 0.f;
   const int p0 = v.nl_off[i], p1 = v.nl_off[i + 1];
   for (int p = p0; p < p1; ++p) {
     const int j = v.nl_j[p];
     PairGeom pg;
-    if (!pair_geom(v, j, xi, yi, zi, L, v.nl_s[p], pg)) continue;
-    float (*u)[NTX] = v.sp[j] == 0 ? uh : up;
-    float wx, wy, wz;
-    pair_force(pg, v.rc, [&](int n, int lm) { return u[n * NLM + lm][t]; }, wx, wy, wz);
-    fx += wx;
-    fy += wy;
-    fz += wz;
-    unsafeAtomicAdd(&F[j], -wx);
-    unsafeAtomicAdd(&F[nn + j], -wy);
-    unsafeAtomicAdd(&F[2 * nn + j], -wz);
+    float wx = 0.f, wy = 0.f, wz = 0.f;
+    if (pair_geom(v, j, xi, yi, zi, L, v.nl_s[p], pg)) {
+      float (*u)[NTX] = v.sp[j] == 0 ? uh : up;
+      pair_force(pg, v.rc, [&](int n, int lm) { return u[n * NLM + lm][t]; }, wx, wy, wz);
+    }
+    w[p] = wx;
+    w[P + p] = wy;
+    w[2 * P + p] = wz;
   }
-  unsafeAtomicAdd(&F[i], fx);
-  unsafeAtomicAdd(&F[nn + i], fy);
-  unsafeAtomicAdd(&F[2 * nn + i], fz);
 }
 
 }  // namespace
 
 void compute_forces(flare_state* s) {
   const PairView v = pair_view(s);
-  StageTimer tm(s, FLARE_T_FORCE1);
-  (void)hipMemsetAsync(s->f_int, 0, 3 * (size_t)s->n_atoms * sizeof(float), s->stream);
-  if (s->rows1 > 0)
-    k_force_single<<<(s->rows1 + NT - 1) / NT, NT, 0, s->stream>>>(v, s->rows1, s->atom_of_row1.p, s->G1.p,
-                                                                   s->f_int);
-  StageTimer tm2(s, FLARE_T_FORCEX);
-  if (s->rowsx > 0)
-    k_force_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rowsx, s->atom_of_rowx.p,
-                                                                     s->Gx.p, s->f_int);
+  const long long P = s->max_pairs;
+  {
+    StageTimer tm(s, FLARE_T_FORCE1);
+    if (s->rows1 > 0)
+      k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->w_pair, P);
+  }
+  {
+    StageTimer tm(s, FLARE_T_FORCEX);
+    if (s->rowsx > 0)
+      k_adjoint_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rowsx, s->atom_of_rowx.p,
+                                                                          s->Gx.p, s->w_pair, P);
+  }
 }
 
 }  // namespace flare

@@ -131,6 +131,23 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
               (float)parts[part][(size_t)(start[b] + k) * ND + (start[b] + n)];
     hipError_t e = hipMalloc((void**)&m->W[b], w.size() * sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(m->W[b], w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (b < 4 && e == hipSuccess) {
+      // fragment order for v_mfma_f32_16x16x4_f32 B operands: element
+      // [part][kc][cb][lane][t] = M[kc*16 + 4*(lane/16) + t][cb*16 + lane%16]
+      const int nkc = ND1 / 16, ncb = ND1 / 16;
+      std::vector<float> f((size_t)2 * nkc * ncb * 64 * 4);
+      for (int part = 0; part < 2; ++part)
+        for (int kc = 0; kc < nkc; ++kc)
+          for (int cb = 0; cb < ncb; ++cb)
+            for (int lane = 0; lane < 64; ++lane)
+              for (int t = 0; t < 4; ++t) {
+                const int k = kc * 16 + 4 * (lane / 16) + t, col = cb * 16 + lane % 16;
+                f[((((size_t)part * nkc + kc) * ncb + cb) * 64 + lane) * 4 + t] =
+                    (float)parts[part][(size_t)(start[b] + k) * ND + (start[b] + col)];
+              }
+      e = hipMalloc((void**)&m->Wf[b], f.size() * sizeof(float));
+      if (e == hipSuccess) e = hipMemcpy(m->Wf[b], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
       set_error(std::string("model upload: ") + hipGetErrorString(e));
       flare_model_destroy(m);
@@ -145,6 +162,8 @@ int flare_model_destroy(flare_model* m) {
   if (!m) return FLARE_OK;
   for (int b = 0; b < NBUCKET; ++b)
     if (m->W[b]) (void)hipFree(m->W[b]);
+  for (int b = 0; b < 4; ++b)
+    if (m->Wf[b]) (void)hipFree(m->Wf[b]);
   delete m;
   return FLARE_OK;
 }
@@ -157,8 +176,8 @@ int flare_descriptor_dim(const flare_model* m, int* n_d) {
 
 static void free_state(flare_state* s) {
   void* ptrs[] = {s->perm, s->sp,  s->sid, s->bin,   s->envmask, s->bucket, s->row_of, s->nl_cnt,
-                  s->nl_off, s->w, s->off, s->pos,   s->nrm,     s->e_int,  s->v_int,  s->f_int,
-                  s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->d_status,
+                  s->nl_off, s->w, s->off, s->pos,   s->nrm,     s->e_int,  s->v_int,
+                  s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->nl_rev, s->w_pair, s->d_status,
                   s->d_info};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -217,7 +236,6 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   al((void**)&s->nrm, n * 4);
   al((void**)&s->e_int, n * 4);
   al((void**)&s->v_int, n * 4);
-  al((void**)&s->f_int, 3 * n * 4);
   al((void**)&s->o_bin, n * 4);
   al((void**)&s->o_sid, n * 4);
   al((void**)&s->o_w, 3 * n * 8);
@@ -225,6 +243,8 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   al((void**)&s->sorted, n * 4);
   al((void**)&s->nl_j, (size_t)max_pairs * 4);
   al((void**)&s->nl_s, (size_t)max_pairs * 4);
+  al((void**)&s->nl_rev, (size_t)max_pairs * 4);
+  al((void**)&s->w_pair, 3 * (size_t)max_pairs * 4);
   al((void**)&s->d_status, 64);
   al((void**)&s->d_info, 64);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_info, 64, hipHostMallocDefault);
@@ -388,11 +408,19 @@ int flare_descriptors(flare_state* s, const double* x, const double* y, const do
     return FLARE_E_STALE;
   }
   ARG(s->n_atoms == 0 || (x && y && z), "null positions");
-  gather_positions(s, x, y, z);
-  compute_descriptors(s);
-  export_descriptors(s, d_out, norm_out);
+  {
+    StageTimer tm(s, FLARE_T_DESC1);
+    gather_positions(s, x, y, z);
+  }
+  if (d_out || norm_out) {
+    // the single-species rows come from the fused kernel run without quadratic forms
+    fused_quadratic_forms(s, 0, s->D1.p);
+    compute_descriptors_mixed(s);
+    export_descriptors(s, d_out, norm_out);
+  }
   CHK(hipGetLastError());
   s->have_desc = true;
+  s->pos_gen += 1;
   return FLARE_OK;
 }
 
@@ -405,13 +433,22 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
   }
   ARG(s->n_atoms == 0 || (fx && fy && fz), "force outputs are required");
   const bool want_v = var_atom || sigma_atom;
-  quadratic_forms(s, true, want_v);
+  {
+    StageTimer tm(s, FLARE_T_QFORM1);
+    fused_quadratic_forms(s, 1 | (want_v ? 2 : 0), nullptr);
+  }
+  compute_descriptors_mixed(s);
+  {
+    StageTimer tm(s, FLARE_T_QFORMX);
+    mixed_quadratic_forms(s, true, want_v);
+  }
   compute_forces(s);
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, e_atom, fx, fy, fz, var_atom, sigma_atom);
     reduce_cells(s, e_struct, nullptr);
   }
+  if (want_v) s->v_gen = s->pos_gen;
   CHK(hipGetLastError());
   return FLARE_OK;
 }
@@ -422,7 +459,18 @@ int flare_variance(flare_state* s, float* var_atom, float* sigma_atom, float* si
     set_error("flare_variance before flare_descriptors");
     return FLARE_E_STALE;
   }
-  quadratic_forms(s, false, true);
+  if (s->v_gen != s->pos_gen) {
+    {
+      StageTimer tm(s, FLARE_T_QFORM1);
+      fused_quadratic_forms(s, 2, nullptr);
+    }
+    compute_descriptors_mixed(s);
+    {
+      StageTimer tm(s, FLARE_T_QFORMX);
+      mixed_quadratic_forms(s, false, true);
+    }
+    s->v_gen = s->pos_gen;
+  }
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, nullptr, nullptr, nullptr, nullptr, var_atom, sigma_atom);

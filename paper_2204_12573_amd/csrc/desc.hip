@@ -4,10 +4,10 @@
 //   d~_{(a,b),l}  = sum_m c_{a,l,m} c_{b,l,m}    (a <= b, packed)
 //   d             = d~ / |d~|
 //
-// One thread per descriptor row; rows are grouped by environment bucket, so a wave
-// sees atoms of one kind (similar pair counts). A single-species atom keeps its 8x16
-// densities in registers and writes only its 144-component block. A mixed atom keeps
-// the H half in LDS (one column per thread) and the Pt half in registers.
+// This file holds the mixed-environment rows (544 components): one thread per row, the
+// H-channel densities in LDS (one column per thread) and the Pt half in registers.
+// Single-species rows are formed inside the fused quadratic-form kernel (fused.hip).
+// b2_same below is the single-species block of a row, used for the (Pt, Pt) block.
 // Pair geometry: positions are FP64; Delta = (x_j - x_i) + s*L is formed in FP64 and
 // rounded to FP32 before the basis is evaluated.
 #include "basis.h"
@@ -52,33 +52,6 @@ __device__ __forceinline__ float4 b2_pair(const float* a, const float* b) {
 #pragma unroll
   for (int lm = 9; lm < 16; ++lm) d3 += a[lm] * b[lm];
   return make_float4(d0, d1, d2, d3);
-}
-
-__global__ __launch_bounds__(NT) void k_desc_single(PairView v, int rows,
-                                                    const int* __restrict__ atom_of_row,
-                                                    float* __restrict__ D,
-                                                    float* __restrict__ nrm_out) {
-  const int row = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-  if (row >= rows) return;
-  float4* out = reinterpret_cast<float4*>(D + (size_t)row * ND1);
-  const int i = atom_of_row[row];
-  if (i < 0) {
-    for (int k = 0; k < NP1; ++k) out[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
-  }
-  float c[NR][NLM];
-#pragma unroll
-  for (int n = 0; n < NR; ++n)
-#pragma unroll
-    for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
-  accumulate_densities(v, i, -1, c);
-  float nrm2 = 0.f;
-  b2_same(c, nullptr, 1.f, nrm2);
-  const float nrm = sqrtf(nrm2);
-  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
-  float dummy = 0.f;
-  b2_same(c, out, inv, dummy);
-  nrm_out[i] = nrm;
 }
 
 __global__ __launch_bounds__(NTX) void k_desc_mixed(PairView v, int rows,
@@ -212,13 +185,9 @@ void gather_positions(flare_state* s, const double* x, const double* y, const do
                                                            lim * lim, s->d_status);
 }
 
-void compute_descriptors(flare_state* s) {
+void compute_descriptors_mixed(flare_state* s) {
   const PairView v = pair_view(s);
-  StageTimer tm(s, FLARE_T_DESC1);
-  if (s->rows1 > 0)
-    k_desc_single<<<(s->rows1 + NT - 1) / NT, NT, 0, s->stream>>>(v, s->rows1, s->atom_of_row1.p, s->D1.p,
-                                                                  s->nrm);
-  StageTimer tm2(s, FLARE_T_DESCX);
+  StageTimer tm(s, FLARE_T_DESCX);
   if (s->rowsx > 0)
     k_desc_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rowsx, s->atom_of_rowx.p,
                                                                     s->Dx.p, s->nrm);

@@ -1,0 +1,52 @@
+// Two lanes per descriptor row: lane h = 0 owns (l, m) indices 0..7 (l = 0, 1 and the
+// first four m of l = 2), lane h = 1 owns 8..15 (the last m of l = 2 and l = 3). Both
+// lanes of a row sit next to each other in one wave, so per-row sums combine with one
+// xor-1 exchange and no barrier. Used by the fused descriptor/quadratic-form kernel
+// and by the adjoint kernel.
+#pragma once
+
+#include "pair.h"
+
+namespace flare {
+
+constexpr int NQ = 8;   // (l, m) indices per lane
+
+// c[n][q] += R_n Y_{8h+q} over the neighbours of atom i inside the cutoff.
+__device__ __forceinline__ void accumulate_half(const PairView& v, int i, int h, float (*c)[NQ]) {
+  const size_t n = (size_t)v.n;
+  const double xi = v.pos[i], yi = v.pos[n + i], zi = v.pos[2 * n + i];
+  const CellGrid* g = v.grids + v.sid[i];
+  const double L[3] = {g->L[0], g->L[1], g->L[2]};
+  const int p0 = v.nl_off[i], p1 = v.nl_off[i + 1];
+  for (int p = p0; p < p1; ++p) {
+    PairGeom pg;
+    if (!pair_geom(v, v.nl_j[p], xi, yi, zi, L, v.nl_s[p], pg)) continue;
+    float R[NR], Y[NLM];
+    radial(pg.r, v.rc, R);
+    sph_harm(pg.ux, pg.uy, pg.uz, Y);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const float y = h ? Y[NQ + q] : Y[q];
+#pragma unroll
+      for (int nn = 0; nn < NR; ++nn) c[nn][q] += R[nn] * y;
+    }
+  }
+}
+
+// One B2 radial pair (a, b) of a single-species block: the four l-components, identical
+// in both lanes of the row. prod_q = c_a,q c_b,q; lane h = 0 holds l = 0 (q0), l = 1
+// (q1..3) and part of l = 2 (q4..7); lane h = 1 the rest of l = 2 (q0) and l = 3 (q1..7).
+__device__ __forceinline__ float4 b2_half(const float* ca, const float* cb, int h) {
+  const float v0 = ca[0] * cb[0];
+  const float v1 = ca[1] * cb[1] + ca[2] * cb[2] + ca[3] * cb[3];
+  const float v2 = ca[4] * cb[4] + ca[5] * cb[5] + ca[6] * cb[6] + ca[7] * cb[7];
+  const float p0 = __shfl_xor(v0, 1, 64);
+  const float p1 = __shfl_xor(v1, 1, 64);
+  const float p2 = __shfl_xor(v2, 1, 64);
+  // (u*) = values of lane h = 0, (w*) = values of lane h = 1
+  const float u0 = h ? p0 : v0, u1 = h ? p1 : v1, u2 = h ? p2 : v2;
+  const float w0 = h ? v0 : p0, w1 = h ? v1 : p1, w2 = h ? v2 : p2;
+  return make_float4(u0, u1, u2 + w0, w1 + w2);
+}
+
+}  // namespace flare

@@ -206,6 +206,32 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
   if (!FILL) block_bucket_counts(b_out, blk, nblk);
 }
 
+// For every pair p = (i, j, s) find q = (j, i, -s) in j's list. The list is symmetric
+// because the FP64 distance test gives the same value for both orders (negating a
+// rounded difference is exact). A missing partner sets the species flag bit 8.
+__global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ nl_off,
+                                                const int* __restrict__ nl_j,
+                                                const int32_t* __restrict__ nl_s,
+                                                int* __restrict__ rev, int* __restrict__ status) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  for (int p = nl_off[i]; p < nl_off[i + 1]; ++p) {
+    const int j = nl_j[p];
+    int sx, sy, sz;
+    unpack_shift(nl_s[p], sx, sy, sz);
+    const int32_t want = pack_shift(-sx, -sy, -sz);
+    int found = -1;
+    for (int q = nl_off[j]; q < nl_off[j + 1]; ++q) {
+      if (nl_j[q] == i && nl_s[q] == want) {
+        found = q;
+        break;
+      }
+    }
+    if (found < 0) atomicOr(status, 256);
+    rev[p] = found < 0 ? p : found;
+  }
+}
+
 struct Row0 {
   int r[NBUCKET];
 };
@@ -351,6 +377,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     k_pairs<true><<<nblk, NT, 0, st>>>(n, s->d_grids.p, s->sid, s->bin, s->w, s->sp, s->bin_start.p,
                                         rl2, nullptr, nullptr, nullptr, nullptr, nblk, s->nl_off,
                                         s->nl_j, s->nl_s);
+    k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev, s->d_status);
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
   }

@@ -233,62 +233,37 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
   for (int k = lane; k < ND; k += 64) g[k] = s2 * (y[k] - e * d[k]);
 }
 
-void launch_class(flare_state* s, bool single, int mode) {
+}  // namespace
+
+// Quadratic forms of the mixed-environment rows (544-wide), split over four column tiles.
+void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
+  const int mode = (want_e ? 1 : 0) | (want_v ? 2 : 0);
+  const int rows = s->rowsx;
+  if (!mode || rows == 0) return;
   const flare_model* m = s->model;
   QArgs q{};
   q.mode = mode;
   q.nrm = s->nrm;
   q.e_int = s->e_int;
   q.v_int = s->v_int;
-  const int first = single ? 0 : 4, nb = single ? 4 : 2;
-  const int kd = single ? ND1 : ND;
-  q.nbk = nb;
-  for (int k = 0; k < nb; ++k) {
-    const int bk = first + k;
+  q.nbk = 2;
+  for (int k = 0; k < 2; ++k) {
+    const int bk = 4 + k;
     const int padded = (s->bucket_count[bk] + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
     q.row0[k] = s->bucket_row0[bk];
     q.row1[k] = s->bucket_row0[bk] + padded;
-    q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)kd * kd);
+    q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)ND * ND);
   }
-  const int rows = single ? s->rows1 : s->rowsx;
-  if (rows == 0) return;
-  const int tiles = rows / TM;
+  q.D = s->Dx.p;
+  q.G = s->Gx.p;
+  q.aor = s->atom_of_rowx.p;
+  q.Y = s->Yx.p;
+  q.P = s->Px.p;
   const int parts = ((mode & 1) ? 1 : 0) + ((mode & 2) ? 1 : 0);
-  if (single) {
-    q.D = s->D1.p;
-    q.G = s->G1.p;
-    q.aor = s->atom_of_row1.p;
-    if (parts == 2)
-      k_qform<ND1, 18, true><<<dim3(tiles, 1), NTQ, 0, s->stream>>>(q);
-    else
-      k_qform<ND1, 9, true><<<dim3(tiles, 1), NTQ, 0, s->stream>>>(q);
-  } else {
-    q.D = s->Dx.p;
-    q.G = s->Gx.p;
-    q.aor = s->atom_of_rowx.p;
-    q.Y = s->Yx.p;
-    q.P = s->Px.p;
-    const int ntiles = 2 * parts;   // 272 columns per tile
-    k_qform<ND, 17, false><<<dim3(tiles, ntiles), NTQ, 0, s->stream>>>(q);
-    k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
-                                                          s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int,
-                                                          s->v_int);
-  }
-}
-
-}  // namespace
-
-void quadratic_forms(flare_state* s, bool want_e, bool want_v) {
-  const int mode = (want_e ? 1 : 0) | (want_v ? 2 : 0);
-  if (!mode) return;
-  {
-    StageTimer tm(s, FLARE_T_QFORM1);
-    launch_class(s, true, mode);
-  }
-  {
-    StageTimer tm(s, FLARE_T_QFORMX);
-    launch_class(s, false, mode);
-  }
+  const int ntiles = 2 * parts;   // 272 columns per tile
+  k_qform<ND, 17, false><<<dim3(rows / TM, ntiles), NTQ, 0, s->stream>>>(q);
+  k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
+                                                        s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int);
 }
 
 }  // namespace flare

@@ -10,24 +10,35 @@ namespace {
 
 constexpr int NT = 256;
 
-__global__ __launch_bounds__(NT) void k_finalize(int n, const int* __restrict__ perm,
-                                                 const int* __restrict__ bucket,
-                                                 const float* __restrict__ e_int,
-                                                 const float* __restrict__ v_int,
-                                                 const float* __restrict__ f_int,
-                                                 float* __restrict__ e_atom, float* __restrict__ fx,
-                                                 float* __restrict__ fy, float* __restrict__ fz,
-                                                 float* __restrict__ var_atom,
-                                                 float* __restrict__ sigma_atom) {
+// Caller-order outputs. Forces by gathering the per-pair adjoint terms:
+// F_i = sum_{p in list(i)} (w_p - w_rev(p)), in list order (deterministic).
+__global__ __launch_bounds__(NT) void k_outputs(int n, const int* __restrict__ perm,
+                                                const int* __restrict__ bucket,
+                                                const int* __restrict__ nl_off,
+                                                const int* __restrict__ rev,
+                                                const float* __restrict__ w, long long P,
+                                                const float* __restrict__ e_int,
+                                                const float* __restrict__ v_int,
+                                                float* __restrict__ e_atom, float* __restrict__ fx,
+                                                float* __restrict__ fy, float* __restrict__ fz,
+                                                float* __restrict__ var_atom,
+                                                float* __restrict__ sigma_atom) {
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   const int a = perm[i];
   const bool has = bucket[i] >= 0;
   if (e_atom) e_atom[a] = has ? e_int[i] : 0.f;
   if (fx) {
-    fx[a] = f_int[i];
-    fy[a] = f_int[(size_t)n + i];
-    fz[a] = f_int[2 * (size_t)n + i];
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int p = nl_off[i]; p < nl_off[i + 1]; ++p) {
+      const int q = rev[p];
+      sx += w[p] - w[q];
+      sy += w[P + p] - w[P + q];
+      sz += w[2 * P + p] - w[2 * P + q];
+    }
+    fx[a] = sx;
+    fy[a] = sy;
+    fz[a] = sz;
   }
   const float v = has ? v_int[i] : 0.f;
   if (var_atom) var_atom[a] = v;
@@ -145,8 +156,9 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
                       float* var_atom, float* sigma_atom) {
   const int n = s->n_atoms;
   if (n == 0) return;
-  k_finalize<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->bucket, s->e_int, s->v_int, s->f_int,
-                                                      e_atom, fx, fy, fz, var_atom, sigma_atom);
+  k_outputs<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->bucket, s->nl_off, s->nl_rev, s->w_pair,
+                                                     s->max_pairs, s->e_int, s->v_int, e_atom, fx, fy, fz,
+                                                     var_atom, sigma_atom);
 }
 
 void reduce_cells(flare_state* s, double* e_struct, float* sigma_max) {

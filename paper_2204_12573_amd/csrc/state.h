@@ -68,6 +68,9 @@ struct flare_model {
   // nb..2nb-1 the Sigma sub-block of the central species, restricted to the bucket's
   // descriptor block (nb = 144 for single-species buckets, 544 for mixed).
   float* W[flare::NBUCKET] = {};
+  // Single-species buckets: the same matrices in MFMA fragment order,
+  // [part 2][K chunk 9][column block 9][lane 64] float4 (see fused.hip).
+  float* Wf[4] = {};
 };
 
 struct flare_state {
@@ -80,6 +83,8 @@ struct flare_state {
   // ---- current list ----
   bool have_list = false;
   bool have_desc = false;
+  long long pos_gen = 0;     // positions staged by flare_descriptors
+  long long v_gen = -1;      // positions the variances were computed for
   int n_atoms = 0;
   int n_struct = 0;
   int n_bins = 0;
@@ -111,7 +116,6 @@ struct flare_state {
   float* nrm = nullptr;      // |d~| per internal atom
   float* e_int = nullptr;
   float* v_int = nullptr;
-  float* f_int = nullptr;    // [3][N]
   // caller-order temporaries of the list build
   int* o_bin = nullptr;
   int* o_sid = nullptr;
@@ -122,6 +126,8 @@ struct flare_state {
   // ---- per-pair ----
   int* nl_j = nullptr;       // internal index of the neighbour
   int32_t* nl_s = nullptr;   // packed image shift
+  int* nl_rev = nullptr;     // index of the reverse pair (j, i, -s) in j's list
+  float* w_pair = nullptr;   // [3][max_pairs] de_i/dDelta_ij of each listed pair
 
   // ---- grow-at-build buffers ----
   flare::DevBuf<flare::CellGrid> d_grids;
@@ -159,9 +165,10 @@ struct StageTimer {
 int build_list(flare_state* s, const double* x, const double* y, const double* z,
                const int32_t* species);
 void gather_positions(flare_state* s, const double* x, const double* y, const double* z);
-void compute_descriptors(flare_state* s);
+void compute_descriptors_mixed(flare_state* s);
 void export_descriptors(flare_state* s, float* d_out, float* norm_out);
-void quadratic_forms(flare_state* s, bool want_e, bool want_v);
+void fused_quadratic_forms(flare_state* s, int mode, float* d_out);
+void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v);
 void compute_forces(flare_state* s);
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
                       float* var_atom, float* sigma_atom);
