@@ -52,12 +52,102 @@ def cpu_baseline(st, beta, sigma, half_width=6.0):
                       f"the same cell, one E+F+sigma evaluation in {dt:.1f} s; numpy FP64, BLAS threads={blas}"}
 
 
+def md_throughput(engine, torch, st, beta, sigma, steps, warmup, precision):
+    n = st.n
+    model = engine.Model(beta, sigma, precision=precision)
+    ev = engine.Evaluator(model, max_atoms=n, max_pairs=12 * n)
+    p, s = engine.to_device(st.pos, st.species)
+    v = torch.zeros_like(p)
+    md = engine.MD(ev, p, v, s, [0, n], st.box, dt=0.5, skin=0.2, rebuild=10, want_var=True)
+    for _ in range(warmup):
+        md.step()
+    torch.cuda.synchronize()
+    ev.timers(True)
+    ev.read_timers(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        md.step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = ev.read_timers(reset=True)
+    ev.timers(False)
+    return ev, model, el, tm
+
+
+def sample_errors(engine, torch, st, beta, sigma, precision, tg, ref):
+    """E, F, sigma of one evaluation at the initial positions vs the FP64 oracle sample."""
+    import numpy as np
+    model = engine.Model(beta, sigma, precision=precision)
+    ev = engine.Evaluator(model, max_atoms=st.n, max_pairs=12 * st.n)
+    p, s = engine.to_device(st.pos, st.species)
+    ev.neighbors(p, s, [0, st.n], st.box, 0.2)
+    out = ev.compute(p, want_var=True)
+    torch.cuda.synchronize()
+    rows = ref.row_of(tg)
+    e = out["e"].cpu().numpy()[tg]
+    f = out["f"].cpu().numpy().T[tg]
+    sg = out["sigma"].cpu().numpy()[tg]
+    return {"e": float(np.abs(e - ref.e[rows]).max() / np.abs(ref.e[rows]).max()),
+            "f": float(np.linalg.norm(f - ref.f, axis=1).max() / np.linalg.norm(ref.f, axis=1).max()),
+            "sigma": float(np.abs(sg - ref.sigma[rows]).max() / np.abs(ref.sigma[rows]).max())}
+
+
+def serving(engine, torch, beta, sigma, n_req, rate):
+    from paper_2204_12573_amd import binding, serve
+    out = {}
+    reqs_proto = serve.poisson_requests(n_req, rate=rate, seed=7)
+    for name, prec, lanes, mb in [("batched_split", binding.BF16_SPLIT, 2, 10**9),
+                                  ("one_at_a_time_fp32", binding.FP32, 1, 1)]:
+        reqs = [serve.Request(r.rid, r.arrival, r.pos, r.species, r.box) for r in reqs_proto]
+        model = engine.Model(beta, sigma, precision=prec)
+        ex = serve.GpuExecutor(model, n_lanes=lanes, lane_atoms=400_000)
+        # warm up the lanes on the first few structures
+        serve.Scheduler(ex, max_batch=mb).run([serve.Request(-1 - k, 0.0, r.pos, r.species, r.box)
+                                               for k, r in enumerate(reqs[:4])])
+        torch.cuda.synchronize()
+        _, stats = serve.Scheduler(ex, max_batch=mb).run(reqs)
+        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+        del ex, model
+    out["offered"] = {"rate_req_s": rate, "requests": n_req,
+                      "mean_atoms": float(sum(r.n for r in reqs_proto) / n_req)}
+    return out
+
+
+def autograd_cells(engine, torch, beta, sigma):
+    import numpy as np
+
+    from paper_2204_12573_amd import autograd as AG, structures as S
+    b = S.config_cells(n_cells=256, seed=0)
+    model = engine.Model(beta, sigma)
+    mod = AG.FlareEnergy(model, b.species, b.offsets, b.boxes)
+    pos = torch.from_numpy(np.ascontiguousarray(b.pos.T)).cuda().requires_grad_(True)
+    for _ in range(2):
+        E = mod(pos)
+        (g,) = torch.autograd.grad(E.sum(), pos)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        E = mod(pos)
+        (g,) = torch.autograd.grad(E.sum(), pos)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    npairs, counts = mod.ev.list_info()
+    held = mod.ev.memory_bytes(with_model=False)
+    stored = AG.stored_gradient_bytes(npairs, counts[:4].sum(), counts[4:].sum(), npairs, 0)
+    return {"cells": 256, "atoms": int(b.n), "pairs": int(npairs), "ms_forward_backward": round(dt * 1e3, 3),
+            "M_atom_grad_per_s": round(b.n / dt / 1e6, 3), "state_bytes": int(held),
+            "stored_dd_dr_bytes": int(stored["dd_dr_full"]), "stored_dc_dr_bytes": int(stored["dc_dr"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the split-precision, serving and autograd legs")
+    ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy, a kernel of known traffic for counter scaling")
     args = ap.parse_args()
@@ -83,33 +173,16 @@ def main():
     st = S.config_large()
     beta, sigma = S.random_model(544)
     n = st.n
-    model = engine.Model(beta, sigma)
-    ev = engine.Evaluator(model, max_atoms=n, max_pairs=12 * n)
-    p, s = engine.to_device(st.pos, st.species)
-    v = torch.zeros_like(p)
-    md = engine.MD(ev, p, v, s, [0, n], st.box, dt=0.5, skin=0.2, rebuild=10, want_var=True)
+    ev, model, el, tm = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup, 0)
     npairs, counts = ev.list_info()
-    log(f"atoms {n}, pairs {npairs}, buckets {counts.tolist()}")
-    for _ in range(args.warmup):
-        md.step()
-    torch.cuda.synchronize()
-    ev.timers(True)
-    ev.read_timers(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        md.step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tm = ev.read_timers(reset=True)
-    ev.timers(False)
     status = ev.status()
-    el = t1 - t0
+    log(f"atoms {n}, pairs {npairs}, buckets {counts.tolist()}")
     value = n * args.steps / el / 1e6
     log(f"{args.steps} steps in {el*1e3:.1f} ms -> {value:.2f} M atom-steps/s, status {status}")
     for k, (ms, c) in tm.items():
         if c:
             log(f"  {k:9s} {ms/c*1e3:9.1f} us/launch x {c}")
+    del ev, model
 
     # dominant kernel: quadratic forms on the 144-wide rows (beta and Sigma, E+V)
     n144 = int(counts[:4].sum())
@@ -141,6 +214,31 @@ def main():
         "stage_us_per_launch": stage_us,
         "status_flags": status,
     }
+    if not args.no_forms:
+        from paper_2204_12573_amd import binding
+        from oracle import evaluate as oev
+        log("split-precision MD ...")
+        ev2, m2, el2, tm2 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
+                                          binding.BF16_SPLIT)
+        del ev2, m2
+        log("errors vs the FP64 oracle on a 300-atom sample ...")
+        rng = np.random.default_rng(12)
+        ztop = 23 * S.DZ
+        surf = np.nonzero(np.abs(st.pos[:, 2] - ztop) < 4.0)[0]
+        tg = np.unique(np.concatenate([rng.choice(n, 200, replace=False), rng.choice(surf, 100, replace=False)]))
+        ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma, targets=tg)
+        out["plain_fp32"] = {"value": round(value, 3),
+                             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, 0, tg, ref)}
+        out["mixed_bf16_split"] = {
+            "value": round(n * args.steps / el2 / 1e6, 3), "ms_per_step": round(el2 / args.steps * 1e3, 4),
+            "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.BF16_SPLIT, tg, ref),
+            "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm2.items() if c},
+            "note": "energy pass BF16 x3 (d and beta split hi/lo), variance |L^T d|^2 on FP32 cores "
+                    "with an FP64 Cholesky factor, FP64 sums; mixed-environment rows FP32"}
+        log("serving ...")
+        out["serving"] = serving(engine, torch, beta, sigma, args.serve_requests, 2000.0)
+        log("autograd (256 cells) ...")
+        out["autograd"] = autograd_cells(engine, torch, beta, sigma)
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")
         out["cpu_baseline"] = cpu_baseline(st, beta, sigma)

@@ -142,17 +142,28 @@ int flare_descriptors(flare_state* state, const double* x, const double* y, cons
                       float* d_out, float* norm_out);
 
 /*
- * Energies and forces from the resident descriptors (needs flare_descriptors first).
+ * Energies and forces for the positions staged by the last flare_descriptors call.
  *   e_atom         DEVICE FP32 [n_atoms] e_i                         (NULL = not written)
- *   fx, fy, fz     DEVICE FP32 [n_atoms] forces, eV/A                 (all three required)
+ *   fx, fy, fz     DEVICE FP32 [n_atoms] forces, eV/A. Pass all three, or all three NULL
+ *                  to evaluate energies only; the gradients stay resident so that a later
+ *                  flare_forces call for the same positions returns the forces.
  *   e_struct       DEVICE FP64 [n_struct] sum of e_i per cell, compensated (NULL = skip)
  *   var_atom, sigma_atom  DEVICE FP32 [n_atoms]: when either is non-NULL the variance
  *                  quadratic form is evaluated in the same pass over the descriptors.
- * Forces are accumulated with device atomics: they are reproducible to rounding, not
- * bitwise.
+ * Forces are gathered per atom in a fixed order (no atomics): results are bitwise
+ * reproducible and do not depend on which other cells share the call.
  */
 int flare_energy_forces(flare_state* state, float* e_atom, float* fx, float* fy, float* fz,
                         double* e_struct, float* var_atom, float* sigma_atom);
+
+/*
+ * Forces (the adjoint of the energy) for the positions of the last flare_energy_forces
+ * call, which must have run for the current flare_descriptors positions.
+ *   cell_scale     optional DEVICE FP64 [n_struct]: the forces of cell k are multiplied
+ *                  by cell_scale[k] (a backward pass passes -dL/dE_k to obtain dL/dr)
+ *   fx, fy, fz     DEVICE FP32 [n_atoms]
+ */
+int flare_forces(flare_state* state, const double* cell_scale, float* fx, float* fy, float* fz);
 
 /*
  * Variance and uncertainty only (Eq. 2), from the resident descriptors.
@@ -193,6 +204,9 @@ int flare_md_second_half(flare_state* state, double* vx, double* vy, double* vz,
 #define FLARE_T_MD        8  /* integrator halves                              */
 int flare_timers_enable(flare_state* state, int on);
 int flare_timers_read(flare_state* state, double* ms, long long* counts, int reset);
+
+/* Device memory held by the model (model may be NULL) and the state, in bytes (HOST). */
+int flare_memory_bytes(const flare_model* model, const flare_state* state, long long* bytes);
 
 /* Read and clear the device status word (SYNCHRONISING). flags_host: HOST int32.
  * flare_neighbors starts a new interval: it clears the word before its own checks. */

@@ -45,7 +45,9 @@ SIGNATURES = {
     "flare_neighbors_export": (_i, [_p, _p, _p, _p]),
     "flare_descriptors": (_i, [_p, _p, _p, _p, _p, _p]),
     "flare_energy_forces": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
+    "flare_forces": (_i, [_p, _p, _p, _p, _p]),
     "flare_variance": (_i, [_p, _p, _p, _p]),
+    "flare_memory_bytes": (_i, [_p, _p, ctypes.POINTER(_ll)]),
     "flare_md_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
     "flare_md_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
     "flare_timers_enable": (_i, [_p, _i]),

@@ -83,9 +83,8 @@ __device__ __forceinline__ int pair_index_same(int na, int nb) {
 // three groups of constant l: {0}, {1,2,3}, {4..7} with l = (0,1,2) for h = 0 and
 // (2,3,3) for h = 1. Each lane forms its partial w over its own (l, m); the xor-1
 // partner adds the rest.
-__global__ __launch_bounds__(TA) void k_adjoint144(PairView v, const int* __restrict__ atom_of_row,
-                                                   const float* __restrict__ G, float* __restrict__ w,
-                                                   long long P) {
+__global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __restrict__ atom_of_row,
+                                                   const float* __restrict__ G, float4* __restrict__ w) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int t = threadIdx.x, rl = t >> 1, h = t & 1;
   const int i = atom_of_row[tile * 128 + rl];
@@ -95,7 +94,8 @@ __global__ __launch_bounds__(TA) void k_adjoint144(PairView v, const int* __rest
   for (int n = 0; n < NR; ++n)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
-  accumulate_half(v, i, h, c);
+  const int R = tile * 128 + rl;
+  accumulate_half(v, R, h, c);
   // u = G^ c, group by group
   const float* g = G + (size_t)tile * ND1 * 128 + rl;
   const int lg0 = h ? 2 : 0, lg1 = h ? 3 : 1, lg2 = h ? 3 : 2;
@@ -128,17 +128,14 @@ __global__ __launch_bounds__(TA) void k_adjoint144(PairView v, const int* __rest
     }
   }
   const float fl0 = (float)lg0, fl1 = (float)lg1, fl2 = (float)lg2;
-  const size_t nn = (size_t)v.n;
-  const double xi = v.pos[i], yi = v.pos[nn + i], zi = v.pos[2 * nn + i];
-  const CellGrid* cg = v.grids + v.sid[i];
-  const double L[3] = {cg->L[0], cg->L[1], cg->L[2]};
-  const int p0 = v.nl_off[i], p1 = v.nl_off[i + 1];
-  for (int p = p0; p < p1; ++p) {
+  const int len = slice_len(v, R);
+  for (int k = 0; k < len; ++k) {
     PairGeom pg;
+    int sp;
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (pair_geom(v, v.nl_j[p], xi, yi, zi, L, v.nl_s[p], pg)) {
-      float R[NR], dR[NR], Y[NLM];
-      radial_d(pg.r, v.rc, R, dR);
+    if (slot_geom(v, R, k, pg, sp)) {
+      float Rn[NR], dR[NR], Y[NLM];
+      radial_d(pg.r, v.rc, Rn, dR);
       sph_harm(pg.ux, pg.uy, pg.uz, Y);
       float ys[NQ];
 #pragma unroll
@@ -155,9 +152,9 @@ __global__ __launch_bounds__(TA) void k_adjoint144(PairView v, const int* __rest
         const float z2 = c[n][4] * ys[4] + c[n][5] * ys[5] + c[n][6] * ys[6] + c[n][7] * ys[7];
         const float z = z0 + z1 + z2;
         const float zl = fl0 * z0 + fl1 * z1 + fl2 * z2;
-        s1 += dR[n] * z - R[n] * zl * inv_r;
+        s1 += dR[n] * z - Rn[n] * zl * inv_r;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) Aq[q] += c[n][q] * R[n];
+        for (int q = 0; q < NQ; ++q) Aq[q] += c[n][q] * Rn[n];
       }
       float A[NLM];
 #pragma unroll
@@ -174,18 +171,14 @@ __global__ __launch_bounds__(TA) void k_adjoint144(PairView v, const int* __rest
     wx += __shfl_xor(wx, 1, 64);
     wy += __shfl_xor(wy, 1, 64);
     wz += __shfl_xor(wz, 1, 64);
-    if (h == 0) {
-      w[p] = wx;
-      w[P + p] = wy;
-      w[2 * P + p] = wz;
-    }
+    if (h == 0) w[slot_of(v.slice_base, R, k)] = make_float4(wx, wy, wz, 0.f);
   }
 }
 
-__global__ __launch_bounds__(NTX) void k_adjoint_mixed(PairView v, int rows,
+__global__ __launch_bounds__(NTX) void k_adjoint_mixed(SlotView v, int rows1, int rows,
                                                        const int* __restrict__ atom_of_row,
                                                        const float* __restrict__ G,
-                                                       float* __restrict__ w, long long P) {
+                                                       float4* __restrict__ w) {
   // densities, then adjoints, of both species halves; one column per thread
   __shared__ float uh[NR * NLM][NTX];
   __shared__ float up[NR * NLM][NTX];
@@ -200,7 +193,7 @@ __global__ __launch_bounds__(NTX) void k_adjoint_mixed(PairView v, int rows,
     for (int n = 0; n < NR; ++n)
 #pragma unroll
       for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
-    accumulate_densities(v, i, half, c);
+    accumulate_densities(v, rows1 + row, half, c);
     float (*dst)[NTX] = half ? up : uh;
 #pragma unroll
     for (int n = 0; n < NR; ++n)
@@ -238,40 +231,34 @@ __global__ __launch_bounds__(NTX) void k_adjoint_mixed(PairView v, int rows,
       up[n * NLM + lm][t] = op[n];
     }
   }
-  const size_t nn = (size_t)v.n;
-  const double xi = v.pos[i], yi = v.pos[nn + i], zi = v.pos[2 * nn + i];
-  const CellGrid* cg = v.grids + v.sid[i];
-  const double L[3] = {cg->L[0], cg->L[1], cg->L[2]};
-  const int p0 = v.nl_off[i], p1 = v.nl_off[i + 1];
-  for (int p = p0; p < p1; ++p) {
-    const int j = v.nl_j[p];
+  const int R = rows1 + row;
+  const int len = slice_len(v, R);
+  for (int k = 0; k < len; ++k) {
     PairGeom pg;
+    int sp;
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (pair_geom(v, j, xi, yi, zi, L, v.nl_s[p], pg)) {
-      float (*u)[NTX] = v.sp[j] == 0 ? uh : up;
+    if (slot_geom(v, R, k, pg, sp)) {
+      float (*u)[NTX] = sp == 0 ? uh : up;
       pair_force(pg, v.rc, [&](int n, int lm) { return u[n * NLM + lm][t]; }, wx, wy, wz);
     }
-    w[p] = wx;
-    w[P + p] = wy;
-    w[2 * P + p] = wz;
+    w[slot_of(v.slice_base, R, k)] = make_float4(wx, wy, wz, 0.f);
   }
 }
 
 }  // namespace
 
 void compute_forces(flare_state* s) {
-  const PairView v = pair_view(s);
-  const long long P = s->max_pairs;
+  const SlotView v = slot_view(s);
   {
     StageTimer tm(s, FLARE_T_FORCE1);
     if (s->rows1 > 0)
-      k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->w_pair, P);
+      k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->w_slot.p);
   }
   {
     StageTimer tm(s, FLARE_T_FORCEX);
     if (s->rowsx > 0)
-      k_adjoint_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rowsx, s->atom_of_rowx.p,
-                                                                          s->Gx.p, s->w_pair, P);
+      k_adjoint_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rows1, s->rowsx,
+                                                                          s->atom_of_rowx.p, s->Gx.p, s->w_slot.p);
   }
 }
 

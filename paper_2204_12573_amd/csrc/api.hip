@@ -29,6 +29,14 @@ PairView pair_view(const flare_state* s) {
   return v;
 }
 
+SlotView slot_view(const flare_state* s) {
+  SlotView v;
+  v.geom = s->geom.p;
+  v.slice_base = s->slice_base.p;
+  v.rc = (float)s->model->r_cut;
+  return v;
+}
+
 namespace {
 hipEvent_t take_event(flare_state* s) {
   if (!s->timers.pool.empty()) {
@@ -79,6 +87,79 @@ using namespace flare;
     }                           \
   } while (0)
 
+namespace {
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f32(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+// Cholesky factor (lower) of a symmetric positive definite n x n matrix, FP64, in place
+// on a copy; returns false when a pivot is not positive.
+bool cholesky(std::vector<double>& a, int n) {
+  for (int j = 0; j < n; ++j) {
+    double d = a[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    a[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = a[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+      a[(size_t)i * n + j] = v / d;
+    }
+    for (int k = j + 1; k < n; ++k) a[(size_t)j * n + k] = 0.0;
+  }
+  return true;
+}
+
+// sub-block [start, start+nb)^2 of an n_d x n_d FP64 matrix
+std::vector<double> sub_block(const double* m, int start, int nb) {
+  std::vector<double> out((size_t)nb * nb);
+  for (int r = 0; r < nb; ++r)
+    for (int c = 0; c < nb; ++c) out[(size_t)r * nb + c] = m[(size_t)(start + r) * ND + (start + c)];
+  return out;
+}
+
+int upload(void** dst, const void* src, size_t bytes) {
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_error(std::string("model upload: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
+  }
+  return FLARE_OK;
+}
+
+// BF16 split fragments of one 144-block: B[k][n] = M[k][n], K padded to 160.
+// Layout [ks 5][cb 9][hi/lo 2][lane 64][8].
+void bf16_fragments(const std::vector<double>& M, uint16_t* out /* [5][9][2][64][8] */) {
+  const int nks = 5, ncb = ND1 / 16;
+  for (int ks = 0; ks < nks; ++ks)
+    for (int cb = 0; cb < ncb; ++cb)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 8; ++t) {
+          const int k = ks * 32 + 8 * (lane / 16) + t, n = cb * 16 + lane % 16;
+          const float v = k < ND1 ? (float)M[(size_t)k * ND1 + n] : 0.f;
+          const uint16_t hi = bf16_rne(v);
+          const uint16_t lo = bf16_rne(v - bf16_to_f32(hi));
+          const size_t base = ((((size_t)ks * ncb + cb) * 2) * 64 + lane) * 8 + t;
+          out[base] = hi;
+          out[base + 64 * 8] = lo;
+        }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* flare_last_error(void) { return g_last_error.c_str(); }
@@ -108,8 +189,8 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
     set_error("this build has kernels for n_species=2, n_rad=8, l_max=3 only");
     return FLARE_E_UNSUPPORTED;
   }
-  if (precision != FLARE_FP32) {
-    set_error("only FLARE_FP32 is available");
+  if (precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT) {
+    set_error("precision must be FLARE_FP32 or FLARE_BF16_SPLIT");
     return FLARE_E_UNSUPPORTED;
   }
   flare_model* m = new (std::nothrow) flare_model();
@@ -154,6 +235,60 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
       return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
     }
   }
+  if (precision == FLARE_BF16_SPLIT) {
+    const int nkc = ND1 / 16, ncb = ND1 / 16;
+    for (int b = 0; b < 4; ++b) {
+      const int s = b & 1;
+      const int st = b < 2 ? 0 : ND - ND1;
+      std::vector<double> beta = sub_block(beta_host + (size_t)s * ND * ND, st, ND1);
+      std::vector<double> L = sub_block(sigma_host + (size_t)s * ND * ND, st, ND1);
+      if (!cholesky(L, ND1)) {
+        set_error("Sigma block is not positive definite (needed by the split form)");
+        flare_model_destroy(m);
+        return FLARE_E_ARG;
+      }
+      const size_t per = (size_t)5 * ncb * 2 * 64 * 8;
+      std::vector<uint16_t> frag(per);
+      bf16_fragments(beta, frag.data());
+      int rc = upload((void**)&m->Wb[b], frag.data(), frag.size() * sizeof(uint16_t));
+      if (rc != FLARE_OK) {
+        flare_model_destroy(m);
+        return rc;
+      }
+      // FP32 fragments of L replace the Sigma part (part 1) of Wf
+      std::vector<float> f((size_t)nkc * ncb * 64 * 4);
+      for (int kc = 0; kc < nkc; ++kc)
+        for (int cb = 0; cb < ncb; ++cb)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int t = 0; t < 4; ++t) {
+              const int k = kc * 16 + 4 * (lane / 16) + t, col = cb * 16 + lane % 16;
+              f[(((size_t)kc * ncb + cb) * 64 + lane) * 4 + t] = (float)L[(size_t)k * ND1 + col];
+            }
+      hipError_t e = hipMemcpy(m->Wf[b] + (size_t)nkc * ncb * 64 * 4, f.data(), f.size() * sizeof(float),
+                               hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        set_error(std::string("model upload: ") + hipGetErrorString(e));
+        flare_model_destroy(m);
+        return FLARE_E_HIP;
+      }
+    }
+    for (int s = 0; s < NS; ++s) {
+      std::vector<double> L(sigma_host + (size_t)s * ND * ND, sigma_host + (size_t)(s + 1) * ND * ND);
+      if (!cholesky(L, ND)) {
+        set_error("Sigma is not positive definite (needed by the split form)");
+        flare_model_destroy(m);
+        return FLARE_E_ARG;
+      }
+      std::vector<float> lt((size_t)ND * ND);   // row n = column n of L
+      for (int n = 0; n < ND; ++n)
+        for (int k = 0; k < ND; ++k) lt[(size_t)n * ND + k] = (float)L[(size_t)k * ND + n];
+      int rc = upload((void**)&m->Lx[s], lt.data(), lt.size() * sizeof(float));
+      if (rc != FLARE_OK) {
+        flare_model_destroy(m);
+        return rc;
+      }
+    }
+  }
   *out = m;
   return FLARE_OK;
 }
@@ -162,8 +297,12 @@ int flare_model_destroy(flare_model* m) {
   if (!m) return FLARE_OK;
   for (int b = 0; b < NBUCKET; ++b)
     if (m->W[b]) (void)hipFree(m->W[b]);
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < 4; ++b) {
     if (m->Wf[b]) (void)hipFree(m->Wf[b]);
+    if (m->Wb[b]) (void)hipFree(m->Wb[b]);
+  }
+  for (int k = 0; k < 2; ++k)
+    if (m->Lx[k]) (void)hipFree(m->Lx[k]);
   delete m;
   return FLARE_OK;
 }
@@ -177,7 +316,7 @@ int flare_descriptor_dim(const flare_model* m, int* n_d) {
 static void free_state(flare_state* s) {
   void* ptrs[] = {s->perm, s->sp,  s->sid, s->bin,   s->envmask, s->bucket, s->row_of, s->nl_cnt,
                   s->nl_off, s->w, s->off, s->pos,   s->nrm,     s->e_int,  s->v_int,
-                  s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->nl_rev, s->w_pair, s->d_status,
+                  s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->nl_rev, s->slot_of_pair, s->d_status,
                   s->d_info};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -202,6 +341,15 @@ static void free_state(flare_state* s) {
   s->d_first_task.release();
   s->red_e.release();
   s->red_s.release();
+  s->slice_len.release();
+  s->slice_base.release();
+  s->slot_atom.release();
+  s->slot_j.release();
+  s->slot_s.release();
+  s->slot_pair.release();
+  s->slot_rev.release();
+  s->geom.release();
+  s->w_slot.release();
 }
 
 int flare_state_create(flare_state** out, const flare_model* model, int max_atoms,
@@ -220,6 +368,7 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   const size_t n = (size_t)max_atoms;
   auto al = [&](void** p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 4);
+    if (e == hipSuccess) s->fixed_bytes += (long long)(bytes ? bytes : 4);
   };
   al((void**)&s->perm, n * 4);
   al((void**)&s->sp, n * 4);
@@ -244,7 +393,7 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   al((void**)&s->nl_j, (size_t)max_pairs * 4);
   al((void**)&s->nl_s, (size_t)max_pairs * 4);
   al((void**)&s->nl_rev, (size_t)max_pairs * 4);
-  al((void**)&s->w_pair, 3 * (size_t)max_pairs * 4);
+  al((void**)&s->slot_of_pair, (size_t)max_pairs * 4);
   al((void**)&s->d_status, 64);
   al((void**)&s->d_info, 64);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_info, 64, hipHostMallocDefault);
@@ -411,6 +560,7 @@ int flare_descriptors(flare_state* s, const double* x, const double* y, const do
   {
     StageTimer tm(s, FLARE_T_DESC1);
     gather_positions(s, x, y, z);
+    pair_geometry(s);
   }
   if (d_out || norm_out) {
     // the single-species rows come from the fused kernel run without quadratic forms
@@ -431,7 +581,8 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
     set_error("flare_energy_forces before flare_descriptors");
     return FLARE_E_STALE;
   }
-  ARG(s->n_atoms == 0 || (fx && fy && fz), "force outputs are required");
+  const bool want_f = fx || fy || fz;
+  ARG(!want_f || (fx && fy && fz), "pass all three force arrays or none");
   const bool want_v = var_atom || sigma_atom;
   {
     StageTimer tm(s, FLARE_T_QFORM1);
@@ -442,13 +593,30 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
     StageTimer tm(s, FLARE_T_QFORMX);
     mixed_quadratic_forms(s, true, want_v);
   }
-  compute_forces(s);
+  s->g_gen = s->pos_gen;
+  if (want_f) compute_forces(s);
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, e_atom, fx, fy, fz, var_atom, sigma_atom);
     reduce_cells(s, e_struct, nullptr);
   }
   if (want_v) s->v_gen = s->pos_gen;
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_forces(flare_state* s, const double* cell_scale, float* fx, float* fy, float* fz) {
+  ARG(s, "null state");
+  ARG(fx && fy && fz, "null force array");
+  if (!s->have_desc || s->g_gen != s->pos_gen) {
+    set_error("flare_forces needs flare_energy_forces for the current positions");
+    return FLARE_E_STALE;
+  }
+  compute_forces(s);
+  {
+    StageTimer tm(s, FLARE_T_OUT);
+    finalize_outputs(s, nullptr, fx, fy, fz, nullptr, nullptr, cell_scale);
+  }
   CHK(hipGetLastError());
   return FLARE_OK;
 }
@@ -512,6 +680,27 @@ int flare_md_second_half(flare_state* s, double* vx, double* vy, double* vz, con
     md_second(s, vx, vy, vz, fx, fy, fz, species, 1.0 / masses_host[0], 1.0 / masses_host[1], dt);
   }
   CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* bytes) {
+  ARG(bytes, "null pointer");
+  long long b = 0;
+  if (m) {
+    for (int k = 0; k < NBUCKET; ++k) b += (long long)2 * bucket_width(k) * bucket_width(k) * sizeof(float);
+    b += 4LL * 2 * ND1 * ND1 * sizeof(float);
+  }
+  if (s) {
+    b += s->fixed_bytes;
+    b += s->d_grids.bytes() + s->d_struct_off.bytes() + s->bin_count.bytes() + s->bin_start.bytes() +
+         s->bin_fill.bytes() + s->blk_bucket.bytes() + s->blk_bucket_scan.bytes() + s->scan_scratch.bytes() +
+         s->atom_of_row1.bytes() + s->atom_of_rowx.bytes() + s->D1.bytes() + s->G1.bytes() + s->Dx.bytes() +
+         s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
+         s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
+         s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_s.bytes() + s->slot_pair.bytes() +
+         s->slot_rev.bytes() + s->geom.bytes() + s->w_slot.bytes();
+  }
+  *bytes = b;
   return FLARE_OK;
 }
 

@@ -54,7 +54,7 @@ __device__ __forceinline__ float4 b2_pair(const float* a, const float* b) {
   return make_float4(d0, d1, d2, d3);
 }
 
-__global__ __launch_bounds__(NTX) void k_desc_mixed(PairView v, int rows,
+__global__ __launch_bounds__(NTX) void k_desc_mixed(SlotView v, int rows1, int rows,
                                                     const int* __restrict__ atom_of_row,
                                                     float* __restrict__ D,
                                                     float* __restrict__ nrm_out) {
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NTX) void k_desc_mixed(PairView v, int rows,
   for (int n = 0; n < NR; ++n)
 #pragma unroll
     for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
-  accumulate_densities(v, i, 0, c);
+  accumulate_densities(v, rows1 + row, 0, c);
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(NTX) void k_desc_mixed(PairView v, int rows,
       ch[n * NLM + lm][t] = c[n][lm];
       c[n][lm] = 0.f;
     }
-  accumulate_densities(v, i, 1, c);     // c now holds the Pt channels
+  accumulate_densities(v, rows1 + row, 1, c);     // c now holds the Pt channels
   float a[NLM], b[NLM];
   float scale = 1.f;
   for (int pass = 0; pass < 2; ++pass) {
@@ -149,6 +149,39 @@ __global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict
   }
 }
 
+// Per-step geometry of every slot: Delta = (x_j - x_i) + s*L in FP64, kept when
+// |Delta|^2 < r_c^2, then (u^, r) in FP32 with the sign of r carrying the neighbour species.
+__global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __restrict__ slot_atom,
+                                              const int* __restrict__ slot_j,
+                                              const int32_t* __restrict__ slot_s,
+                                              const int* __restrict__ sp, const int* __restrict__ sid,
+                                              const CellGrid* __restrict__ grids,
+                                              const double* __restrict__ pos, int n, double rc2,
+                                              float4* __restrict__ geom) {
+  const long long slot = (long long)blockIdx.x * NTG + threadIdx.x;
+  if (slot >= nslots) return;
+  const int i = slot_atom[slot];
+  float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (i >= 0) {
+    const int j = slot_j[slot];
+    int sx, sy, sz;
+    unpack_shift(slot_s[slot], sx, sy, sz);
+    const CellGrid* g = grids + sid[i];
+    const size_t nn = (size_t)n;
+    const double dx = (pos[j] - pos[i]) + (double)sx * g->L[0];
+    const double dy = (pos[nn + j] - pos[nn + i]) + (double)sy * g->L[1];
+    const double dz = (pos[2 * nn + j] - pos[2 * nn + i]) + (double)sz * g->L[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rc2) {
+      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      const float inv = 1.f / r;
+      out = make_float4(fx * inv, fy * inv, fz * inv, sp[j] ? r : -r);
+    }
+  }
+  geom[slot] = out;
+}
+
 __global__ __launch_bounds__(NTG) void k_export_desc(int n, const int* __restrict__ perm,
                                                      const int* __restrict__ bucket,
                                                      const int* __restrict__ row_of,
@@ -185,11 +218,20 @@ void gather_positions(flare_state* s, const double* x, const double* y, const do
                                                            lim * lim, s->d_status);
 }
 
+void pair_geometry(flare_state* s) {
+  const long long ns = s->n_slots;
+  if (ns == 0) return;
+  const double rc = s->model->r_cut;
+  k_geom<<<(int)((ns + NTG - 1) / NTG), NTG, 0, s->stream>>>(ns, s->slot_atom.p, s->slot_j.p, s->slot_s.p, s->sp,
+                                                             s->sid, s->d_grids.p, s->pos, s->n_atoms, rc * rc,
+                                                             s->geom.p);
+}
+
 void compute_descriptors_mixed(flare_state* s) {
-  const PairView v = pair_view(s);
+  const SlotView v = slot_view(s);
   StageTimer tm(s, FLARE_T_DESCX);
   if (s->rowsx > 0)
-    k_desc_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rowsx, s->atom_of_rowx.p,
+    k_desc_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rows1, s->rowsx, s->atom_of_rowx.p,
                                                                     s->Dx.p, s->nrm);
 }
 

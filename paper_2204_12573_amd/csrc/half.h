@@ -11,16 +11,14 @@ namespace flare {
 
 constexpr int NQ = 8;   // (l, m) indices per lane
 
-// c[n][q] += R_n Y_{8h+q} over the neighbours of atom i inside the cutoff.
-__device__ __forceinline__ void accumulate_half(const PairView& v, int i, int h, float (*c)[NQ]) {
-  const size_t n = (size_t)v.n;
-  const double xi = v.pos[i], yi = v.pos[n + i], zi = v.pos[2 * n + i];
-  const CellGrid* g = v.grids + v.sid[i];
-  const double L[3] = {g->L[0], g->L[1], g->L[2]};
-  const int p0 = v.nl_off[i], p1 = v.nl_off[i + 1];
-  for (int p = p0; p < p1; ++p) {
+// c[n][q] += R_n Y_{8h+q} over the neighbours of row R inside the cutoff. All rows of a
+// wave share one slice, so the trip count is uniform across the wave.
+__device__ __forceinline__ void accumulate_half(const SlotView& v, int Rw, int h, float (*c)[NQ]) {
+  const int len = slice_len(v, Rw);
+  for (int k = 0; k < len; ++k) {
     PairGeom pg;
-    if (!pair_geom(v, v.nl_j[p], xi, yi, zi, L, v.nl_s[p], pg)) continue;
+    int sp;
+    if (!slot_geom(v, Rw, k, pg, sp)) continue;
     float R[NR], Y[NLM];
     radial(pg.r, v.rc, R);
     sph_harm(pg.ux, pg.uy, pg.uz, Y);

@@ -232,6 +232,57 @@ __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ n
   }
 }
 
+// ---- sliced pair layout ----
+// Row R of atom i: 144-wide rows R = row_of[i], mixed rows R = rows1 + row_of[i].
+__device__ inline int global_row(int b, int r, int rows1) { return b < 4 ? r : rows1 + r; }
+
+__global__ __launch_bounds__(NT) void k_slice_len(int n, const int* __restrict__ bucket,
+                                                  const int* __restrict__ row_of,
+                                                  const int* __restrict__ cnt, int rows1,
+                                                  int* __restrict__ slice_len) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int b = bucket[i];
+  if (b < 0) return;
+  atomicMax(&slice_len[global_row(b, row_of[i], rows1) >> 5], cnt[i]);
+}
+
+__global__ __launch_bounds__(NT) void k_fill_slots(int n, const int* __restrict__ bucket,
+                                                   const int* __restrict__ row_of,
+                                                   const int* __restrict__ nl_off,
+                                                   const int* __restrict__ nl_j,
+                                                   const int32_t* __restrict__ nl_s, int rows1,
+                                                   const int* __restrict__ slice_base,
+                                                   int* __restrict__ slot_atom, int* __restrict__ slot_j,
+                                                   int* __restrict__ slot_s, int* __restrict__ slot_pair,
+                                                   int* __restrict__ slot_of_pair) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int b = bucket[i];
+  if (b < 0) return;
+  const int R = global_row(b, row_of[i], rows1);
+  const int p0 = nl_off[i], p1 = nl_off[i + 1];
+  for (int p = p0; p < p1; ++p) {
+    const int slot = slot_of(slice_base, R, p - p0);
+    slot_atom[slot] = i;
+    slot_j[slot] = nl_j[p];
+    slot_s[slot] = nl_s[p];
+    slot_pair[slot] = p;
+    slot_of_pair[p] = slot;
+  }
+}
+
+// slot of the reverse pair; padding slots point at themselves
+__global__ __launch_bounds__(NT) void k_rev_slots(long long nslots, const int* __restrict__ slot_atom,
+                                                  const int* __restrict__ slot_pair,
+                                                  const int* __restrict__ nl_rev,
+                                                  const int* __restrict__ slot_of_pair,
+                                                  int* __restrict__ slot_rev) {
+  const long long slot = (long long)blockIdx.x * NT + threadIdx.x;
+  if (slot >= nslots) return;
+  slot_rev[slot] = slot_atom[slot] < 0 ? (int)slot : slot_of_pair[nl_rev[slot_pair[slot]]];
+}
+
 struct Row0 {
   int r[NBUCKET];
 };
@@ -381,6 +432,42 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
   }
+  // sliced layout: slice lengths, their prefix, then the slots
+  s->n_slices = (r1 + rx) / 32;
+  HIPCHK(s->slice_len.reserve(s->n_slices + 1));
+  HIPCHK(s->slice_base.reserve(s->n_slices + 1));
+  HIPCHK(hipMemsetAsync(s->slice_len.p, 0, (s->n_slices + 1) * sizeof(int), st));
+  if (n > 0)
+    k_slice_len<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, s->nl_cnt, r1, s->slice_len.p);
+  HIPCHK(s->scan_scratch.reserve(scan_scratch_ints(std::max<long long>(scan_n, s->n_slices))));
+  scan_exclusive(s->slice_len.p, s->slice_base.p, s->n_slices, s->scan_scratch.p, st);
+  HIPCHK(hipMemcpyAsync(s->h_info + 9, s->slice_base.p + s->n_slices, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(s->h_info + 10, s->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s->h_info[10] & 256) {
+    set_error("internal: neighbour list is not symmetric");
+    return FLARE_E_HIP;
+  }
+  const long long nslots = 32LL * s->h_info[9];
+  s->n_slots = nslots;
+  HIPCHK(s->slot_atom.reserve(nslots + 1));
+  HIPCHK(s->slot_j.reserve(nslots + 1));
+  HIPCHK(s->slot_s.reserve(nslots + 1));
+  HIPCHK(s->slot_pair.reserve(nslots + 1));
+  HIPCHK(s->slot_rev.reserve(nslots + 1));
+  HIPCHK(s->geom.reserve(nslots + 1));
+  HIPCHK(s->w_slot.reserve(nslots + 1));
+  HIPCHK(hipMemsetAsync(s->slot_atom.p, 0xff, (nslots + 1) * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(s->slot_j.p, 0, (nslots + 1) * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(s->slot_s.p, 0, (nslots + 1) * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(s->slot_pair.p, 0, (nslots + 1) * sizeof(int), st));
+  if (n > 0) {
+    k_fill_slots<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, s->nl_off, s->nl_j, s->nl_s, r1, s->slice_base.p,
+                                      s->slot_atom.p, s->slot_j.p, s->slot_s.p, s->slot_pair.p, s->slot_of_pair);
+  }
+  if (nslots > 0)
+    k_rev_slots<<<(int)((nslots + NT - 1) / NT), NT, 0, st>>>(nslots, s->slot_atom.p, s->slot_pair.p, s->nl_rev,
+                                                              s->slot_of_pair, s->slot_rev.p);
   // reduction tasks: contiguous internal ranges of one cell, at most 16384 atoms each
   s->tasks.clear();
   for (int c = 0; c < nc; ++c) {

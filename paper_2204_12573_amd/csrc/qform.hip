@@ -36,6 +36,8 @@ struct QArgs {
   float* Y;              // [rows][KD]      beta-part products, split path
   float* P;              // [rows][4]       partial row-dots, split path
   int mode;              // bit 0: beta part, bit 1: Sigma part
+  int sumsq;             // Sigma part given as its Cholesky factor L: V = |d L|^2
+  int pbase;             // first partial slot written by this launch
   int nbk;               // buckets in this launch
   int row0[4];           // first row of each bucket (padded to TM)
   int row1[4];           // one past its last padded row
@@ -145,9 +147,9 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
         const int col = col_base + j * 16 + l16;
         const bool beta_col = has_e && col < KD;
         const int kcol = beta_col ? col : (has_e ? col - KD : col);
-        const float prod = acc[i][j][r] * drow[kcol];
-        if (beta_col) pe[r] += prod;
-        else pv[r] += prod;
+        const float y = acc[i][j][r];
+        if (beta_col) pe[r] += y * drow[kcol];
+        else pv[r] += q.sumsq ? y * y : y * drow[kcol];
       }
     }
 #pragma unroll
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
           }
         }
       } else {
-        if (l16 == 0) q.P[(size_t)row * 4 + ntile] = has_e && col_base < KD ? pe[r] : pv[r];
+        if (l16 == 0) q.P[(size_t)row * 4 + q.pbase + ntile] = has_e && col_base < KD ? pe[r] : pv[r];
         if (has_e && col_base < KD) {
           float* yrow = q.Y + (size_t)row * KD;
 #pragma unroll
@@ -254,6 +256,9 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
     q.row1[k] = s->bucket_row0[bk] + padded;
     q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)ND * ND);
   }
+  // split form: the Sigma columns come from L (V = |d L|^2); with both parts the kernel
+  // reads the beta rows of W then continues into L through a second launch
+  q.sumsq = m->precision == FLARE_BF16_SPLIT ? 1 : 0;
   q.D = s->Dx.p;
   q.G = s->Gx.p;
   q.aor = s->atom_of_rowx.p;
@@ -261,7 +266,21 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   q.P = s->Px.p;
   const int parts = ((mode & 1) ? 1 : 0) + ((mode & 2) ? 1 : 0);
   const int ntiles = 2 * parts;   // 272 columns per tile
-  k_qform<ND, 17, false><<<dim3(rows / TM, ntiles), NTQ, 0, s->stream>>>(q);
+  if (q.sumsq && (mode & 2)) {
+    // beta tiles (if any) from W, Sigma tiles from L, partials in the same slots
+    if (mode & 1) {
+      QArgs qe = q;
+      qe.mode = 1;
+      k_qform<ND, 17, false><<<dim3(rows / TM, 2), NTQ, 0, s->stream>>>(qe);
+    }
+    QArgs qv = q;
+    qv.mode = 2;
+    qv.pbase = (mode & 1) ? 2 : 0;
+    for (int k = 0; k < 2; ++k) qv.W[k] = m->Lx[k];
+    k_qform<ND, 17, false><<<dim3(rows / TM, 2), NTQ, 0, s->stream>>>(qv);
+  } else {
+    k_qform<ND, 17, false><<<dim3(rows / TM, ntiles), NTQ, 0, s->stream>>>(q);
+  }
   k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
                                                         s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int);
 }

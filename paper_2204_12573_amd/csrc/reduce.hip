@@ -10,39 +10,73 @@ namespace {
 
 constexpr int NT = 256;
 
-// Caller-order outputs. Forces by gathering the per-pair adjoint terms:
-// F_i = sum_{p in list(i)} (w_p - w_rev(p)), in list order (deterministic).
-__global__ __launch_bounds__(NT) void k_outputs(int n, const int* __restrict__ perm,
-                                                const int* __restrict__ bucket,
-                                                const int* __restrict__ nl_off,
-                                                const int* __restrict__ rev,
-                                                const float* __restrict__ w, long long P,
+// Caller-order outputs, one thread per row. Forces by gathering the per-pair adjoint
+// terms over the row's slots: F_i = sum_k (w_slot(i,k) - w_rev(slot(i,k))), in slot order
+// (deterministic; padding slots hold w = 0 and point at themselves).
+__global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* __restrict__ aor1,
+                                                const int* __restrict__ aorx,
+                                                const int* __restrict__ slice_base,
+                                                const float4* __restrict__ w,
+                                                const int* __restrict__ slot_rev,
+                                                const int* __restrict__ perm,
+                                                const int* __restrict__ sid,
+                                                const double* __restrict__ cell_scale,
                                                 const float* __restrict__ e_int,
                                                 const float* __restrict__ v_int,
                                                 float* __restrict__ e_atom, float* __restrict__ fx,
                                                 float* __restrict__ fy, float* __restrict__ fz,
                                                 float* __restrict__ var_atom,
                                                 float* __restrict__ sigma_atom) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
+  const int R = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  if (R >= rows) return;
+  const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
+  if (i < 0) return;
   const int a = perm[i];
-  const bool has = bucket[i] >= 0;
-  if (e_atom) e_atom[a] = has ? e_int[i] : 0.f;
+  if (e_atom) e_atom[a] = e_int[i];
   if (fx) {
+    const int base = slice_base[R >> 5], len = slice_base[(R >> 5) + 1] - base;
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int p = nl_off[i]; p < nl_off[i + 1]; ++p) {
-      const int q = rev[p];
-      sx += w[p] - w[q];
-      sy += w[P + p] - w[P + q];
-      sz += w[2 * P + p] - w[2 * P + q];
+    for (int k = 0; k < len; ++k) {
+      const int slot = (base + k) * 32 + (R & 31);
+      const float4 wo = w[slot];
+      const float4 wr = w[slot_rev[slot]];
+      sx += wo.x - wr.x;
+      sy += wo.y - wr.y;
+      sz += wo.z - wr.z;
+    }
+    if (cell_scale) {
+      const float k = (float)cell_scale[sid[i]];
+      sx *= k;
+      sy *= k;
+      sz *= k;
     }
     fx[a] = sx;
     fy[a] = sy;
     fz[a] = sz;
   }
-  const float v = has ? v_int[i] : 0.f;
+  const float v = v_int[i];
   if (var_atom) var_atom[a] = v;
   if (sigma_atom) sigma_atom[a] = sqrtf(fmaxf(v, 0.f));
+}
+
+// Atoms without any neighbour in the list radius: zero energy, force and variance.
+__global__ __launch_bounds__(NT) void k_outputs_empty(int n, const int* __restrict__ bucket,
+                                                      const int* __restrict__ perm,
+                                                      float* __restrict__ e_atom, float* __restrict__ fx,
+                                                      float* __restrict__ fy, float* __restrict__ fz,
+                                                      float* __restrict__ var_atom,
+                                                      float* __restrict__ sigma_atom) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n || bucket[i] >= 0) return;
+  const int a = perm[i];
+  if (e_atom) e_atom[a] = 0.f;
+  if (fx) {
+    fx[a] = 0.f;
+    fy[a] = 0.f;
+    fz[a] = 0.f;
+  }
+  if (var_atom) var_atom[a] = 0.f;
+  if (sigma_atom) sigma_atom[a] = 0.f;
 }
 
 __device__ inline void two_sum_add(double& s, double& c, double x) {
@@ -153,12 +187,17 @@ __global__ __launch_bounds__(NT) void k_md_second(int n, double* __restrict__ vx
 }  // namespace
 
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
-                      float* var_atom, float* sigma_atom) {
+                      float* var_atom, float* sigma_atom, const double* cell_scale) {
   const int n = s->n_atoms;
   if (n == 0) return;
-  k_outputs<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->bucket, s->nl_off, s->nl_rev, s->w_pair,
-                                                     s->max_pairs, s->e_int, s->v_int, e_atom, fx, fy, fz,
-                                                     var_atom, sigma_atom);
+  const int rows = s->rows1 + s->rowsx;
+  if (rows > 0)
+    k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
+                                                         s->slice_base.p, s->w_slot.p, s->slot_rev.p, s->perm,
+                                                         s->sid, cell_scale, s->e_int, s->v_int, e_atom, fx, fy, fz, var_atom,
+                                                         sigma_atom);
+  k_outputs_empty<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->bucket, s->perm, e_atom, fx, fy, fz, var_atom,
+                                                           sigma_atom);
 }
 
 void reduce_cells(flare_state* s, double* e_struct, float* sigma_max) {

@@ -11,6 +11,7 @@ template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t cap = 0;
+  size_t bytes() const { return cap * sizeof(T); }
   hipError_t reserve(size_t n) {
     if (n <= cap) return hipSuccess;
     if (p) (void)hipFree(p);
@@ -51,6 +52,22 @@ struct Timers {
   long long cnt[FLARE_NTIMERS] = {};
 };
 
+// Per-step pair data in the sliced layout (see nlist.hip): rows are grouped in slices of
+// 32 consecutive rows; the k-th pair of every row of a slice sits in one contiguous group
+// of 32 slots, so a wave reading "pair k of its 32 rows" reads 512 contiguous bytes.
+//   row R: 144-wide rows are R = 0..rows1-1, mixed rows R = rows1 + r
+//   slot(R, k) = (slice_base[R / 32] + k) * 32 + R % 32
+struct SlotView {
+  const float4* geom;       // per slot: (u_x, u_y, u_z, r) of the pair, r = 0 outside the
+                            // cutoff or padding; r < 0 marks an H neighbour, r > 0 Pt
+  const int* slice_base;    // [slices + 1] in groups of 32 slots
+  float rc;
+};
+
+__host__ __device__ inline int slot_of(const int* slice_base, int R, int k) {
+  return (slice_base[R >> 5] + k) * 32 + (R & 31);
+}
+
 // Reduction task: a contiguous internal atom range of one cell.
 struct RedTask {
   int cell;
@@ -71,6 +88,13 @@ struct flare_model {
   // Single-species buckets: the same matrices in MFMA fragment order,
   // [part 2][K chunk 9][column block 9][lane 64] float4 (see fused.hip).
   float* Wf[4] = {};
+  // BF16 split form (precision FLARE_BF16_SPLIT), single-species buckets: beta as
+  // [K step 5][column block 9][hi/lo 2][lane 64] x 8 bf16 (K padded 144 -> 160). In this
+  // form the Sigma part of Wf holds the Cholesky factor L of Sigma (Sigma = L L^T).
+  uint16_t* Wb[4] = {};
+  // Mixed buckets in the split form: L of the 544 x 544 Sigma_s, [544][544] FP32, stored
+  // like W (row n = column n of L).
+  float* Lx[2] = {};
 };
 
 struct flare_state {
@@ -85,6 +109,8 @@ struct flare_state {
   bool have_desc = false;
   long long pos_gen = 0;     // positions staged by flare_descriptors
   long long v_gen = -1;      // positions the variances were computed for
+  long long g_gen = -1;      // positions the energy gradients were computed for
+  long long fixed_bytes = 0; // device bytes of the fixed-size arrays
   int n_atoms = 0;
   int n_struct = 0;
   int n_bins = 0;
@@ -127,7 +153,7 @@ struct flare_state {
   int* nl_j = nullptr;       // internal index of the neighbour
   int32_t* nl_s = nullptr;   // packed image shift
   int* nl_rev = nullptr;     // index of the reverse pair (j, i, -s) in j's list
-  float* w_pair = nullptr;   // [3][max_pairs] de_i/dDelta_ij of each listed pair
+  int* slot_of_pair = nullptr;
 
   // ---- grow-at-build buffers ----
   flare::DevBuf<flare::CellGrid> d_grids;
@@ -141,6 +167,13 @@ struct flare_state {
   flare::DevBuf<int> d_first_task;                   // [n_struct] first task of each cell
   flare::DevBuf<double> red_e;                       // [tasks][2] (sum, compensation)
   flare::DevBuf<float> red_s;                        // [tasks]
+  // sliced pair layout (grown at list builds)
+  int n_slices = 0;
+  long long n_slots = 0;
+  flare::DevBuf<int> slice_len, slice_base;          // [slices (+1)]
+  flare::DevBuf<int> slot_atom, slot_j, slot_s, slot_pair, slot_rev;
+  flare::DevBuf<float4> geom;                        // per slot, per step
+  flare::DevBuf<float4> w_slot;                      // per slot: de_i/dDelta (x, y, z, 0)
 
   flare::Timers timers;
 
@@ -152,6 +185,7 @@ struct flare_state {
 
 namespace flare {
 PairView pair_view(const flare_state* s);
+SlotView slot_view(const flare_state* s);
 
 // Records the stage's start event on construction and its stop event on destruction.
 struct StageTimer {
@@ -165,13 +199,14 @@ struct StageTimer {
 int build_list(flare_state* s, const double* x, const double* y, const double* z,
                const int32_t* species);
 void gather_positions(flare_state* s, const double* x, const double* y, const double* z);
+void pair_geometry(flare_state* s);
 void compute_descriptors_mixed(flare_state* s);
 void export_descriptors(flare_state* s, float* d_out, float* norm_out);
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out);
 void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v);
 void compute_forces(flare_state* s);
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
-                      float* var_atom, float* sigma_atom);
+                      float* var_atom, float* sigma_atom, const double* cell_scale = nullptr);
 void reduce_cells(flare_state* s, double* e_struct, float* sigma_max);
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy,
               double* vz, const float* fx, const float* fy, const float* fz,

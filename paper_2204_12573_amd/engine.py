@@ -105,6 +105,33 @@ class Evaluator:
                                                  B.ptr(out.get("var")), B.ptr(out.get("sigma"))))
         return out
 
+    def energies(self, out=None, want_var=False):
+        """Energies (and variances) without forces; the gradients stay resident."""
+        out = {} if out is None else out
+        dev = self.device
+        out.setdefault("e", torch.empty(self.n, dtype=torch.float32, device=dev))
+        out.setdefault("E", torch.empty(self.n_struct, dtype=torch.float64, device=dev))
+        if want_var:
+            out.setdefault("var", torch.empty(self.n, dtype=torch.float32, device=dev))
+            out.setdefault("sigma", torch.empty(self.n, dtype=torch.float32, device=dev))
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_energy_forces(self.handle, B.ptr(out["e"]), None, None, None, B.ptr(out["E"]),
+                                                 B.ptr(out.get("var")), B.ptr(out.get("sigma"))))
+        return out
+
+    def forces(self, cell_scale=None, f=None):
+        """Forces of the last energies() / energy_forces() positions, optionally scaled per cell."""
+        f = torch.empty((3, self.n), dtype=torch.float32, device=self.device) if f is None else f
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_forces(self.handle, B.ptr(cell_scale), B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2])))
+        return f
+
+    def memory_bytes(self, with_model=True):
+        b = ctypes.c_longlong()
+        B.check(self.lib.flare_memory_bytes(self.model.handle if with_model else None, self.handle,
+                                            ctypes.byref(b)))
+        return b.value
+
     def variance(self, out=None):
         out = out or {}
         dev = self.device

@@ -22,13 +22,13 @@ def rel_vec(f, ref):
 
 
 def gpu_eval(pos, species, box_or_boxes, beta, sigma, offsets=None, skin=0.2, want_d=False,
-             max_pairs=None):
+             max_pairs=None, precision=0):
     """Full evaluation on the GPU; returns numpy arrays in the caller's atom order."""
     n = len(species)
     boxes = np.asarray(box_or_boxes, np.float64).reshape(-1, 3)
     if offsets is None:
         offsets = np.array([0, n], np.int32)
-    model = engine.Model(beta, sigma)
+    model = engine.Model(beta, sigma, precision=precision)
     ev = engine.Evaluator(model, max_atoms=max(n, 1), max_pairs=max_pairs or max(64 * n, 1024))
     p, s = engine.to_device(pos, species)
     ev.neighbors(p, s, offsets, boxes, skin)
