@@ -26,6 +26,35 @@ PEAK_FP32_MFMA = 157.3e12      # dense FP32 matrix FLOP/s, MI355X
 PEAK_HBM = 8.0e12              # B/s
 
 
+PROFILE = os.path.join(ROOT, "profiles", "bench_large_fp32.txt")
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ["fused.hip", "half.h", "pair.h", "basis.h", "common.h", "state.h"]:
+        with open(os.path.join(ROOT, "paper_2204_12573_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel="k_fused144<0>"):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    try:
+        with open(PROFILE) as fh:
+            txt = fh.read()
+        data = json.loads(txt.split("# json\n", 1)[1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("sha256") != kernel_sources_sha():
+        return None
+    k = data["kernels"].get(kernel)
+    if not k:
+        return None
+    return (k["fetch_MB"] + k["write_MB"]) * 1e6
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -191,8 +220,9 @@ def main():
     flops_per_launch = n144 * 2 * 2 * 144 * 144
     achieved = flops_per_launch / (q_ms / q_cnt * 1e-3)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                "kernel": "k_qform<144,18> (D[beta|Sigma], 144-wide rows, FP32 MFMA)"}
+                "frac": achieved / PEAK_FP32_MFMA, "traffic": profiled_traffic(),
+                "kernel": "k_fused144 (descriptors + D[Sigma], D[beta] on FP32 MFMA, 144-wide rows)",
+                "algorithmic_flop_per_launch": flops_per_launch, "avg_launch_us": q_ms / q_cnt * 1e3}
     stage_us = {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm.items() if c}
     out = {
         "metric": METRIC,
@@ -221,6 +251,9 @@ def main():
         ev2, m2, el2, tm2 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
                                           binding.BF16_SPLIT)
         del ev2, m2
+        ev3, m3, el3, tm3 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
+                                          binding.FP8_SPLIT)
+        del ev3, m3
         log("errors vs the FP64 oracle on a 300-atom sample ...")
         rng = np.random.default_rng(12)
         ztop = 23 * S.DZ
@@ -235,6 +268,12 @@ def main():
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm2.items() if c},
             "note": "energy pass BF16 x3 (d and beta split hi/lo), variance |L^T d|^2 on FP32 cores "
                     "with an FP64 Cholesky factor, FP64 sums; mixed-environment rows FP32"}
+        out["mixed_fp8_split"] = {
+            "value": round(n * args.steps / el3 / 1e6, 3), "ms_per_step": round(el3 / args.steps * 1e3, 4),
+            "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.FP8_SPLIT, tg, ref),
+            "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm3.items() if c},
+            "note": "energy pass OCP e4m3 x3 with power-of-two row and block scales (d and beta split "
+                    "hi/lo'), variance as in the BF16 form; mixed-environment rows FP32"}
         log("serving ...")
         out["serving"] = serving(engine, torch, beta, sigma, args.serve_requests, 2000.0)
         log("autograd (256 cells) ...")

@@ -79,10 +79,11 @@ __device__ __forceinline__ int pair_index_same(int na, int nb) {
   return na * NR - na * (na - 1) / 2 + (nb - na);
 }
 
-// Two lanes per row (see half.h). Lane h holds u[n][q] for (l, m) = 8h + q; its q fall in
-// three groups of constant l: {0}, {1,2,3}, {4..7} with l = (0,1,2) for h = 0 and
-// (2,3,3) for h = 1. Each lane forms its partial w over its own (l, m); the xor-1
-// partner adds the rest.
+// Two lanes per row (see half.h). The densities and u = G^ c are formed split by (l, m):
+// lane h holds u[n][q] for (l, m) = 8h + q, whose q fall in three groups of constant l,
+// {0}, {1,2,3}, {4..7}, with l = (0,1,2) for h = 0 and (2,3,3) for h = 1. The two halves
+// are then exchanged so that each lane holds all of u, and the row's pairs are split
+// between the lanes (slots k = h, h + 2, ...): every pair term is evaluated once.
 __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __restrict__ atom_of_row,
                                                    const float* __restrict__ G, float4* __restrict__ w) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -127,51 +128,30 @@ __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __rest
       }
     }
   }
-  const float fl0 = (float)lg0, fl1 = (float)lg1, fl2 = (float)lg2;
-  const int len = slice_len(v, R);
-  for (int k = 0; k < len; ++k) {
+  // full u in both lanes of the row
+  float u[NR][NLM];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const float other = xor1(c[n][q]);
+      u[n][q] = h ? other : c[n][q];
+      u[n][NQ + q] = h ? c[n][q] : other;
+    }
+  const int base = v.slice_base[R >> 5];
+  const int len = v.slice_base[(R >> 5) + 1] - base;
+  const float4* gp = v.geom + (size_t)base * 32 + (R & 31);
+  float4* wp = w + (size_t)base * 32 + (R & 31);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 gnext = h < len ? gp[(size_t)h * 32] : zero;
+  for (int k = h; k < len; k += 2) {
+    const float4 gk = gnext;
+    gnext = k + 2 < len ? gp[(size_t)(k + 2) * 32] : zero;
     PairGeom pg;
     int sp;
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (slot_geom(v, R, k, pg, sp)) {
-      float Rn[NR], dR[NR], Y[NLM];
-      radial_d(pg.r, v.rc, Rn, dR);
-      sph_harm(pg.ux, pg.uy, pg.uz, Y);
-      float ys[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) ys[q] = h ? Y[NQ + q] : Y[q];
-      const float inv_r = 1.f / pg.r;
-      float s1 = 0.f;
-      float Aq[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) Aq[q] = 0.f;
-#pragma unroll
-      for (int n = 0; n < NR; ++n) {
-        const float z0 = c[n][0] * ys[0];
-        const float z1 = c[n][1] * ys[1] + c[n][2] * ys[2] + c[n][3] * ys[3];
-        const float z2 = c[n][4] * ys[4] + c[n][5] * ys[5] + c[n][6] * ys[6] + c[n][7] * ys[7];
-        const float z = z0 + z1 + z2;
-        const float zl = fl0 * z0 + fl1 * z1 + fl2 * z2;
-        s1 += dR[n] * z - Rn[n] * zl * inv_r;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) Aq[q] += c[n][q] * Rn[n];
-      }
-      float A[NLM];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        A[q] = h ? 0.f : Aq[q];
-        A[NQ + q] = h ? Aq[q] : 0.f;
-      }
-      float gx, gy, gz;
-      poly_grad_dot(A, pg.ux, pg.uy, pg.uz, gx, gy, gz);
-      wx = pg.ux * s1 + gx * inv_r;
-      wy = pg.uy * s1 + gy * inv_r;
-      wz = pg.uz * s1 + gz * inv_r;
-    }
-    wx += __shfl_xor(wx, 1, 64);
-    wy += __shfl_xor(wy, 1, 64);
-    wz += __shfl_xor(wz, 1, 64);
-    if (h == 0) w[slot_of(v.slice_base, R, k)] = make_float4(wx, wy, wz, 0.f);
+    if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
+    wp[(size_t)k * 32] = make_float4(wx, wy, wz, 0.f);
   }
 }
 
@@ -232,12 +212,12 @@ __global__ __launch_bounds__(NTX) void k_adjoint_mixed(SlotView v, int rows1, in
     }
   }
   const int R = rows1 + row;
-  const int len = slice_len(v, R);
-  for (int k = 0; k < len; ++k) {
+  SLOT_STREAM_BEGIN(v, R);
+  for (int k = 0; k < ss_len; ++k) {
     PairGeom pg;
     int sp;
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (slot_geom(v, R, k, pg, sp)) {
+    if (unpack_geom(SLOT_STREAM_NEXT(k), pg, sp)) {
       float (*u)[NTX] = sp == 0 ? uh : up;
       pair_force(pg, v.rc, [&](int n, int lm) { return u[n * NLM + lm][t]; }, wx, wy, wz);
     }

@@ -189,8 +189,8 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
     set_error("this build has kernels for n_species=2, n_rad=8, l_max=3 only");
     return FLARE_E_UNSUPPORTED;
   }
-  if (precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT) {
-    set_error("precision must be FLARE_FP32 or FLARE_BF16_SPLIT");
+  if (precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT && precision != FLARE_FP8_SPLIT) {
+    set_error("precision must be FLARE_FP32, FLARE_BF16_SPLIT or FLARE_FP8_SPLIT");
     return FLARE_E_UNSUPPORTED;
   }
   flare_model* m = new (std::nothrow) flare_model();
@@ -235,7 +235,7 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
       return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
     }
   }
-  if (precision == FLARE_BF16_SPLIT) {
+  if (precision == FLARE_BF16_SPLIT || precision == FLARE_FP8_SPLIT) {
     const int nkc = ND1 / 16, ncb = ND1 / 16;
     for (int b = 0; b < 4; ++b) {
       const int s = b & 1;
@@ -247,10 +247,43 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
         flare_model_destroy(m);
         return FLARE_E_ARG;
       }
-      const size_t per = (size_t)5 * ncb * 2 * 64 * 8;
-      std::vector<uint16_t> frag(per);
-      bf16_fragments(beta, frag.data());
-      int rc = upload((void**)&m->Wb[b], frag.data(), frag.size() * sizeof(uint16_t));
+      int rc = FLARE_OK;
+      if (precision == FLARE_BF16_SPLIT) {
+        const size_t per = (size_t)5 * ncb * 2 * 64 * 8;
+        std::vector<uint16_t> frag(per);
+        bf16_fragments(beta, frag.data());
+        rc = upload((void**)&m->Wb[b], frag.data(), frag.size() * sizeof(uint16_t));
+      } else {
+        double mx = 0.0;
+        for (double x : beta) mx = std::max(mx, std::fabs(x));
+        int ex = 0;
+        std::frexp(mx > 0.0 ? mx : 1.0, &ex);               // mx = f 2^ex, f in [0.5, 1)
+        const float sb = std::ldexp(1.0f, 4 - ex);         // |sb beta| < 16
+        m->beta_scale[b] = sb;
+        std::vector<float> vals((size_t)5 * ncb * 64 * 8);
+        for (int ks = 0; ks < 5; ++ks)
+          for (int cb = 0; cb < ncb; ++cb)
+            for (int lane = 0; lane < 64; ++lane)
+              for (int t = 0; t < 8; ++t) {
+                const int k = ks * 32 + 8 * (lane / 16) + t, n = cb * 16 + lane % 16;
+                vals[(((size_t)ks * ncb + cb) * 64 + lane) * 8 + t] =
+                    k < ND1 ? sb * (float)beta[(size_t)k * ND1 + n] : 0.f;
+              }
+        float* dvals = nullptr;
+        rc = upload((void**)&dvals, vals.data(), vals.size() * sizeof(float));
+        if (rc == FLARE_OK) {
+          hipError_t e = hipMalloc((void**)&m->W8[b], (size_t)5 * ncb * 2 * 64 * sizeof(uint64_t));
+          if (e == hipSuccess) {
+            make_fp8_fragments(dvals, 5 * ncb, m->W8[b]);
+            e = hipDeviceSynchronize();
+          }
+          (void)hipFree(dvals);
+          if (e != hipSuccess) {
+            set_error(std::string("fp8 model: ") + hipGetErrorString(e));
+            rc = FLARE_E_HIP;
+          }
+        }
+      }
       if (rc != FLARE_OK) {
         flare_model_destroy(m);
         return rc;
@@ -300,6 +333,7 @@ int flare_model_destroy(flare_model* m) {
   for (int b = 0; b < 4; ++b) {
     if (m->Wf[b]) (void)hipFree(m->Wf[b]);
     if (m->Wb[b]) (void)hipFree(m->Wb[b]);
+    if (m->W8[b]) (void)hipFree(m->W8[b]);
   }
   for (int k = 0; k < 2; ++k)
     if (m->Lx[k]) (void)hipFree(m->Lx[k]);
@@ -379,9 +413,9 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   al((void**)&s->row_of, n * 4);
   al((void**)&s->nl_cnt, n * 4);
   al((void**)&s->nl_off, (n + 1) * 4);
-  al((void**)&s->w, 3 * n * 8);
+  al((void**)&s->w, n * 32);
   al((void**)&s->off, 3 * n * 8);
-  al((void**)&s->pos, 3 * n * 8);
+  al((void**)&s->pos, n * 32);
   al((void**)&s->nrm, n * 4);
   al((void**)&s->e_int, n * 4);
   al((void**)&s->v_int, n * 4);

@@ -67,6 +67,48 @@ __device__ inline int xcd_remap(int g, int n) {
   return start + k;
 }
 
+// ---- cross-lane moves on the DPP network (no LDS round trip) ----
+// xor-1 / xor-2 exchanges inside quads, then mirrors inside half rows and rows: after
+// sum16 every lane of a 16-lane row holds the row's total.
+__device__ __forceinline__ float dpp_f(float v, int ctrl_sel) {
+  int x = __float_as_int(v);
+  switch (ctrl_sel) {
+    case 0: x = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true); break;   // quad_perm 1,0,3,2
+    case 1: x = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true); break;   // quad_perm 2,3,0,1
+    case 2: x = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true); break;  // row_half_mirror
+    default: x = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true); break; // row_mirror
+  }
+  return __int_as_float(x);
+}
+__device__ __forceinline__ float xor1(float v) { return dpp_f(v, 0); }
+__device__ __forceinline__ float sum16(float v) {
+  v += dpp_f(v, 0);
+  v += dpp_f(v, 1);
+  v += dpp_f(v, 2);
+  v += dpp_f(v, 3);
+  return v;
+}
+__device__ __forceinline__ double xor1d(double v) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double dpp_d(double v, int sel) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __float_as_int(dpp_f(__int_as_float((int)(b & 0xffffffffLL)), sel));
+  const int hi = __float_as_int(dpp_f(__int_as_float((int)(b >> 32)), sel));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double sum16d(double v) {
+  v += dpp_d(v, 0);
+  v += dpp_d(v, 1);
+  v += dpp_d(v, 2);
+  v += dpp_d(v, 3);
+  return v;
+}
+
 // ---- device-wide exclusive scan (scan.hip) ----
 size_t scan_scratch_ints(long long n);
 // out[0..n] = exclusive prefix of in[0..n-1], out[n] = total. in and out may alias only

@@ -129,8 +129,8 @@ __global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict
                                                     const double* __restrict__ y,
                                                     const double* __restrict__ z,
                                                     const double* __restrict__ off,
-                                                    const double* __restrict__ w,
-                                                    double* __restrict__ pos, double lim2,
+                                                    const double4* __restrict__ w,
+                                                    double4* __restrict__ pos, double lim2,
                                                     int* __restrict__ status) {
   const int i = blockIdx.x * NTG + threadIdx.x;
   if (i >= n) return;
@@ -138,10 +138,9 @@ __global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict
   const double p0 = x[a] + off[i];
   const double p1 = y[a] + off[(size_t)n + i];
   const double p2 = z[a] + off[2 * (size_t)n + i];
-  pos[i] = p0;
-  pos[(size_t)n + i] = p1;
-  pos[2 * (size_t)n + i] = p2;
-  const double d0 = p0 - w[i], d1 = p1 - w[(size_t)n + i], d2 = p2 - w[2 * (size_t)n + i];
+  pos[i] = make_double4(p0, p1, p2, 0.0);
+  const double4 wi = w[i];
+  const double d0 = p0 - wi.x, d1 = p1 - wi.y, d2 = p2 - wi.z;
   const double d2s = d0 * d0 + d1 * d1 + d2 * d2;
   if (!(d2s <= lim2)) {
     if (!isfinite(d2s)) atomicOr(status, FLARE_FLAG_NONFINITE);
@@ -156,7 +155,7 @@ __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __res
                                               const int32_t* __restrict__ slot_s,
                                               const int* __restrict__ sp, const int* __restrict__ sid,
                                               const CellGrid* __restrict__ grids,
-                                              const double* __restrict__ pos, int n, double rc2,
+                                              const double4* __restrict__ pos, int n, double rc2,
                                               float4* __restrict__ geom) {
   const long long slot = (long long)blockIdx.x * NTG + threadIdx.x;
   if (slot >= nslots) return;
@@ -167,10 +166,10 @@ __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __res
     int sx, sy, sz;
     unpack_shift(slot_s[slot], sx, sy, sz);
     const CellGrid* g = grids + sid[i];
-    const size_t nn = (size_t)n;
-    const double dx = (pos[j] - pos[i]) + (double)sx * g->L[0];
-    const double dy = (pos[nn + j] - pos[nn + i]) + (double)sy * g->L[1];
-    const double dz = (pos[2 * nn + j] - pos[2 * nn + i]) + (double)sz * g->L[2];
+    const double4 pj = pos[j], pi = pos[i];
+    const double dx = (pj.x - pi.x) + (double)sx * g->L[0];
+    const double dy = (pj.y - pi.y) + (double)sy * g->L[1];
+    const double dz = (pj.z - pi.z) + (double)sz * g->L[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
       const float fx = (float)dx, fy = (float)dy, fz = (float)dz;

@@ -3,15 +3,17 @@
 //
 // A work-group owns a tile of 128 rows of one environment bucket (one central species,
 // one neighbour species, 144-component block):
-//   1. descriptors: two lanes per row accumulate the densities, form d~ (B2), |d~| and
-//      d = d~/|d~| straight into an LDS tile [128][148] (the padding makes the 16-byte
-//      fragment reads below conflict-free); nothing goes to HBM;
+//   1. descriptors: two lanes per row accumulate the densities and form d~ (B2) and |d~|
+//      straight into an LDS tile [128][148] (the padding makes the 16-byte fragment reads
+//      below conflict-free); nothing goes to HBM. The tile holds the unnormalised d~: the
+//      products are linear in the row, so the epilogue applies 1/|d~|^2 once;
 //   2. quadratic forms on the FP32 matrix cores (v_mfma_f32_16x16x4_f32): Y = D W for
 //      W = Sigma_b then W = beta_b, A fragments from LDS, B fragments streamed from L2 in a
 //      fragment-major copy of W (one contiguous 1 KB load per 16x16 block and K chunk);
-//   3. epilogue: V_i = Y_i . d_i, e_i = Y_i . d_i, g_i = (2/|d~_i|)(Y_i - e_i d_i) written
-//      into the tile and copied out coalesced as G[tile][k][row] (the layout the adjoint
-//      kernel reads with one lane pair per row).
+//   3. epilogue, with Y~ = d~ W: V_i = Y~ . d~ / |d~|^2 (or |Z~|^2/|d~|^2 in the split form),
+//      e_i = Y~ . d~ / |d~|^2, g_i = de_i/dd~_i = (2/|d~|^2)(Y~ - e_i d~) written into the
+//      tile and copied out coalesced as G[tile][k][row] (the layout the adjoint kernel
+//      reads with one lane pair per row).
 // Inside a 16-wide K chunk, k-step t of lane group q uses k = 4q + t for A and B alike.
 #include "half.h"
 #include "state.h"
@@ -35,6 +37,8 @@ struct FusedArgs {
   int row0[4], row1[4];
   const float4* Wf[4];   // per bucket [part 2][kc 9][cb 9][lane 64]
   const uint4* Wb[4];    // split form: beta as [ks 5][cb 9][hi/lo 2][lane 64] x 8 bf16
+  const uint64_t* W8[4]; // FP8 split form: s_b beta as [ks 5][cb 9][hi/lo' 2][lane 64] x 8 e4m3
+  float bscale[4];       // FP8 split form: s_b per bucket (a power of two)
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
   float* G;              // [tiles][144][128]
   float* nrm;            // per atom
@@ -143,6 +147,107 @@ __device__ __forceinline__ void mfma_pass_bf16(const float* As, const uint4* __r
   }
 }
 
+// FP8 split form on v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3, 3 mantissa bits). Each row is
+// pre-scaled by a power of two s_r so that |s_r d~| < 16, and beta by s_b so that
+// |s_b beta| < 16. With x = s_r d~ = x_hi + x_lo and b = s_b beta = b_hi + b_lo, the
+// operands x_hi, x_lo' = fp8(16 x_lo), b_hi, b_lo' = fp8(16 b_lo) and 16 x_hi (exact: a
+// power-of-two multiple of an e4m3 value that stays below 448) let one accumulator hold
+//   (16 x_hi) b_hi + x_hi b_lo' + x_lo' b_hi  =  16 x b  minus the dropped 16 x_lo b_lo,
+// so Y~ = acc / (16 s_r s_b). Lane (m, q) supplies k = 32t + 8q .. +7 as 8 bytes.
+__device__ __forceinline__ long fp8x8(const float (&v)[8]) {
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
+  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], hi, true);
+  return (long)(((unsigned long)(unsigned int)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ void fp8_unpack(long w, float (&v)[8]) {
+  const int lo = (int)(w & 0xffffffffL), hi = (int)((unsigned long)w >> 32);
+  v[0] = __builtin_amdgcn_cvt_f32_fp8(lo, 0);
+  v[1] = __builtin_amdgcn_cvt_f32_fp8(lo, 1);
+  v[2] = __builtin_amdgcn_cvt_f32_fp8(lo, 2);
+  v[3] = __builtin_amdgcn_cvt_f32_fp8(lo, 3);
+  v[4] = __builtin_amdgcn_cvt_f32_fp8(hi, 0);
+  v[5] = __builtin_amdgcn_cvt_f32_fp8(hi, 1);
+  v[6] = __builtin_amdgcn_cvt_f32_fp8(hi, 2);
+  v[7] = __builtin_amdgcn_cvt_f32_fp8(hi, 3);
+}
+// split of 8 already-scaled values into (16 x_hi, x_hi, x_lo')
+__device__ __forceinline__ void split8_fp8(const float (&x)[8], long& hi16, long& hi, long& lo) {
+  hi = fp8x8(x);
+  float h[8], r[8], h16[8];
+  fp8_unpack(hi, h);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    r[t] = 16.f * (x[t] - h[t]);
+    h16[t] = 16.f * h[t];
+  }
+  lo = fp8x8(r);
+  hi16 = fp8x8(h16);
+}
+
+__device__ __forceinline__ void mfma_pass_fp8(const float* As, const float* rs, const uint64_t* __restrict__ W,
+                                              int wave, int lane, f4 (&acc)[2][NCB]) {
+  const int l16 = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const uint64_t* Wp = W + lane;
+  float sr[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) sr[i] = rs[wave * 32 + i * 16 + l16];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) {
+    long a16[2], ah[2], al[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      float x[8];
+      if (ks == NKS - 1 && grp >= 2) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = 0.f;
+      } else {
+        const float* p = &As[(wave * 32 + i * 16 + l16) * AS + ks * 32 + 8 * grp];
+        const float4 x0 = *reinterpret_cast<const float4*>(p);
+        const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+        x[0] = x0.x * sr[i]; x[1] = x0.y * sr[i]; x[2] = x0.z * sr[i]; x[3] = x0.w * sr[i];
+        x[4] = x1.x * sr[i]; x[5] = x1.y * sr[i]; x[6] = x1.z * sr[i]; x[7] = x1.w * sr[i];
+      }
+      split8_fp8(x, a16[i], ah[i], al[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+      const long bh = (long)Wp[((ks * NCB + j) * 2 + 0) * 64];
+      const long bl = (long)Wp[((ks * NCB + j) * 2 + 1) * 64];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a16[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(al[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// FP8 fragments of beta for the split form: vals [groups][lane 64][8] (already scaled by
+// s_b) -> out [groups][hi, lo' 2][lane 64], hi = fp8(v), lo' = fp8(16 (v - hi)); the same
+// conversion instruction as the row operands, so both sides share one number format.
+__global__ __launch_bounds__(256) void k_fp8_fragments(const float* __restrict__ vals, int groups,
+                                                       uint64_t* __restrict__ out) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= groups * 64) return;
+  const int g = idx >> 6, lane = idx & 63;
+  float x[8], h[8], r[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) x[t] = vals[(size_t)idx * 8 + t];
+  const long hi = fp8x8(x);
+  fp8_unpack(hi, h);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) r[t] = 16.f * (x[t] - h[t]);
+  out[((size_t)g * 2 + 0) * 64 + lane] = (uint64_t)hi;
+  out[((size_t)g * 2 + 1) * 64 + lane] = (uint64_t)fp8x8(r);
+}
+
 // Sum of squares of the 8 rows a lane touches (Z = D L, V = |z|^2), accumulated in FP64.
 __device__ __forceinline__ void row_sumsq(const f4 (&acc)[2][NCB], float (&out)[2][4]) {
 #pragma unroll
@@ -155,9 +260,7 @@ __device__ __forceinline__ void row_sumsq(const f4 (&acc)[2][NCB], float (&out)[
         const double z = (double)acc[i][j][r];
         s += z * z;
       }
-#pragma unroll
-      for (int m = 1; m < 16; m <<= 1) s += __shfl_xor(s, m, 64);
-      out[i][r] = (float)s;
+      out[i][r] = (float)sum16d(s);
     }
 }
 
@@ -173,9 +276,7 @@ __device__ __forceinline__ void row_dots(const float* As, const f4 (&acc)[2][NCB
       float s = 0.f;
 #pragma unroll
       for (int j = 0; j < NCB; ++j) s += acc[i][j][r] * d[j * 16];
-#pragma unroll
-      for (int m = 1; m < 16; m <<= 1) s += __shfl_xor(s, m, 64);
-      out[i][r] = s;
+      out[i][r] = sum16(s);
     }
 }
 
@@ -183,15 +284,20 @@ template <int PREC>
 __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) float As[FR * AS];
   __shared__ float nrm_s[FR];
+  __shared__ float rsc_s[FR];     // FP8 split form: power-of-two row scale s_r
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const float4* Wb = a.Wf[0];
   const uint4* Wh = a.Wb[0];
+  const uint64_t* W8 = a.W8[0];
+  float bsc = a.bscale[0];
 #pragma unroll
   for (int k = 1; k < 4; ++k)
     if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k]) {
       Wb = a.Wf[k];
       Wh = a.Wb[k];
+      W8 = a.W8[k];
+      bsc = a.bscale[k];
     }
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 
@@ -205,16 +311,10 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
     if (i >= 0) accumulate_half(a.v, row0 + rl, h, c);
+    // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
+    // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
     double nrm2 = 0.0;    // |d~|^2 accumulated in FP64
-#pragma unroll
-    for (int na = 0; na < NR; ++na)
-#pragma unroll
-      for (int nb = na; nb < NR; ++nb) {
-        const float4 d = b2_half(c[na], c[nb], h);
-        nrm2 += (double)(d.x * d.x + d.y * d.y) + (double)(d.z * d.z + d.w * d.w);
-      }
-    const float nrm = (float)sqrt(nrm2);
-    const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+    float amax = 0.f;     // max |d~_k| (FP8 row scale)
     float* rowp = As + rl * AS + 2 * h;
     int k = 0;
 #pragma unroll
@@ -222,10 +322,19 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
 #pragma unroll
       for (int nb = na; nb < NR; ++nb) {
         const float4 d = b2_half(c[na], c[nb], h);
-        *reinterpret_cast<float2*>(rowp + 4 * k) =
-            h ? make_float2(d.z * inv, d.w * inv) : make_float2(d.x * inv, d.y * inv);
+        nrm2 += (double)(d.x * d.x + d.y * d.y) + (double)(d.z * d.z + d.w * d.w);
+        const float2 mine = h ? make_float2(d.z, d.w) : make_float2(d.x, d.y);
+        if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
+        *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
         ++k;
       }
+    const float nrm = (float)sqrt(nrm2);
+    if (PREC == FLARE_FP8_SPLIT) {
+      amax = fmaxf(amax, xor1(amax));
+      int ex = 0;
+      frexpf(amax > 0.f ? amax : 1.f, &ex);      // amax = f 2^ex, f in [0.5, 1)
+      if (h == 0) rsc_s[rl] = ldexpf(1.f, 4 - ex);   // |s_r d~| < 16
+    }
     if (h == 0) {
       nrm_s[rl] = nrm;
       if (i >= 0) a.nrm[i] = nrm;
@@ -235,7 +344,8 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   if (a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
       const int r = idx / ND1, k = idx % ND1;
-      a.D_out[(size_t)(row0 + r) * ND1 + k] = As[r * AS + k];
+      const float nv = nrm_s[r];
+      a.D_out[(size_t)(row0 + r) * ND1 + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
     }
   }
 
@@ -244,7 +354,7 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   f4 acc[2][NCB];
   float dots[2][4];
   if (a.mode & 2) {
-    if (PREC == FLARE_BF16_SPLIT) {
+    if (PREC != FLARE_FP32) {
       mfma_pass<1, true>(As, Wb, wave, lane, acc);   // Z = D L on FP32 cores, L lower-triangular
       row_sumsq(acc, dots);
     } else {
@@ -256,14 +366,30 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int atom = a.aor[row0 + wave * 32 + i * 16 + 4 * grp + r];
-          if (atom >= 0) a.v_int[atom] = dots[i][r];
+          const int rl = wave * 32 + i * 16 + 4 * grp + r;
+          const int atom = a.aor[row0 + rl];
+          const float nv = nrm_s[rl];
+          if (atom >= 0) a.v_int[atom] = nv > 0.f ? dots[i][r] / (nv * nv) : 0.f;
         }
     }
   }
   if (a.mode & 1) {
-    if (PREC == FLARE_BF16_SPLIT) mfma_pass_bf16<0>(As, Wh, wave, lane, acc);
-    else mfma_pass<0>(As, Wb, wave, lane, acc);
+    if (PREC == FLARE_BF16_SPLIT) {
+      mfma_pass_bf16<0>(As, Wh, wave, lane, acc);
+    } else if (PREC == FLARE_FP8_SPLIT) {
+      mfma_pass_fp8(As, rsc_s, W8, wave, lane, acc);
+      // undo the power-of-two scales: Y~ = acc / (16 s_r s_b), exact
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float inv = 1.f / (16.f * rsc_s[wave * 32 + i * 16 + 4 * grp + r] * bsc);
+#pragma unroll
+          for (int j = 0; j < NCB; ++j) acc[i][j][r] *= inv;
+        }
+    } else {
+      mfma_pass<0>(As, Wb, wave, lane, acc);
+    }
     row_dots(As, acc, wave, lane, dots);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -271,13 +397,15 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int rl = wave * 32 + i * 16 + 4 * grp + r;
         const int atom = a.aor[row0 + rl];
-        if (l16 == 0 && atom >= 0) a.e_int[atom] = dots[i][r];
         const float nv = nrm_s[rl];
-        const float s2 = nv > 0.f ? 2.f / nv : 0.f;
+        const float inv2 = nv > 0.f ? 1.f / (nv * nv) : 0.f;
+        const float e = dots[i][r] * inv2;        // e = Y~ . d~ / |d~|^2
+        if (l16 == 0 && atom >= 0) a.e_int[atom] = e;
+        const float s2 = 2.f * inv2;              // g = (2/|d~|^2) (Y~ - e d~)
         float* d = As + rl * AS + l16;
         // each lane reads its own d-elements before overwriting them with g
 #pragma unroll
-        for (int j = 0; j < NCB; ++j) d[j * 16] = s2 * (acc[i][j][r] - dots[i][r] * d[j * 16]);
+        for (int j = 0; j < NCB; ++j) d[j * 16] = s2 * (acc[i][j][r] - e * d[j * 16]);
       }
     __syncthreads();
     float* G = a.G + (size_t)tile * ND1 * FR;
@@ -291,6 +419,10 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
 
 }  // namespace
 
+void make_fp8_fragments(const float* vals, int groups, uint64_t* out) {
+  k_fp8_fragments<<<(groups * 64 + 255) / 256, 256>>>(vals, groups, out);
+}
+
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   if (s->rows1 == 0 || (!mode && !d_out)) return;
   FusedArgs a{};
@@ -303,6 +435,8 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     a.row1[k] = s->bucket_row0[k] + padded;
     a.Wf[k] = reinterpret_cast<const float4*>(s->model->Wf[k]);
     a.Wb[k] = reinterpret_cast<const uint4*>(s->model->Wb[k]);
+    a.W8[k] = s->model->W8[k];
+    a.bscale[k] = s->model->beta_scale[k];
   }
   a.mode = mode;
   a.G = s->G1.p;
@@ -312,6 +446,8 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   a.D_out = d_out;
   if (s->model->precision == FLARE_BF16_SPLIT)
     k_fused144<FLARE_BF16_SPLIT><<<s->rows1 / FR, FT, 0, s->stream>>>(a);
+  else if (s->model->precision == FLARE_FP8_SPLIT)
+    k_fused144<FLARE_FP8_SPLIT><<<s->rows1 / FR, FT, 0, s->stream>>>(a);
   else
     k_fused144<FLARE_FP32><<<s->rows1 / FR, FT, 0, s->stream>>>(a);
 }

@@ -14,11 +14,11 @@ constexpr int NQ = 8;   // (l, m) indices per lane
 // c[n][q] += R_n Y_{8h+q} over the neighbours of row R inside the cutoff. All rows of a
 // wave share one slice, so the trip count is uniform across the wave.
 __device__ __forceinline__ void accumulate_half(const SlotView& v, int Rw, int h, float (*c)[NQ]) {
-  const int len = slice_len(v, Rw);
-  for (int k = 0; k < len; ++k) {
+  SLOT_STREAM_BEGIN(v, Rw);
+  for (int k = 0; k < ss_len; ++k) {
     PairGeom pg;
     int sp;
-    if (!slot_geom(v, Rw, k, pg, sp)) continue;
+    if (!unpack_geom(SLOT_STREAM_NEXT(k), pg, sp)) continue;
     float R[NR], Y[NLM];
     radial(pg.r, v.rc, R);
     sph_harm(pg.ux, pg.uy, pg.uz, Y);
@@ -38,9 +38,9 @@ __device__ __forceinline__ float4 b2_half(const float* ca, const float* cb, int 
   const float v0 = ca[0] * cb[0];
   const float v1 = ca[1] * cb[1] + ca[2] * cb[2] + ca[3] * cb[3];
   const float v2 = ca[4] * cb[4] + ca[5] * cb[5] + ca[6] * cb[6] + ca[7] * cb[7];
-  const float p0 = __shfl_xor(v0, 1, 64);
-  const float p1 = __shfl_xor(v1, 1, 64);
-  const float p2 = __shfl_xor(v2, 1, 64);
+  const float p0 = xor1(v0);
+  const float p1 = xor1(v1);
+  const float p2 = xor1(v2);
   // (u*) = values of lane h = 0, (w*) = values of lane h = 1
   const float u0 = h ? p0 : v0, u1 = h ? p1 : v1, u2 = h ? p2 : v2;
   const float w0 = h ? v0 : p0, w1 = h ? v1 : p1, w2 = h ? v2 : p2;

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) void k_to_internal(int n, const int* __restrict
                                                     const int32_t* __restrict__ species,
                                                     int* __restrict__ perm, int* __restrict__ sp,
                                                     int* __restrict__ sid, int* __restrict__ bin,
-                                                    double* __restrict__ w,
+                                                    double4* __restrict__ w,
                                                     double* __restrict__ off) {
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
@@ -117,10 +117,8 @@ __global__ __launch_bounds__(NT) void k_to_internal(int n, const int* __restrict
   sp[i] = (s < 0 || s >= NS) ? 0 : s;
   sid[i] = o_sid[a];
   bin[i] = o_bin[a];
-  for (int ax = 0; ax < 3; ++ax) {
-    w[(size_t)ax * n + i] = o_w[(size_t)ax * n + a];
-    off[(size_t)ax * n + i] = o_off[(size_t)ax * n + a];
-  }
+  w[i] = make_double4(o_w[a], o_w[(size_t)n + a], o_w[2 * (size_t)n + a], 0.0);
+  for (int ax = 0; ax < 3; ++ax) off[(size_t)ax * n + i] = o_off[(size_t)ax * n + a];
 }
 
 // Per-wave ballot counts of each bucket, combined per block into blk[b * nblk + block].
@@ -141,7 +139,7 @@ template <bool FILL>
 __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict__ grids,
                                               const int* __restrict__ sid,
                                               const int* __restrict__ bin,
-                                              const double* __restrict__ w,
+                                              const double4* __restrict__ w,
                                               const int* __restrict__ sp,
                                               const int* __restrict__ bstart, double rl2,
                                               int* __restrict__ cnt_out,
@@ -158,7 +156,8 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
     const int bx = local % g.nb[0];
     const int by = (local / g.nb[0]) % g.nb[1];
     const int bz = local / (g.nb[0] * g.nb[1]);
-    const double wx = w[i], wy = w[(size_t)n + i], wz = w[2 * (size_t)n + i];
+    const double4 wi = w[i];
+    const double wx = wi.x, wy = wi.y, wz = wi.z;
     int cnt = 0, mask = 0;
     long long o = FILL ? nl_off[i] : 0;
     for (int oz = -g.K[2]; oz <= g.K[2]; ++oz) {
@@ -180,9 +179,10 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
           const int j0 = bstart[bb], j1 = bstart[bb + 1];
           const bool zero_shift = (sx == 0) && (sy == 0) && (sz == 0);
           for (int j = j0; j < j1; ++j) {
-            const double dx = (w[j] - wx) + tx;
-            const double dy = (w[(size_t)n + j] - wy) + ty;
-            const double dz = (w[2 * (size_t)n + j] - wz) + tz;
+            const double4 wj = w[j];
+            const double dx = (wj.x - wx) + tx;
+            const double dy = (wj.y - wy) + ty;
+            const double dz = (wj.z - wz) + tz;
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < rl2 && !(zero_shift && j == i)) {
               if (FILL) {

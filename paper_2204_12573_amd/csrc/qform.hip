@@ -6,8 +6,8 @@
 // beta_b / Sigma_b are the central species' matrices restricted to the bucket's
 // descriptor block (144 x 144 for single-species environments, 544 x 544 otherwise).
 //
-// Tiling: a work-group of 4 waves owns 128 rows; each wave owns 32 rows (two 16-row
-// blocks) x CB 16-column blocks, accumulated by v_mfma_f32_16x16x4_f32. K advances in
+// Tiling: a work-group of 4 waves owns 64 RB rows; each wave owns RB 16-row blocks x CB
+// 16-column blocks, accumulated by v_mfma_f32_16x16x4_f32. K advances in
 // chunks of 16 staged in LDS (double-buffered). Inside a chunk the four k-steps are
 // interleaved so that each lane reads its four k-values of A and of B with one
 // 128-bit LDS load: k-step t, lane group g uses k = 4g + t (the same map for A and B,
@@ -23,8 +23,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int NTQ = 256;
 constexpr int KC = 16;          // K chunk
 constexpr int LDSW = KC + 4;    // padded LDS row (floats)
-constexpr int RB = 2;           // 16-row blocks per wave
-constexpr int TM = 4 * RB * 16; // rows per work-group (128)
+
 
 struct QArgs {
   const float* D;        // [rows][KD]
@@ -44,8 +43,9 @@ struct QArgs {
   const float* W[4];     // [(parts)*KD][KD] row n = column n of [beta | Sigma]
 };
 
-template <int KD, int CB, bool FUSED>
+template <int KD, int CB, bool FUSED, int RB>
 __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
+  constexpr int TM = 4 * RB * 16;              // rows per work-group
   constexpr int NC = CB * 16;                  // columns per work-group
   constexpr int NCHUNK = KD / KC;
   static_assert(KD % KC == 0, "K must be a multiple of the chunk");
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
     float4 a[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
-      a[i] = *reinterpret_cast<const float4*>(&As[buf][(wave * 32 + i * 16 + l16) * LDSW + 4 * grp]);
+      a[i] = *reinterpret_cast<const float4*>(&As[buf][(wave * RB * 16 + i * 16 + l16) * LDSW + 4 * grp]);
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
       const float4 bv = *reinterpret_cast<const float4*>(&Bs[buf][(j * 16 + l16) * LDSW + 4 * grp]);
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
     float pe[4] = {0.f, 0.f, 0.f, 0.f}, pv[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wave * 32 + i * 16 + 4 * grp + r;
+      const int row = row0 + wave * RB * 16 + i * 16 + 4 * grp + r;
       const float* drow = D + (size_t)row * KD;
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
@@ -154,15 +154,12 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-#pragma unroll
-      for (int m = 1; m < 16; m <<= 1) {
-        pe[r] += __shfl_xor(pe[r], m, 64);
-        pv[r] += __shfl_xor(pv[r], m, 64);
-      }
+      pe[r] = sum16(pe[r]);
+      pv[r] = sum16(pv[r]);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wave * 32 + i * 16 + 4 * grp + r;
+      const int row = row0 + wave * RB * 16 + i * 16 + 4 * grp + r;
       const int atom = q.aor[row];
       if (FUSED) {
         if (atom >= 0 && l16 == 0) {
@@ -258,7 +255,7 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   }
   // split form: the Sigma columns come from L (V = |d L|^2); with both parts the kernel
   // reads the beta rows of W then continues into L through a second launch
-  q.sumsq = m->precision == FLARE_BF16_SPLIT ? 1 : 0;
+  q.sumsq = m->precision != FLARE_FP32 ? 1 : 0;
   q.D = s->Dx.p;
   q.G = s->Gx.p;
   q.aor = s->atom_of_rowx.p;
@@ -271,15 +268,15 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
     if (mode & 1) {
       QArgs qe = q;
       qe.mode = 1;
-      k_qform<ND, 17, false><<<dim3(rows / TM, 2), NTQ, 0, s->stream>>>(qe);
+      k_qform<ND, 17, false, 1><<<dim3(rows / 64, 2), NTQ, 0, s->stream>>>(qe);
     }
     QArgs qv = q;
     qv.mode = 2;
     qv.pbase = (mode & 1) ? 2 : 0;
     for (int k = 0; k < 2; ++k) qv.W[k] = m->Lx[k];
-    k_qform<ND, 17, false><<<dim3(rows / TM, 2), NTQ, 0, s->stream>>>(qv);
+    k_qform<ND, 17, false, 1><<<dim3(rows / 64, 2), NTQ, 0, s->stream>>>(qv);
   } else {
-    k_qform<ND, 17, false><<<dim3(rows / TM, ntiles), NTQ, 0, s->stream>>>(q);
+    k_qform<ND, 17, false, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
   }
   k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
                                                         s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int);

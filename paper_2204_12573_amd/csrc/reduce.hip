@@ -11,14 +11,15 @@ namespace {
 constexpr int NT = 256;
 
 // Caller-order outputs, one thread per row. Forces by gathering the per-pair adjoint
-// terms over the row's slots: F_i = sum_k (w_slot(i,k) - w_rev(slot(i,k))), in slot order
-// (deterministic; padding slots hold w = 0 and point at themselves).
+// terms over the row's slots: F_i = sum_k (w_slot(i,k) - w_rev(slot(i,k))) for the row's
+// own pairs k < count, in slot order (deterministic).
 __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* __restrict__ aor1,
                                                 const int* __restrict__ aorx,
                                                 const int* __restrict__ slice_base,
                                                 const float4* __restrict__ w,
                                                 const int* __restrict__ slot_rev,
                                                 const int* __restrict__ perm,
+                                                const int* __restrict__ cnt,
                                                 const int* __restrict__ sid,
                                                 const double* __restrict__ cell_scale,
                                                 const float* __restrict__ e_int,
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* 
   const int a = perm[i];
   if (e_atom) e_atom[a] = e_int[i];
   if (fx) {
-    const int base = slice_base[R >> 5], len = slice_base[(R >> 5) + 1] - base;
+    const int base = slice_base[R >> 5], len = cnt[i];   // the row's own pairs (no padding)
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int k = 0; k < len; ++k) {
       const int slot = (base + k) * 32 + (R & 31);
@@ -194,7 +195,7 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
   if (rows > 0)
     k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
                                                          s->slice_base.p, s->w_slot.p, s->slot_rev.p, s->perm,
-                                                         s->sid, cell_scale, s->e_int, s->v_int, e_atom, fx, fy, fz, var_atom,
+                                                         s->nl_cnt, s->sid, cell_scale, s->e_int, s->v_int, e_atom, fx, fy, fz, var_atom,
                                                          sigma_atom);
   k_outputs_empty<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->bucket, s->perm, e_atom, fx, fy, fz, var_atom,
                                                            sigma_atom);

@@ -32,7 +32,7 @@ struct DevBuf {
 // Read-only view of the per-step pair data, passed to kernels by value.
 struct PairView {
   int n;                              // atoms
-  const double* pos;                  // [3][n] internal positions
+  const double4* pos;                 // [n] internal positions
   const int* sp;                      // species
   const int* sid;                     // cell of each atom
   const CellGrid* grids;              // per cell
@@ -92,6 +92,11 @@ struct flare_model {
   // [K step 5][column block 9][hi/lo 2][lane 64] x 8 bf16 (K padded 144 -> 160). In this
   // form the Sigma part of Wf holds the Cholesky factor L of Sigma (Sigma = L L^T).
   uint16_t* Wb[4] = {};
+  // FP8 split form (precision FLARE_FP8_SPLIT): s_b * beta as [K step 5][column block 9]
+  // [hi, lo' 2][lane 64] x 8 OCP e4m3 bytes, converted on the device by the same
+  // instruction the kernel uses for d; lo' = fp8(16 (x - hi)). s_b = 2^k keeps |s_b beta| <= 16.
+  uint64_t* W8[4] = {};
+  float beta_scale[4] = {1.f, 1.f, 1.f, 1.f};
   // Mixed buckets in the split form: L of the 544 x 544 Sigma_s, [544][544] FP32, stored
   // like W (row n = column n of L).
   float* Lx[2] = {};
@@ -136,9 +141,9 @@ struct flare_state {
   int* row_of = nullptr;     // row of each internal atom inside its width class (-1: none)
   int* nl_cnt = nullptr;
   int* nl_off = nullptr;     // [max_atoms + 1]
-  double* w = nullptr;       // [3][N] wrapped positions at the list build
+  double4* w = nullptr;      // [N] wrapped positions at the list build (x, y, z, 0)
   double* off = nullptr;     // [3][N] image offset: internal position = x + off
-  double* pos = nullptr;     // [3][N] internal positions of the current step
+  double4* pos = nullptr;    // [N] internal positions of the current step (x, y, z, 0)
   float* nrm = nullptr;      // |d~| per internal atom
   float* e_int = nullptr;
   float* v_int = nullptr;
@@ -215,4 +220,6 @@ void md_second(flare_state* s, double* vx, double* vy, double* vz, const float* 
                const float* fy, const float* fz, const int32_t* species, double inv_m0,
                double inv_m1, double dt);
 void set_error(const std::string& msg);
+// FP8 fragments from FP32 values in fragment order [groups][lane 64][8] (fused.hip)
+void make_fp8_fragments(const float* vals, int groups, uint64_t* out);
 }  // namespace flare

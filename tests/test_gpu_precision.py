@@ -1,6 +1,16 @@
-"""Precision form: the BF16 split quadratic forms (beta = beta_hi + beta_lo and
-d = d_hi + d_lo on BF16 matrix cores, FP32 accumulation; variance as |L^T d|^2 with an
-FP64 Cholesky factor, summed in FP64) against the FP64 oracle, beside plain FP32."""
+"""Precision forms: the split quadratic forms (beta = beta_hi + beta_lo and
+d = d_hi + d_lo on BF16 or FP8-e4m3 matrix cores, FP32 accumulation; variance as
+|L^T d|^2 with an FP64 Cholesky factor, summed in FP64) against the FP64 oracle, beside
+plain FP32.
+
+Tolerances. BF16 has 8 significant bits: each split operand keeps ~16 bits and the
+dropped lo*lo product is ~2^-16 of a term, so E and F land near 1e-5 of their scale;
+1e-4 leaves room for the sum over 144^2 terms. FP8 e4m3 has 4 significant bits: with
+power-of-two scales keeping every operand normal, each term 16 x b is represented to
+3 * 2^-8 of |x||b| (two rounded lo' parts and the dropped lo*lo), so the worst case is
+about 1.2e-2 of sum_kl |d_k||beta_kl||d_l| / |d|^2; random rounding errors average down
+and the test asks for 1e-2 of the largest energy and force. The variance of both split
+forms never touches the narrow formats."""
 import numpy as np
 import pytest
 
@@ -12,8 +22,11 @@ from .gpu_util import gpu_eval, rel_max, rel_vec
 
 pytestmark = pytest.mark.gpu
 
-SPLIT_TOL_E = 1e-4     # energies, forces of the split form (BF16 x 3 products)
-SPLIT_TOL_S = 1e-5     # sigma of the split form (sum of squares, no cancellation)
+SPLIT_TOL_E = 1e-4     # energies, forces of the BF16 split form (BF16 x 3 products)
+SPLIT_TOL_S = 1e-5     # sigma of the split forms (sum of squares, no cancellation)
+FP8_TOL_E = 1e-2       # energies, forces of the FP8 split form (e4m3 x 3 products)
+TOL_E = {Bd.BF16_SPLIT: SPLIT_TOL_E, Bd.FP8_SPLIT: FP8_TOL_E}
+PREC = [pytest.param(Bd.BF16_SPLIT, id="bf16"), pytest.param(Bd.FP8_SPLIT, id="fp8")]
 
 
 def _errs(res, ref):
@@ -21,8 +34,9 @@ def _errs(res, ref):
             "var_pointwise": float(np.max(np.abs(res["var"] - ref.v) / np.abs(ref.v)))}
 
 
+@pytest.mark.parametrize("prec", PREC)
 @pytest.mark.parametrize("case", ["tiny", "cells"])
-def test_split_form_random_models(case):
+def test_split_form_random_models(case, prec):
     beta, sigma = S.random_model(DEFAULT.n_desc)
     if case == "tiny":
         st = S.config_tiny()
@@ -32,14 +46,14 @@ def test_split_form_random_models(case):
         b = S.config_cells(n_cells=6, seed=3)
         cells = [(b.structure(k), b.offsets[k], b.offsets[k + 1]) for k in range(6)]
         pos, species, boxes, offsets = b.pos, b.species, b.boxes, b.offsets
-    print(f"case: split form {case}", flush=True)
-    res = gpu_eval(pos, species, boxes, beta, sigma, offsets=offsets, precision=Bd.BF16_SPLIT)
+    print(f"case: split form {case} precision {prec}", flush=True)
+    res = gpu_eval(pos, species, boxes, beta, sigma, offsets=offsets, precision=prec)
     for st, lo, hi in cells:
         ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
         sub = {k: res[k][lo:hi] for k in ["e", "f", "sigma", "var"]}
         errs = _errs(sub, ref)
         print(errs)
-        assert errs["e"] <= SPLIT_TOL_E and errs["f"] <= SPLIT_TOL_E and errs["sigma"] <= SPLIT_TOL_S
+        assert errs["e"] <= TOL_E[prec] and errs["f"] <= TOL_E[prec] and errs["sigma"] <= SPLIT_TOL_S
 
 
 def test_near_cancelling_variance():
@@ -54,20 +68,21 @@ def test_near_cancelling_variance():
     gamma = np.stack([sgp.gamma_mapped(d[(st.species == s)][::2], sigma2, noise) for s in (0, 1)])
     ref = oev.evaluate(st.pos, st.species, st.box, beta, gamma)
     out = {}
-    for name, prec in [("fp32", Bd.FP32), ("split", Bd.BF16_SPLIT)]:
+    for name, prec in [("fp32", Bd.FP32), ("split", Bd.BF16_SPLIT), ("fp8", Bd.FP8_SPLIT)]:
         res = gpu_eval(st.pos, st.species, st.box, beta, gamma, precision=prec)
         out[name] = float(np.max(np.abs(res["var"] - ref.v) / ref.v))
     print("pointwise relative error of V:", out, "V/sigma^2 range:", ref.v.min() / sigma2, ref.v.max() / sigma2)
     assert ref.v.min() < 1e-3 * sigma2              # genuinely near-cancelling
-    assert out["split"] <= 2e-4
+    assert out["split"] <= 2e-4 and out["fp8"] <= 2e-4
     assert out["split"] < out["fp32"] / 5
 
 
-def test_split_form_large_sample():
+@pytest.mark.parametrize("prec", PREC)
+def test_split_form_large_sample(prec):
     st = S.config_large()
     beta, sigma = S.random_model(DEFAULT.n_desc)
-    print("case: split form, large cell", flush=True)
-    res = gpu_eval(st.pos, st.species, st.box, beta, sigma, max_pairs=12 * st.n, precision=Bd.BF16_SPLIT)
+    print(f"case: split form, large cell, precision {prec}", flush=True)
+    res = gpu_eval(st.pos, st.species, st.box, beta, sigma, max_pairs=12 * st.n, precision=prec)
     rng = np.random.default_rng(21)
     tg = np.unique(rng.choice(st.n, 200, replace=False))
     ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma, targets=tg)
@@ -75,4 +90,4 @@ def test_split_form_large_sample():
     errs = {"e": rel_max(res["e"][tg], ref.e[rows]), "f": rel_vec(res["f"][tg], ref.f),
             "sigma": rel_max(res["sigma"][tg], ref.sigma[rows])}
     print(errs)
-    assert errs["e"] <= SPLIT_TOL_E and errs["f"] <= SPLIT_TOL_E and errs["sigma"] <= SPLIT_TOL_S
+    assert errs["e"] <= TOL_E[prec] and errs["f"] <= TOL_E[prec] and errs["sigma"] <= SPLIT_TOL_S
