@@ -174,6 +174,20 @@ int flare_energy_forces(flare_state* state, float* e_atom, float* fx, float* fy,
 int flare_forces(flare_state* state, const double* cell_scale, float* fx, float* fy, float* fz);
 
 /*
+ * Virial of each cell, the strain derivative behind the stress the model predicts
+ * (Section VI): under x -> (I + eps) x of positions and box every pair vector Delta
+ * becomes (I + eps) Delta, so
+ *   W_ab = -dE/deps_ab = -sum over list pairs (i, j) inside r_cut of Delta_a * (de_i/dDelta)_b
+ * (the stress is -W / volume). Uses the per-pair adjoint terms of the last force
+ * evaluation, which must be for the current positions (FLARE_E_STALE otherwise).
+ *   virial_struct  DEVICE FP64 [n_struct][9], row-major W_xx W_xy W_xz W_yx ... W_zz.
+ * Per-atom terms are summed in FP32 over each atom's pairs in list order, then in FP64
+ * over the cell's atoms in a fixed order (deterministic). Grows two internal buffers
+ * (36 bytes per atom) on the first call.
+ */
+int flare_virial(flare_state* state, double* virial_struct);
+
+/*
  * Variance and uncertainty only (Eq. 2), from the resident descriptors.
  *   var_atom, sigma_atom  DEVICE FP32 [n_atoms] (either may be NULL)
  *   sigma_max             DEVICE FP32 [n_struct] largest sigma per cell (NULL = skip)

@@ -26,6 +26,7 @@ class Result:
     f: np.ndarray | None      # forces [targets, 3]
     energy: float | None      # total energy (full evaluations only)
     c: np.ndarray | None = None
+    virial: np.ndarray | None = None   # W = -dE/d(strain), 3x3 (full evaluations, on request)
 
     def row_of(self, atoms):
         where = {int(a): k for k, a in enumerate(self.rows)}
@@ -33,7 +34,7 @@ class Result:
 
 
 def evaluate(pos, species, box, beta, gamma, h: Hyper = DEFAULT, targets=None,
-             want_forces=True, keep_c=False):
+             want_forces=True, keep_c=False, want_virial=False):
     pos = np.asarray(pos, np.float64)
     species = np.asarray(species)
     n = len(pos)
@@ -54,15 +55,21 @@ def evaluate(pos, species, box, beta, gamma, h: Hyper = DEFAULT, targets=None,
     e = model.energies(d, sp, beta)
     v = model.variances(d, sp, gamma)
     f = None
-    if want_forces:
+    vir = None
+    if want_forces or want_virial:
         g = model.energy_grad_dtilde(d, norm, sp, beta)
         where = -np.ones(n, np.int64)
         where[rows] = np.arange(len(rows))
-        f = forces.forces_explicit(n, species, i, j, delta, c, g, where, h,
-                                   targets=None if targets is None else tg)
+        if want_forces:
+            f = forces.forces_explicit(n, species, i, j, delta, c, g, where, h,
+                                       targets=None if targets is None else tg)
+        if want_virial:
+            if targets is not None:
+                raise ValueError("the virial is a whole-cell quantity")
+            vir = forces.virial_explicit(species, i, j, delta, c, g, where, h)
     energy = model.total_energy(e) if targets is None else None
     return Result(rows, d, norm, e, v, model.uncertainties(v), tg, f, energy,
-                  c if keep_c else None)
+                  c if keep_c else None, vir)
 
 
 def total_energy(pos, species, box, beta, h: Hyper = DEFAULT):

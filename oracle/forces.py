@@ -8,6 +8,11 @@
        h_p = de_i/dDelta_p          = g_i . dd~_i/dDelta_p
    then dE/dr_j += h_p and dE/dr_i -= h_p.
 2. Central finite differences of the total energy, step h (FP64).
+
+Virial (the stress the paper's model predicts, Section VI): under a homogeneous strain
+x -> (I + eps) x of positions and cell, every pair vector becomes (I + eps) Delta_p, so
+    W_ab = -dE/deps_ab = -sum_p h_p,a Delta_p,b
+(symmetric for a rotation-invariant energy). For a free cluster this is sum_i r_i,a F_i,b.
 """
 from __future__ import annotations
 
@@ -75,6 +80,32 @@ def forces_explicit(n_atoms, species, i, j, delta, c_rows, g_rows, where, h: Hyp
         np.add.at(grad_e, ii, -hp)
     f = -grad_e
     return f if targets is None else f[targets]
+
+
+def virial_explicit(species, i, j, delta, c_rows, g_rows, where, h: Hyper, chunk=512):
+    """W = -sum_p h_p (x) Delta_p over all list entries inside the cutoff (FP64 3x3)."""
+    r = np.sqrt((delta * delta).sum(-1))
+    keep = r < h.r_cut
+    i, j, delta = i[keep], j[keep], delta[keep]
+    w = np.zeros((3, 3))
+    for a in range(0, len(i), chunk):
+        ii, jj, dd = i[a:a + chunk], j[a:a + chunk], delta[a:a + chunk]
+        jac = descriptor_grad(c_rows[where[ii]], species[jj], dd, h)
+        hp = np.einsum("pk,pkx->px", g_rows[where[ii]], jac)
+        w -= hp.T @ dd
+    return w
+
+
+def virial_fd(energy_fn, pos, box, axis, step=1e-5):
+    """-dE/deps_aa by central differences of a uniaxial strain of positions and box."""
+    pos = np.array(pos, np.float64)
+    box = np.array(box, np.float64)
+    out = []
+    for sgn in (1.0, -1.0):
+        f = np.ones(3)
+        f[axis] += sgn * step
+        out.append(energy_fn(pos * f, box * f))
+    return -(out[0] - out[1]) / (2 * step)
 
 
 def forces_fd(energy_fn, pos, atoms=None, step=1e-4):

@@ -1,89 +1,19 @@
 // Forces by the reordered (adjoint) sum of the paper's Section V.B: the descriptor
-// gradient is never formed.
-//
-// With g_i = de_i/dd~_i from the quadratic-form pass and d~_{(a,b),l} = sum_m c_a c_b:
-//   u_{a,l,m} = de_i/dc_{a,l,m} = sum_b G^_{ab,l} c_{b,l,m},
-//               G^_{ab,l} = g_{(min,max),l}, doubled on the diagonal a = b.
-// For each listed pair p = (i, j, s) inside the cutoff, with Delta = r_j + s L - r_i:
-//   w_p = de_i/dDelta = sum_{n,l,m} u_{(s_j,n),l,m} grad_Delta [R_n(r) Y_lm(Delta/r)]
-//       = u^ sum_n (R_n' Z_n - R_n Zl_n / r) + (1/r) sum_lm A_lm grad P_lm(u^)
-//   with Z_n = sum_lm u_{n,lm} Y_lm, Zl_n = sum_lm l u_{n,lm} Y_lm, A_lm = sum_n u_{n,lm} R_n,
-// and w_p = 0 outside the cutoff. The densities c are recomputed from the pair list.
-// Forces follow without atomics: F_i = sum_{p in list(i)} (w_p - w_rev(p)), rev(p) being
-// the pair (j, i, -s) (reduce.hip), so they are deterministic and independent of how
-// cells are batched.
-#include "basis.h"
-#include "half.h"
-#include "pair.h"
+// gradient is never formed (the per-pair terms are in adjoint.h). The densities c are
+// recomputed from the pair list. Forces follow without atomics:
+// F_i = sum_{p in list(i)} (w_p - w_rev(p)), rev(p) being the pair (j, i, -s)
+// (reduce.hip), so they are deterministic and independent of how cells are batched.
+#include "adjoint.h"
 #include "state.h"
 
 namespace flare {
 namespace {
 
-constexpr int NT = 128;
 constexpr int NTX = 64;
 constexpr int TA = 256;   // threads of the 144-row adjoint kernel (128 rows, 2 lanes each)
 
-// sum_lm A_lm grad P_lm(x, y, z)
-__device__ __forceinline__ void poly_grad_dot(const float* A, float x, float y, float z,
-                                              float& gx, float& gy, float& gz) {
-  const float xx = x * x, yy = y * y, zz = z * z;
-  gx = kY1 * A[3] + kY2a * (y * A[4] + z * A[7]) + kY20 * (-2.f * x) * A[6] + 2.f * kY22 * x * A[8] +
-       6.f * kY33 * x * y * A[9] + kY32a * y * z * A[10] - 2.f * kY31 * x * y * A[11] -
-       6.f * kY30 * x * z * A[12] + kY31 * (4.f * zz - 3.f * xx - yy) * A[13] +
-       2.f * kY32b * x * z * A[14] + 3.f * kY33 * (xx - yy) * A[15];
-  gy = kY1 * A[1] + kY2a * (x * A[4] + z * A[5]) + kY20 * (-2.f * y) * A[6] - 2.f * kY22 * y * A[8] +
-       3.f * kY33 * (xx - yy) * A[9] + kY32a * x * z * A[10] + kY31 * (4.f * zz - xx - 3.f * yy) * A[11] -
-       6.f * kY30 * y * z * A[12] - 2.f * kY31 * x * y * A[13] - 2.f * kY32b * y * z * A[14] -
-       6.f * kY33 * x * y * A[15];
-  gz = kY1 * A[2] + kY2a * (y * A[5] + x * A[7]) + 4.f * kY20 * z * A[6] + kY32a * x * y * A[10] +
-       8.f * kY31 * y * z * A[11] + kY30 * (6.f * zz - 3.f * xx - 3.f * yy) * A[12] +
-       8.f * kY31 * x * z * A[13] + kY32b * (xx - yy) * A[14];
-}
-
-// w = de_i/dDelta for one pair from the adjoint densities u[n][lm] of the neighbour's
-// species (all 16 (l, m) in one thread).
-template <class U>
-__device__ __forceinline__ void pair_force(const PairGeom& pg, float rc, U u, float& wx, float& wy,
-                                           float& wz) {
-  float R[NR], dR[NR], Y[NLM];
-  radial_d(pg.r, rc, R, dR);
-  sph_harm(pg.ux, pg.uy, pg.uz, Y);
-  float A[NLM];
-#pragma unroll
-  for (int lm = 0; lm < NLM; ++lm) A[lm] = 0.f;
-  float s1 = 0.f;
-  const float inv_r = 1.f / pg.r;
-#pragma unroll
-  for (int n = 0; n < NR; ++n) {
-    float S[LMAX + 1] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int lm = 0; lm < NLM; ++lm) {
-      const float un = u(n, lm);
-      S[lm_l(lm)] += un * Y[lm];
-      A[lm] += un * R[n];
-    }
-    const float z = S[0] + S[1] + S[2] + S[3];
-    const float zl = S[1] + 2.f * S[2] + 3.f * S[3];
-    s1 += dR[n] * z - R[n] * zl * inv_r;
-  }
-  float gx, gy, gz;
-  poly_grad_dot(A, pg.ux, pg.uy, pg.uz, gx, gy, gz);
-  wx = pg.ux * s1 + gx * inv_r;
-  wy = pg.uy * s1 + gy * inv_r;
-  wz = pg.uz * s1 + gz * inv_r;
-}
-
-__device__ __forceinline__ int pair_index_same(int na, int nb) {
-  // packed index of (na <= nb) inside a single-species block, row-major
-  return na * NR - na * (na - 1) / 2 + (nb - na);
-}
-
-// Two lanes per row (see half.h). The densities and u = G^ c are formed split by (l, m):
-// lane h holds u[n][q] for (l, m) = 8h + q, whose q fall in three groups of constant l,
-// {0}, {1,2,3}, {4..7}, with l = (0,1,2) for h = 0 and (2,3,3) for h = 1. The two halves
-// are then exchanged so that each lane holds all of u, and the row's pairs are split
-// between the lanes (slots k = h, h + 2, ...): every pair term is evaluated once.
+// One row per lane pair (see half.h and adjoint.h), reading g from the tile-transposed
+// G[tile][k][128] written by the quadratic-form kernel.
 __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __restrict__ atom_of_row,
                                                    const float* __restrict__ G, float4* __restrict__ w) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -97,62 +27,8 @@ __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __rest
     for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
   const int R = tile * 128 + rl;
   accumulate_half(v, R, h, c);
-  // u = G^ c, group by group
-  const float* g = G + (size_t)tile * ND1 * 128 + rl;
-  const int lg0 = h ? 2 : 0, lg1 = h ? 3 : 1, lg2 = h ? 3 : 2;
-#pragma unroll
-  for (int grp = 0; grp < 3; ++grp) {
-    const int l = grp == 0 ? lg0 : (grp == 1 ? lg1 : lg2);
-    const int q0 = grp == 0 ? 0 : (grp == 1 ? 1 : 4);
-    const int q1 = grp == 0 ? 1 : (grp == 1 ? 4 : 8);
-    float gh[NR][NR];
-#pragma unroll
-    for (int na = 0; na < NR; ++na)
-#pragma unroll
-      for (int nb = na; nb < NR; ++nb) {
-        const float val = g[(size_t)(pair_index_same(na, nb) * 4 + l) * 128];
-        gh[na][nb] = na == nb ? 2.f * val : val;
-        gh[nb][na] = gh[na][nb];
-      }
-#pragma unroll
-    for (int q = q0; q < q1; ++q) {
-      float col[NR];
-#pragma unroll
-      for (int n = 0; n < NR; ++n) col[n] = c[n][q];
-#pragma unroll
-      for (int n = 0; n < NR; ++n) {
-        float acc = 0.f;
-#pragma unroll
-        for (int m = 0; m < NR; ++m) acc += gh[n][m] * col[m];
-        c[n][q] = acc;
-      }
-    }
-  }
-  // full u in both lanes of the row
-  float u[NR][NLM];
-#pragma unroll
-  for (int n = 0; n < NR; ++n)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const float other = xor1(c[n][q]);
-      u[n][q] = h ? other : c[n][q];
-      u[n][NQ + q] = h ? c[n][q] : other;
-    }
-  const int base = v.slice_base[R >> 5];
-  const int len = v.slice_base[(R >> 5) + 1] - base;
-  const float4* gp = v.geom + (size_t)base * 32 + (R & 31);
-  float4* wp = w + (size_t)base * 32 + (R & 31);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 gnext = h < len ? gp[(size_t)h * 32] : zero;
-  for (int k = h; k < len; k += 2) {
-    const float4 gk = gnext;
-    gnext = k + 2 < len ? gp[(size_t)(k + 2) * 32] : zero;
-    PairGeom pg;
-    int sp;
-    float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
-    wp[(size_t)k * 32] = make_float4(wx, wy, wz, 0.f);
-  }
+  u_transform_half(G + (size_t)tile * ND1 * 128 + rl, 128, h, c);
+  adjoint_pairs_half(v, R, h, c, w);
 }
 
 __global__ __launch_bounds__(NTX) void k_adjoint_mixed(SlotView v, int rows1, int rows,
@@ -227,9 +103,9 @@ __global__ __launch_bounds__(NTX) void k_adjoint_mixed(SlotView v, int rows1, in
 
 }  // namespace
 
-void compute_forces(flare_state* s) {
+void compute_forces(flare_state* s, bool rows144) {
   const SlotView v = slot_view(s);
-  {
+  if (rows144) {
     StageTimer tm(s, FLARE_T_FORCE1);
     if (s->rows1 > 0)
       k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->w_slot.p);

@@ -375,6 +375,8 @@ static void free_state(flare_state* s) {
   s->d_first_task.release();
   s->red_e.release();
   s->red_s.release();
+  s->vir_int.release();
+  s->red_w.release();
   s->slice_len.release();
   s->slice_base.release();
   s->slot_atom.release();
@@ -619,16 +621,22 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
   ARG(!want_f || (fx && fy && fz), "pass all three force arrays or none");
   const bool want_v = var_atom || sigma_atom;
   {
+    // with forces, the fused kernel also runs the adjoint of the 144-wide rows in place
     StageTimer tm(s, FLARE_T_QFORM1);
-    fused_quadratic_forms(s, 1 | (want_v ? 2 : 0), nullptr);
+    fused_quadratic_forms(s, 1 | (want_v ? 2 : 0) | (want_f ? 4 : 0), nullptr);
   }
   compute_descriptors_mixed(s);
   {
     StageTimer tm(s, FLARE_T_QFORMX);
     mixed_quadratic_forms(s, true, want_v);
   }
-  s->g_gen = s->pos_gen;
-  if (want_f) compute_forces(s);
+  if (want_f) {
+    compute_forces(s, false);
+    s->w_gen = s->pos_gen;
+    s->g_gen = -1;          // the 144-wide gradients stayed on chip
+  } else {
+    s->g_gen = s->pos_gen;
+  }
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, e_atom, fx, fy, fz, var_atom, sigma_atom);
@@ -642,14 +650,33 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
 int flare_forces(flare_state* s, const double* cell_scale, float* fx, float* fy, float* fz) {
   ARG(s, "null state");
   ARG(fx && fy && fz, "null force array");
-  if (!s->have_desc || s->g_gen != s->pos_gen) {
+  if (!s->have_desc || (s->w_gen != s->pos_gen && s->g_gen != s->pos_gen)) {
     set_error("flare_forces needs flare_energy_forces for the current positions");
     return FLARE_E_STALE;
   }
-  compute_forces(s);
+  if (s->w_gen != s->pos_gen) {
+    compute_forces(s, true);
+    s->w_gen = s->pos_gen;
+  }
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, nullptr, fx, fy, fz, nullptr, nullptr, cell_scale);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_virial(flare_state* s, double* virial_struct) {
+  ARG(s && virial_struct, "null pointer");
+  if (!s->have_desc || s->w_gen != s->pos_gen) {
+    set_error("flare_virial needs forces (flare_energy_forces or flare_forces) for the current positions");
+    return FLARE_E_STALE;
+  }
+  CHK(s->vir_int.reserve((size_t)9 * s->n_atoms + 9));
+  CHK(s->red_w.reserve((size_t)9 * s->tasks.size() + 9));
+  {
+    StageTimer tm(s, FLARE_T_OUT);
+    virial_cells(s, virial_struct);
   }
   CHK(hipGetLastError());
   return FLARE_OK;
@@ -723,6 +750,9 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
   if (m) {
     for (int k = 0; k < NBUCKET; ++k) b += (long long)2 * bucket_width(k) * bucket_width(k) * sizeof(float);
     b += 4LL * 2 * ND1 * ND1 * sizeof(float);
+    if (m->precision == FLARE_BF16_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * 8 * sizeof(uint16_t);
+    if (m->precision == FLARE_FP8_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * sizeof(uint64_t);
+    if (m->precision != FLARE_FP32) b += 2LL * ND * ND * sizeof(float);
   }
   if (s) {
     b += s->fixed_bytes;
@@ -732,7 +762,7 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
          s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
          s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
          s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_s.bytes() + s->slot_pair.bytes() +
-         s->slot_rev.bytes() + s->geom.bytes() + s->w_slot.bytes();
+         s->slot_rev.bytes() + s->geom.bytes() + s->w_slot.bytes() + s->vir_int.bytes() + s->red_w.bytes();
   }
   *bytes = b;
   return FLARE_OK;

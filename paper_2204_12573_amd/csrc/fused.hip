@@ -12,10 +12,14 @@
 //      fragment-major copy of W (one contiguous 1 KB load per 16x16 block and K chunk);
 //   3. epilogue, with Y~ = d~ W: V_i = Y~ . d~ / |d~|^2 (or |Z~|^2/|d~|^2 in the split form),
 //      e_i = Y~ . d~ / |d~|^2, g_i = de_i/dd~_i = (2/|d~|^2)(Y~ - e_i d~) written into the
-//      tile and copied out coalesced as G[tile][k][row] (the layout the adjoint kernel
-//      reads with one lane pair per row).
+//      tile, then either copied out coalesced as G[tile][k][row] (the layout the
+//      standalone adjoint kernel reads with one lane pair per row) or, when the forces
+//      are wanted now,
+//   4. adjoint in place: the lane pairs recompute their row's densities, form u = G^ c
+//      from the gradient tile in LDS and write the per-pair terms w (adjoint.h); g never
+//      goes to HBM.
 // Inside a 16-wide K chunk, k-step t of lane group q uses k = 4q + t for A and B alike.
-#include "half.h"
+#include "adjoint.h"
 #include "state.h"
 
 namespace flare {
@@ -40,7 +44,8 @@ struct FusedArgs {
   const uint64_t* W8[4]; // FP8 split form: s_b beta as [ks 5][cb 9][hi/lo' 2][lane 64] x 8 e4m3
   float bscale[4];       // FP8 split form: s_b per bucket (a power of two)
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
-  float* G;              // [tiles][144][128]
+  float* G;              // [tiles][144][128] (written when the forces are not formed here)
+  float4* w;             // per-slot adjoint terms (written when the forces are formed here)
   float* nrm;            // per atom
   float* e_int;
   float* v_int;
@@ -280,7 +285,7 @@ __device__ __forceinline__ void row_dots(const float* As, const f4 (&acc)[2][NCB
     }
 }
 
-template <int PREC>
+template <int PREC, bool FORCES>
 __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) float As[FR * AS];
   __shared__ float nrm_s[FR];
@@ -408,11 +413,25 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
         for (int j = 0; j < NCB; ++j) d[j * 16] = s2 * (acc[i][j][r] - e * d[j * 16]);
       }
     __syncthreads();
-    float* G = a.G + (size_t)tile * ND1 * FR;
-    for (int idx = t; idx < FR * ND1; idx += FT) {
-      const int k = idx >> 7, r = idx & (FR - 1);
-      G[idx] = As[r * AS + k];
-      (void)k;
+    if (FORCES) {
+      // ---- 4. adjoint: u = G^ c from the gradient tile, then the per-pair terms ----
+      const int rl = t >> 1, h = t & 1;
+      if (a.aor[row0 + rl] >= 0) {
+        float c[NR][NQ];
+#pragma unroll
+        for (int n = 0; n < NR; ++n)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
+        accumulate_half(a.v, row0 + rl, h, c);
+        u_transform_half(As + rl * AS, 1, h, c);
+        adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
+      }
+    } else {
+      float* G = a.G + (size_t)tile * ND1 * FR;
+      for (int idx = t; idx < FR * ND1; idx += FT) {
+        const int k = idx >> 7, r = idx & (FR - 1);
+        G[idx] = As[r * AS + k];
+      }
     }
   }
 }
@@ -438,18 +457,25 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     a.W8[k] = s->model->W8[k];
     a.bscale[k] = s->model->beta_scale[k];
   }
-  a.mode = mode;
   a.G = s->G1.p;
+  a.w = s->w_slot.p;
   a.nrm = s->nrm;
   a.e_int = s->e_int;
   a.v_int = s->v_int;
   a.D_out = d_out;
-  if (s->model->precision == FLARE_BF16_SPLIT)
-    k_fused144<FLARE_BF16_SPLIT><<<s->rows1 / FR, FT, 0, s->stream>>>(a);
-  else if (s->model->precision == FLARE_FP8_SPLIT)
-    k_fused144<FLARE_FP8_SPLIT><<<s->rows1 / FR, FT, 0, s->stream>>>(a);
-  else
-    k_fused144<FLARE_FP32><<<s->rows1 / FR, FT, 0, s->stream>>>(a);
+  const int grid = s->rows1 / FR;
+  const bool forces = (mode & 5) == 5;
+  a.mode = mode & 3;
+  if (s->model->precision == FLARE_BF16_SPLIT) {
+    if (forces) k_fused144<FLARE_BF16_SPLIT, true><<<grid, FT, 0, s->stream>>>(a);
+    else k_fused144<FLARE_BF16_SPLIT, false><<<grid, FT, 0, s->stream>>>(a);
+  } else if (s->model->precision == FLARE_FP8_SPLIT) {
+    if (forces) k_fused144<FLARE_FP8_SPLIT, true><<<grid, FT, 0, s->stream>>>(a);
+    else k_fused144<FLARE_FP8_SPLIT, false><<<grid, FT, 0, s->stream>>>(a);
+  } else {
+    if (forces) k_fused144<FLARE_FP32, true><<<grid, FT, 0, s->stream>>>(a);
+    else k_fused144<FLARE_FP32, false><<<grid, FT, 0, s->stream>>>(a);
+  }
 }
 
 }  // namespace flare

@@ -146,6 +146,83 @@ __global__ __launch_bounds__(NT) void k_reduce_cells(int ntask, const RedTask* _
   if (sigma_max) sigma_max[cell] = mx;
 }
 
+// Per-row virial W_i = -sum_k Delta_k (x) w_k over the row's own pairs (Delta = r u from
+// the slot geometry, w = de_i/dDelta from the adjoint), in slot order; [9][n] internal.
+__global__ __launch_bounds__(NT) void k_virial_rows(int rows, int rows1, const int* __restrict__ aor1,
+                                                    const int* __restrict__ aorx,
+                                                    const int* __restrict__ slice_base,
+                                                    const float4* __restrict__ geom,
+                                                    const float4* __restrict__ w,
+                                                    const int* __restrict__ cnt, int n,
+                                                    float* __restrict__ vir) {
+  const int R = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  if (R >= rows) return;
+  const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
+  if (i < 0) return;
+  const int base = slice_base[R >> 5], len = cnt[i];
+  float acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.f;
+  for (int k = 0; k < len; ++k) {
+    const int slot = (base + k) * 32 + (R & 31);
+    const float4 g = geom[slot];
+    const float4 wk = w[slot];
+    const float r = fabsf(g.w);      // 0 outside the cutoff: no contribution
+    const float d[3] = {r * g.x, r * g.y, r * g.z};
+    const float ww[3] = {wk.x, wk.y, wk.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc[3 * a + b] -= d[a] * ww[b];
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) vir[(size_t)c * n + i] = acc[c];
+}
+
+// One block per task: FP64 sums of the 9 virial components over [begin, end), fixed order.
+__global__ __launch_bounds__(NT) void k_virial_tasks(const RedTask* __restrict__ tasks,
+                                                     const int* __restrict__ bucket,
+                                                     const float* __restrict__ vir, int n,
+                                                     double* __restrict__ red_w) {
+  __shared__ double sw[9][NT];
+  const RedTask tk = tasks[blockIdx.x];
+  double acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+  for (int i = tk.begin + threadIdx.x; i < tk.end; i += NT) {
+    if (bucket[i] < 0) continue;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += (double)vir[(size_t)c * n + i];
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) sw[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sw[c][threadIdx.x] += sw[c][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 9) red_w[(size_t)blockIdx.x * 9 + threadIdx.x] = sw[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(NT) void k_virial_cells(int ntask, const RedTask* __restrict__ tasks,
+                                                     const double* __restrict__ red_w,
+                                                     const int* __restrict__ first_task, int ncell,
+                                                     double* __restrict__ out) {
+  const int cell = blockIdx.x * NT + threadIdx.x;
+  if (cell >= ncell) return;
+  double acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+  for (int k = first_task[cell]; k < ntask && tasks[k].cell == cell; ++k)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += red_w[(size_t)k * 9 + c];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) out[(size_t)cell * 9 + c] = acc[c];
+}
+
 constexpr double KAPPA = 9.648533212e-3;   // (eV/A)/amu in A/fs^2
 
 __global__ __launch_bounds__(NT) void k_md_first(int n, double* __restrict__ x, double* __restrict__ y,
@@ -209,6 +286,21 @@ void reduce_cells(flare_state* s, double* e_struct, float* sigma_max) {
                                            sigma_max != nullptr, s->red_e.p, s->red_s.p);
   k_reduce_cells<<<(s->n_struct + NT - 1) / NT, NT, 0, s->stream>>>(
       nt, s->d_tasks.p, s->red_e.p, s->red_s.p, s->d_first_task.p, s->n_struct, e_struct, sigma_max);
+}
+
+void virial_cells(flare_state* s, double* virial_struct) {
+  const int n = s->n_atoms;
+  const int rows = s->rows1 + s->rowsx;
+  const int nt = (int)s->tasks.size();
+  if (rows > 0)
+    k_virial_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
+                                                             s->slice_base.p, s->geom.p, s->w_slot.p, s->nl_cnt, n,
+                                                             s->vir_int.p);
+  if (nt > 0)
+    k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->vir_int.p, n, s->red_w.p);
+  if (s->n_struct > 0)
+    k_virial_cells<<<(s->n_struct + NT - 1) / NT, NT, 0, s->stream>>>(nt, s->d_tasks.p, s->red_w.p,
+                                                                      s->d_first_task.p, s->n_struct, virial_struct);
 }
 
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,

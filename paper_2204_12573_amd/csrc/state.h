@@ -115,6 +115,7 @@ struct flare_state {
   long long pos_gen = 0;     // positions staged by flare_descriptors
   long long v_gen = -1;      // positions the variances were computed for
   long long g_gen = -1;      // positions the energy gradients were computed for
+  long long w_gen = -1;      // positions the per-pair adjoint terms were computed for
   long long fixed_bytes = 0; // device bytes of the fixed-size arrays
   int n_atoms = 0;
   int n_struct = 0;
@@ -179,6 +180,9 @@ struct flare_state {
   flare::DevBuf<int> slot_atom, slot_j, slot_s, slot_pair, slot_rev;
   flare::DevBuf<float4> geom;                        // per slot, per step
   flare::DevBuf<float4> w_slot;                      // per slot: de_i/dDelta (x, y, z, 0)
+  // virial (allocated at the first flare_virial call)
+  flare::DevBuf<float> vir_int;                      // [9][max_atoms] per internal atom
+  flare::DevBuf<double> red_w;                       // [tasks][9]
 
   flare::Timers timers;
 
@@ -209,10 +213,12 @@ void compute_descriptors_mixed(flare_state* s);
 void export_descriptors(flare_state* s, float* d_out, float* norm_out);
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out);
 void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v);
-void compute_forces(flare_state* s);
+// adjoint terms of the 544-wide rows, and of the 144-wide rows if rows144 (from G1)
+void compute_forces(flare_state* s, bool rows144);
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
                       float* var_atom, float* sigma_atom, const double* cell_scale = nullptr);
 void reduce_cells(flare_state* s, double* e_struct, float* sigma_max);
+void virial_cells(flare_state* s, double* virial_struct);
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy,
               double* vz, const float* fx, const float* fy, const float* fz,
               const int32_t* species, double inv_m0, double inv_m1, double dt);

@@ -126,6 +126,13 @@ class Evaluator:
             B.check(self.lib.flare_forces(self.handle, B.ptr(cell_scale), B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2])))
         return f
 
+    def virial(self, out=None):
+        """Per-cell virial W = -dE/d(strain), [n_struct, 3, 3] FP64, from the last forces."""
+        out = torch.empty((self.n_struct, 3, 3), dtype=torch.float64, device=self.device) if out is None else out
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_virial(self.handle, B.ptr(out)))
+        return out
+
     def memory_bytes(self, with_model=True):
         b = ctypes.c_longlong()
         B.check(self.lib.flare_memory_bytes(self.model.handle if with_model else None, self.handle,

@@ -136,3 +136,45 @@ def _nve_dt(st, beta, v0, dt, n):
         r = ev.evaluate(p, st.species, st.box, beta, np.zeros_like(beta))
         return r.energy, r.f
     return md.nve(st.pos, v0, st.species, dt, n, fn)
+
+
+def test_virial_diagonal_matches_strain_fd(tiny):
+    """W_aa = -dE/deps_aa: central differences of a uniaxial strain of the periodic cell
+    (positions and box together), Richardson-extrapolated."""
+    st, beta, gamma, _ = tiny
+    res = ev.evaluate(st.pos, st.species, st.box, beta, gamma, want_virial=True)
+    fn = lambda p, b: ev.total_energy(p, st.species, b, beta)
+    scale = np.abs(res.virial).max()
+    assert scale > 1e-4
+    for axis in range(3):
+        w1 = forces.virial_fd(fn, st.pos, st.box, axis, step=2e-5)
+        w2 = forces.virial_fd(fn, st.pos, st.box, axis, step=1e-5)
+        rich = (4 * w2 - w1) / 3
+        assert abs(rich - res.virial[axis, axis]) / scale < 1e-8
+
+
+def test_virial_free_cluster_is_sum_r_times_f():
+    """A cluster far from its periodic images: W_ab = sum_i r_i,a F_i,b with F from
+    central differences of the energy (a route that never forms h_p), and W symmetric."""
+    st = S.config_tiny()
+    beta, gamma = S.random_model(DEFAULT.n_desc)
+    centre = st.pos[70]
+    sel = np.nonzero(np.linalg.norm(st.pos - centre, axis=1) < 5.0)[0]
+    box = np.array([40.0, 40.0, 40.0])
+    pos = st.pos[sel] - centre + box / 2
+    sp = st.species[sel]
+    assert len(sel) >= 6 and len(set(sp.tolist())) == 2
+    res = ev.evaluate(pos, sp, box, beta, gamma, want_virial=True)
+    fn = lambda p: ev.total_energy(p, sp, box, beta)
+    f = forces.forces_fd(fn, pos, step=1e-5)
+    w_fd = (pos - box / 2).T @ f
+    scale = np.abs(res.virial).max()
+    assert scale > 1e-4
+    assert np.abs(res.virial - w_fd).max() / scale < 1e-7
+    assert np.abs(res.virial - res.virial.T).max() / scale < 1e-12
+
+
+def test_virial_symmetric_periodic(tiny):
+    st, beta, gamma, _ = tiny
+    w = ev.evaluate(st.pos, st.species, st.box, beta, gamma, want_virial=True).virial
+    assert np.abs(w - w.T).max() < 1e-12 * np.abs(w).max()
