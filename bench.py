@@ -26,19 +26,19 @@ PEAK_FP32_MFMA = 157.3e12      # dense FP32 matrix FLOP/s, MI355X
 PEAK_HBM = 8.0e12              # B/s
 
 
-PROFILE = os.path.join(ROOT, "profiles", "bench_large_fp32.txt")
+PROFILE = os.path.join(ROOT, "profiles", "k_fused144_pp_h2_pt111_1M_fp32.txt")
 
 
 def kernel_sources_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ["fused.hip", "half.h", "pair.h", "basis.h", "common.h", "state.h"]:
+    for f in ["fused.hip", "adjoint.h", "half.h", "pair.h", "basis.h", "common.h", "state.h"]:
         with open(os.path.join(ROOT, "paper_2204_12573_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def profiled_traffic(kernel="k_fused144<0>"):
+def profiled_traffic(kernel="k_fused144_pp<0>"):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
     try:
@@ -221,7 +221,8 @@ def main():
     achieved = flops_per_launch / (q_ms / q_cnt * 1e-3)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_MFMA, "traffic": profiled_traffic(),
-                "kernel": "k_fused144 (descriptors + D[Sigma], D[beta] on FP32 MFMA, 144-wide rows)",
+                "kernel": "k_fused144_pp (144-wide rows: descriptors, D[Sigma] and D[beta] on FP32 MFMA, "
+                          "adjoint terms; the MFMA work bounds it, the vector work runs beside it)",
                 "algorithmic_flop_per_launch": flops_per_launch, "avg_launch_us": q_ms / q_cnt * 1e3}
     stage_us = {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm.items() if c}
     out = {

@@ -12,12 +12,12 @@
 //      fragment-major copy of W (one contiguous 1 KB load per 16x16 block and K chunk);
 //   3. epilogue, with Y~ = d~ W: V_i = Y~ . d~ / |d~|^2 (or |Z~|^2/|d~|^2 in the split form),
 //      e_i = Y~ . d~ / |d~|^2, g_i = de_i/dd~_i = (2/|d~|^2)(Y~ - e_i d~) written into the
-//      tile, then either copied out coalesced as G[tile][k][row] (the layout the
-//      standalone adjoint kernel reads with one lane pair per row) or, when the forces
-//      are wanted now,
-//   4. adjoint in place: the lane pairs recompute their row's densities, form u = G^ c
-//      from the gradient tile in LDS and write the per-pair terms w (adjoint.h); g never
-//      goes to HBM.
+//      tile;
+//   4. either g is copied out coalesced as G[tile][k][row] (the layout the standalone
+//      adjoint kernel reads with one lane pair per row), or, when the forces are wanted
+//      now, the lane pairs recompute their row's densities, form u = G^ c from the
+//      gradient tile in LDS and write the per-pair terms w (adjoint.h): g never goes to
+//      HBM. The forces variant runs as a persistent ping-pong kernel (see k_fused144_pp).
 // Inside a 16-wide K chunk, k-step t of lane group q uses k = 4q + t for A and B alike.
 #include "adjoint.h"
 #include "state.h"
@@ -285,85 +285,78 @@ __device__ __forceinline__ void row_dots(const float* As, const f4 (&acc)[2][NCB
     }
 }
 
-template <int PREC, bool FORCES>
-__global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
-  __shared__ __attribute__((aligned(16))) float As[FR * AS];
-  __shared__ float nrm_s[FR];
-  __shared__ float rsc_s[FR];     // FP8 split form: power-of-two row scale s_r
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int row0 = tile * FR;
-  const float4* Wb = a.Wf[0];
-  const uint4* Wh = a.Wb[0];
-  const uint64_t* W8 = a.W8[0];
-  float bsc = a.bscale[0];
+// Model operands of the bucket that holds rows [row0, row0 + 128).
+struct TileModel {
+  const float4* Wf;
+  const uint4* Wb;
+  const uint64_t* W8;
+  float bsc;
+};
+__device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
+  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.bscale[0]};
 #pragma unroll
-  for (int k = 1; k < 4; ++k)
-    if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k]) {
-      Wb = a.Wf[k];
-      Wh = a.Wb[k];
-      W8 = a.W8[k];
-      bsc = a.bscale[k];
-    }
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int k = 1; k < 4; ++k)   // static indexing keeps the argument arrays out of scratch
+    if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k]) m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.bscale[k]};
+  return m;
+}
 
-  // ---- 1. descriptors into the LDS tile ----
-  {
-    const int rl = t >> 1, h = t & 1;
-    const int i = a.aor[row0 + rl];
-    float c[NR][NQ];
+// 1. descriptors of the tile's rows into the LDS tile (thread t of 256: row t/2, half t&1)
+template <int PREC>
+__device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float* nrm_s, float* rsc_s, int row0,
+                                           int t) {
+  const int rl = t >> 1, h = t & 1;
+  const int i = a.aor[row0 + rl];
+  float c[NR][NQ];
 #pragma unroll
-    for (int n = 0; n < NR; ++n)
+  for (int n = 0; n < NR; ++n)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
-    if (i >= 0) accumulate_half(a.v, row0 + rl, h, c);
-    // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
-    // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
-    double nrm2 = 0.0;    // |d~|^2 accumulated in FP64
-    float amax = 0.f;     // max |d~_k| (FP8 row scale)
-    float* rowp = As + rl * AS + 2 * h;
-    int k = 0;
+    for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
+  if (i >= 0) accumulate_half(a.v, row0 + rl, h, c);
+  // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
+  // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
+  double nrm2 = 0.0;    // |d~|^2 accumulated in FP64
+  float amax = 0.f;     // max |d~_k| (FP8 row scale)
+  float* rowp = As + rl * AS + 2 * h;
+  int k = 0;
 #pragma unroll
-    for (int na = 0; na < NR; ++na)
+  for (int na = 0; na < NR; ++na)
 #pragma unroll
-      for (int nb = na; nb < NR; ++nb) {
-        const float4 d = b2_half(c[na], c[nb], h);
-        nrm2 += (double)(d.x * d.x + d.y * d.y) + (double)(d.z * d.z + d.w * d.w);
-        const float2 mine = h ? make_float2(d.z, d.w) : make_float2(d.x, d.y);
-        if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
-        *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
-        ++k;
-      }
-    const float nrm = (float)sqrt(nrm2);
-    if (PREC == FLARE_FP8_SPLIT) {
-      amax = fmaxf(amax, xor1(amax));
-      int ex = 0;
-      frexpf(amax > 0.f ? amax : 1.f, &ex);      // amax = f 2^ex, f in [0.5, 1)
-      if (h == 0) rsc_s[rl] = ldexpf(1.f, 4 - ex);   // |s_r d~| < 16
+    for (int nb = na; nb < NR; ++nb) {
+      const float4 d = b2_half(c[na], c[nb], h);
+      nrm2 += (double)(d.x * d.x + d.y * d.y) + (double)(d.z * d.z + d.w * d.w);
+      const float2 mine = h ? make_float2(d.z, d.w) : make_float2(d.x, d.y);
+      if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
+      *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
+      ++k;
     }
-    if (h == 0) {
-      nrm_s[rl] = nrm;
-      if (i >= 0) a.nrm[i] = nrm;
-    }
+  const float nrm = (float)sqrt(nrm2);
+  if (PREC == FLARE_FP8_SPLIT) {
+    amax = fmaxf(amax, xor1(amax));
+    int ex = 0;
+    frexpf(amax > 0.f ? amax : 1.f, &ex);      // amax = f 2^ex, f in [0.5, 1)
+    if (h == 0) rsc_s[rl] = ldexpf(1.f, 4 - ex);   // |s_r d~| < 16
   }
-  __syncthreads();
-  if (a.D_out) {
-    for (int idx = t; idx < FR * ND1; idx += FT) {
-      const int r = idx / ND1, k = idx % ND1;
-      const float nv = nrm_s[r];
-      a.D_out[(size_t)(row0 + r) * ND1 + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
-    }
+  if (h == 0) {
+    nrm_s[rl] = nrm;
+    if (i >= 0) a.nrm[i] = nrm;
   }
+}
 
-  // ---- 2/3. quadratic forms and epilogue ----
+// 2/3. quadratic forms and epilogue on a complete descriptor tile; leaves g in the tile
+// when the energy pass runs. Wave w of the 4 owns rows 32w .. 32w + 31.
+template <int PREC>
+__device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const float* nrm_s,
+                                            const float* rsc_s, int row0, int t, const TileModel& tm) {
+  const int lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, grp = lane >> 4;
   f4 acc[2][NCB];
   float dots[2][4];
   if (a.mode & 2) {
     if (PREC != FLARE_FP32) {
-      mfma_pass<1, true>(As, Wb, wave, lane, acc);   // Z = D L on FP32 cores, L lower-triangular
+      mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);   // Z = D L on FP32 cores, L lower-triangular
       row_sumsq(acc, dots);
     } else {
-      mfma_pass<1>(As, Wb, wave, lane, acc);
+      mfma_pass<1>(As, tm.Wf, wave, lane, acc);
       row_dots(As, acc, wave, lane, dots);
     }
     if (l16 == 0) {
@@ -380,20 +373,20 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   }
   if (a.mode & 1) {
     if (PREC == FLARE_BF16_SPLIT) {
-      mfma_pass_bf16<0>(As, Wh, wave, lane, acc);
+      mfma_pass_bf16<0>(As, tm.Wb, wave, lane, acc);
     } else if (PREC == FLARE_FP8_SPLIT) {
-      mfma_pass_fp8(As, rsc_s, W8, wave, lane, acc);
+      mfma_pass_fp8(As, rsc_s, tm.W8, wave, lane, acc);
       // undo the power-of-two scales: Y~ = acc / (16 s_r s_b), exact
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float inv = 1.f / (16.f * rsc_s[wave * 32 + i * 16 + 4 * grp + r] * bsc);
+          const float inv = 1.f / (16.f * rsc_s[wave * 32 + i * 16 + 4 * grp + r] * tm.bsc);
 #pragma unroll
           for (int j = 0; j < NCB; ++j) acc[i][j][r] *= inv;
         }
     } else {
-      mfma_pass<0>(As, Wb, wave, lane, acc);
+      mfma_pass<0>(As, tm.Wf, wave, lane, acc);
     }
     row_dots(As, acc, wave, lane, dots);
 #pragma unroll
@@ -412,27 +405,92 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
 #pragma unroll
         for (int j = 0; j < NCB; ++j) d[j * 16] = s2 * (acc[i][j][r] - e * d[j * 16]);
       }
+  }
+}
+
+// 4. adjoint in place: u = G^ c from the gradient tile, then the per-pair terms.
+__device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t) {
+  const int rl = t >> 1, h = t & 1;
+  if (a.aor[row0 + rl] < 0) return;
+  float c[NR][NQ];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
+  accumulate_half(a.v, row0 + rl, h, c);
+  u_transform_half(As + rl * AS, 1, h, c);
+  adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
+}
+
+// One tile per work-group, phases in sequence (descriptor export, energies or variances
+// without forces: g leaves as G[tile][k][row]).
+template <int PREC>
+__global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) float As[FR * AS];
+  __shared__ float nrm_s[FR];
+  __shared__ float rsc_s[FR];     // FP8 split form: power-of-two row scale s_r
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int row0 = tile * FR;
+  const int t = threadIdx.x;
+  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t);
+  __syncthreads();
+  if (a.D_out) {
+    for (int idx = t; idx < FR * ND1; idx += FT) {
+      const int r = idx / ND1, k = idx % ND1;
+      const float nv = nrm_s[r];
+      a.D_out[(size_t)(row0 + r) * ND1 + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
+    }
+  }
+  forms_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, tile_model(a, row0));
+  if (a.mode & 1) {
     __syncthreads();
-    if (FORCES) {
-      // ---- 4. adjoint: u = G^ c from the gradient tile, then the per-pair terms ----
-      const int rl = t >> 1, h = t & 1;
-      if (a.aor[row0 + rl] >= 0) {
-        float c[NR][NQ];
-#pragma unroll
-        for (int n = 0; n < NR; ++n)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
-        accumulate_half(a.v, row0 + rl, h, c);
-        u_transform_half(As + rl * AS, 1, h, c);
-        adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
-      }
-    } else {
-      float* G = a.G + (size_t)tile * ND1 * FR;
-      for (int idx = t; idx < FR * ND1; idx += FT) {
-        const int k = idx >> 7, r = idx & (FR - 1);
-        G[idx] = As[r * AS + k];
+    float* G = a.G + (size_t)tile * ND1 * FR;
+    for (int idx = t; idx < FR * ND1; idx += FT) {
+      const int k = idx >> 7, r = idx & (FR - 1);
+      G[idx] = As[r * AS + k];
+    }
+  }
+}
+
+// Energies, forces (and variances) with the matrix cores and the vector units busy at
+// the same time. One persistent work-group per CU, two groups of 4 waves, each with its
+// own LDS tile. The WG's tiles are wg, wg + nwg, ...; group g takes every other one. In
+// each step one group runs the quadratic forms of its tile (MFMA) while the other runs
+// the adjoint of its previous tile and the descriptors of its next (VALU); a barrier
+// ends the step and the roles swap. Group g's local step p = s - g: even p = 2m runs the
+// adjoint of local tile m - 1 and the descriptors of tile m, odd p = 2m + 1 the forms of
+// tile m. Every thread executes every step's barrier.
+constexpr int PT = 2 * FT;
+
+template <int PREC>
+__global__ __launch_bounds__(PT, 1) void k_fused144_pp(FusedArgs a, int ntiles) {
+  __shared__ __attribute__((aligned(16))) float As[2][FR * AS];
+  __shared__ float nrm_s[2][FR];
+  __shared__ float rsc_s[2][FR];
+  const int g = threadIdx.x / FT, t = threadIdx.x % FT;
+  const int wg = blockIdx.x, nwg = gridDim.x;
+  const int J = wg < ntiles ? (ntiles - wg + nwg - 1) / nwg : 0;   // tiles of this work-group
+  const int M0 = (J + 1) / 2, M1 = J / 2;
+  const int Mg = g ? M1 : M0;
+  const int nsteps = max(2 * M0 + 1, 2 * M1 + 2);
+  float* A = As[g];
+  float* ns = nrm_s[g];
+  float* rs = rsc_s[g];
+  for (int s = 0; s < nsteps; ++s) {
+    const int p = s - g;
+    if (p >= 0) {
+      const int m = p >> 1;
+      if ((p & 1) == 0) {
+        if (m >= 1 && m - 1 < Mg) adjoint_phase(a, A, (wg + nwg * (2 * (m - 1) + g)) * FR, t);
+        // the lane pair of row r read only row r's gradients above and writes only row r below
+        __builtin_amdgcn_wave_barrier();
+        if (m < Mg) desc_phase<PREC>(a, A, ns, rs, (wg + nwg * (2 * m + g)) * FR, t);
+      } else if (m < Mg) {
+        const int row0 = (wg + nwg * (2 * m + g)) * FR;
+        forms_phase<PREC>(a, A, ns, rs, row0, t, tile_model(a, row0));
       }
     }
+    __syncthreads();
   }
 }
 
@@ -463,19 +521,25 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   a.e_int = s->e_int;
   a.v_int = s->v_int;
   a.D_out = d_out;
-  const int grid = s->rows1 / FR;
-  const bool forces = (mode & 5) == 5;
+  const int ntiles = s->rows1 / FR;
   a.mode = mode & 3;
-  if (s->model->precision == FLARE_BF16_SPLIT) {
-    if (forces) k_fused144<FLARE_BF16_SPLIT, true><<<grid, FT, 0, s->stream>>>(a);
-    else k_fused144<FLARE_BF16_SPLIT, false><<<grid, FT, 0, s->stream>>>(a);
-  } else if (s->model->precision == FLARE_FP8_SPLIT) {
-    if (forces) k_fused144<FLARE_FP8_SPLIT, true><<<grid, FT, 0, s->stream>>>(a);
-    else k_fused144<FLARE_FP8_SPLIT, false><<<grid, FT, 0, s->stream>>>(a);
-  } else {
-    if (forces) k_fused144<FLARE_FP32, true><<<grid, FT, 0, s->stream>>>(a);
-    else k_fused144<FLARE_FP32, false><<<grid, FT, 0, s->stream>>>(a);
+  if ((mode & 5) == 5) {
+    // energies + forces: persistent ping-pong kernel, one work-group per CU
+    const int grid = ntiles < 256 ? ntiles : 256;
+    if (s->model->precision == FLARE_BF16_SPLIT)
+      k_fused144_pp<FLARE_BF16_SPLIT><<<grid, PT, 0, s->stream>>>(a, ntiles);
+    else if (s->model->precision == FLARE_FP8_SPLIT)
+      k_fused144_pp<FLARE_FP8_SPLIT><<<grid, PT, 0, s->stream>>>(a, ntiles);
+    else
+      k_fused144_pp<FLARE_FP32><<<grid, PT, 0, s->stream>>>(a, ntiles);
+    return;
   }
+  if (s->model->precision == FLARE_BF16_SPLIT)
+    k_fused144<FLARE_BF16_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
+  else if (s->model->precision == FLARE_FP8_SPLIT)
+    k_fused144<FLARE_FP8_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
+  else
+    k_fused144<FLARE_FP32><<<ntiles, FT, 0, s->stream>>>(a);
 }
 
 }  // namespace flare

@@ -37,7 +37,28 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* 
   if (fx) {
     const int base = slice_base[R >> 5], len = cnt[i];   // the row's own pairs (no padding)
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int k = 0; k < len; ++k) {
+    int k = 0;
+    // four pairs per trip: the reverse indices, then all eight terms, are in flight together
+    for (; k + 4 <= len; k += 4) {
+      int sl[4], rv[4];
+      float4 wo[4], wr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sl[u] = (base + k + u) * 32 + (R & 31);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rv[u] = slot_rev[sl[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        wo[u] = w[sl[u]];
+        wr[u] = w[rv[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sx += wo[u].x - wr[u].x;
+        sy += wo[u].y - wr[u].y;
+        sz += wo[u].z - wr[u].z;
+      }
+    }
+    for (; k < len; ++k) {
       const int slot = (base + k) * 32 + (R & 31);
       const float4 wo = w[slot];
       const float4 wr = w[slot_rev[slot]];
