@@ -110,8 +110,9 @@ __device__ __forceinline__ void u_transform_half(const float* g, int gstride, in
 }
 
 // Exchange the two halves of u so that both lanes of the row hold all of it, then split
-// the row's slots between the lanes (k = h, h + 2, ...): each pair term is evaluated once
-// and written to its slot (zero for padding and pairs outside the cutoff).
+// the row's slots between the lanes (k = h, h + 2, ...): each pair term is evaluated once,
+// written to its slot (zero for padding and pairs outside the cutoff) and scattered to
+// the reverse pair's slot of w_in, where the force gather of the neighbour reads it.
 __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int h, const float (&c)[NR][NQ],
                                                    float4* __restrict__ w) {
   float u[NR][NLM];
@@ -125,18 +126,24 @@ __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int
     }
   const int base = v.slice_base[R >> 5];
   const int len = v.slice_base[(R >> 5) + 1] - base;
-  const float4* gp = v.geom + (size_t)base * 32 + (R & 31);
-  float4* wp = w + (size_t)base * 32 + (R & 31);
+  const size_t s0 = (size_t)base * 32 + (R & 31);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 gnext = h < len ? gp[(size_t)h * 32] : zero;
+  float4 gnext = h < len ? v.geom[s0 + (size_t)h * 32] : zero;
+  int rnext = h < len ? v.rev[s0 + (size_t)h * 32] : 0;
   for (int k = h; k < len; k += 2) {
     const float4 gk = gnext;
-    gnext = k + 2 < len ? gp[(size_t)(k + 2) * 32] : zero;
+    const int rk = rnext;
+    if (k + 2 < len) {
+      gnext = v.geom[s0 + (size_t)(k + 2) * 32];
+      rnext = v.rev[s0 + (size_t)(k + 2) * 32];
+    }
     PairGeom pg;
     int sp;
     float wx = 0.f, wy = 0.f, wz = 0.f;
     if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
-    wp[(size_t)k * 32] = make_float4(wx, wy, wz, 0.f);
+    const float4 wk = make_float4(wx, wy, wz, 0.f);
+    w[s0 + (size_t)k * 32] = wk;
+    v.w_in[rk] = wk;
   }
 }
 

@@ -1,15 +1,17 @@
 // Forces by the reordered (adjoint) sum of the paper's Section V.B: the descriptor
 // gradient is never formed (the per-pair terms are in adjoint.h). The densities c are
 // recomputed from the pair list. Forces follow without atomics:
-// F_i = sum_{p in list(i)} (w_p - w_rev(p)), rev(p) being the pair (j, i, -s)
-// (reduce.hip), so they are deterministic and independent of how cells are batched.
+// F_i = sum_{p in list(i)} (w_p - w_rev(p)), rev(p) being the pair (j, i, -s): every w_p
+// is also stored at the slot of rev(p) in w_in, and the gather (reduce.hip) reads both
+// arrays at the row's own slots, in slot order, so forces are deterministic and
+// independent of how cells are batched.
 #include "adjoint.h"
+#include "mixed.h"
 #include "state.h"
 
 namespace flare {
 namespace {
 
-constexpr int NTX = 64;
 constexpr int TA = 256;   // threads of the 144-row adjoint kernel (128 rows, 2 lanes each)
 
 // One row per lane pair (see half.h and adjoint.h), reading g from the tile-transposed
@@ -31,73 +33,74 @@ __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __rest
   adjoint_pairs_half(v, R, h, c, w);
 }
 
-__global__ __launch_bounds__(NTX) void k_adjoint_mixed(SlotView v, int rows1, int rows,
-                                                       const int* __restrict__ atom_of_row,
-                                                       const float* __restrict__ G,
-                                                       float4* __restrict__ w) {
-  // densities, then adjoints, of both species halves; one column per thread
-  __shared__ float uh[NR * NLM][NTX];
-  __shared__ float up[NR * NLM][NTX];
-  const int t = threadIdx.x;
-  const int row = blockIdx.x * NTX + t;
-  if (row >= rows) return;
-  const int i = atom_of_row[row];
-  if (i < 0) return;
-  for (int half = 0; half < 2; ++half) {
-    float c[NR][NLM];
-#pragma unroll
-    for (int n = 0; n < NR; ++n)
-#pragma unroll
-      for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
-    accumulate_densities(v, rows1 + row, half, c);
-    float (*dst)[NTX] = half ? up : uh;
-#pragma unroll
-    for (int n = 0; n < NR; ++n)
-#pragma unroll
-      for (int lm = 0; lm < NLM; ++lm) dst[n * NLM + lm][t] = c[n][lm];
-  }
-  const float* g = G + (size_t)row * ND;
-  const float* gHH = g;
-  const float* gHP = g + ND1;
-  const float* gPP = g + ND1 + NDX;
-  for (int lm = 0; lm < NLM; ++lm) {
-    const int l = lm_l(lm);
-    float ch[NR], cp[NR], oh[NR], op[NR];
-#pragma unroll
-    for (int n = 0; n < NR; ++n) {
-      ch[n] = uh[n * NLM + lm][t];
-      cp[n] = up[n * NLM + lm][t];
-    }
-#pragma unroll
-    for (int a = 0; a < NR; ++a) {
-      float acc_h = 0.f, acc_p = 0.f;
-#pragma unroll
-      for (int b = 0; b < NR; ++b) {
-        const int ia = a < b ? a : b, ib = a < b ? b : a;
-        const float w2 = a == b ? 2.f : 1.f;
-        acc_h += w2 * gHH[pair_index_same(ia, ib) * 4 + l] * ch[b] + gHP[(a * NR + b) * 4 + l] * cp[b];
-        acc_p += w2 * gPP[pair_index_same(ia, ib) * 4 + l] * cp[b] + gHP[(b * NR + a) * 4 + l] * ch[b];
-      }
-      oh[a] = acc_h;
-      op[a] = acc_p;
-    }
-#pragma unroll
-    for (int n = 0; n < NR; ++n) {
-      uh[n * NLM + lm][t] = oh[n];
-      up[n * NLM + lm][t] = op[n];
-    }
-  }
+// Mixed rows, 16 lanes per row (mixed.h): lane a = s*8 + n forms its density channel,
+// then its adjoint channel u_{a,lm} = sum_b G^_{ab,l} c_{b,lm} over the 16 channels of
+// the row (G^ from the row's 544 gradient components: (H,H) and (Pt,Pt) blocks doubled on
+// the diagonal, the (H,Pt) block shared by both orders), and the row's slots are split
+// over the lanes (k = L, L + 16, ...), each pair reading u of its neighbour species from LDS.
+__global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows1,
+                                                            const int* __restrict__ atom_of_row,
+                                                            const float* __restrict__ G, float4* __restrict__ w) {
+  __shared__ __attribute__((aligned(16))) float cs[MROWS * MSTRIDE];
+  const int rl = threadIdx.x >> 4, L = threadIdx.x & 15;
+  const int row = blockIdx.x * MROWS + rl;
   const int R = rows1 + row;
-  SLOT_STREAM_BEGIN(v, R);
-  for (int k = 0; k < ss_len; ++k) {
+  const int i = atom_of_row[row];
+  float c[NLM];
+#pragma unroll
+  for (int lm = 0; lm < NLM; ++lm) c[lm] = 0.f;
+  if (i >= 0) mixed_channel_density(v, R, L, c);
+  float* crow = cs + rl * MSTRIDE;
+#pragma unroll
+  for (int lm = 0; lm < NLM; ++lm) crow[cidx(L, lm)] = c[lm];
+  __syncthreads();
+  float u[NLM];
+#pragma unroll
+  for (int lm = 0; lm < NLM; ++lm) u[lm] = 0.f;
+  if (i >= 0) {
+    const float* g = G + (size_t)row * ND;
+    const int sa = L >> 3, na = L & 7;
+#pragma unroll 2
+    for (int b = 0; b < 2 * NR; ++b) {
+      const int sb = b >> 3, nb = b & 7;
+      int base;
+      float f = 1.f;
+      if (sa == sb) {
+        const int lo = na < nb ? na : nb, hi = na < nb ? nb : na;
+        base = (sa ? ND1 + NDX : 0) + pair_index_same(lo, hi) * 4;
+        f = na == nb ? 2.f : 1.f;
+      } else {
+        base = ND1 + (sa == 0 ? na * NR + nb : nb * NR + na) * 4;
+      }
+      const float4 gl = *reinterpret_cast<const float4*>(g + base);
+      const float g0 = f * gl.x, g1 = f * gl.y, g2 = f * gl.z, g3 = f * gl.w;
+      const float* cb = crow + cidx(b, 0);
+      u[0] += g0 * cb[0];
+#pragma unroll
+      for (int lm = 1; lm < 4; ++lm) u[lm] += g1 * cb[lm];
+#pragma unroll
+      for (int lm = 4; lm < 9; ++lm) u[lm] += g2 * cb[lm];
+#pragma unroll
+      for (int lm = 9; lm < 16; ++lm) u[lm] += g3 * cb[lm];
+    }
+  }
+  __syncthreads();   // all channels read: the block now takes u
+#pragma unroll
+  for (int lm = 0; lm < NLM; ++lm) crow[cidx(L, lm)] = u[lm];
+  __syncthreads();
+  if (i < 0) return;
+  const int base = v.slice_base[R >> 5];
+  const int len = v.slice_base[(R >> 5) + 1] - base;
+  for (int k = L; k < len; k += 16) {
+    const size_t slot = (size_t)(base + k) * 32 + (R & 31);
     PairGeom pg;
     int sp;
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (unpack_geom(SLOT_STREAM_NEXT(k), pg, sp)) {
-      float (*u)[NTX] = sp == 0 ? uh : up;
-      pair_force(pg, v.rc, [&](int n, int lm) { return u[n * NLM + lm][t]; }, wx, wy, wz);
-    }
-    w[slot_of(v.slice_base, R, k)] = make_float4(wx, wy, wz, 0.f);
+    if (unpack_geom(v.geom[slot], pg, sp))
+      pair_force(pg, v.rc, [&](int n, int lm) { return crow[cidx(sp * NR + n, lm)]; }, wx, wy, wz);
+    const float4 wk = make_float4(wx, wy, wz, 0.f);
+    w[slot] = wk;
+    v.w_in[v.rev[slot]] = wk;
   }
 }
 
@@ -113,8 +116,8 @@ void compute_forces(flare_state* s, bool rows144) {
   {
     StageTimer tm(s, FLARE_T_FORCEX);
     if (s->rowsx > 0)
-      k_adjoint_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rows1, s->rowsx,
-                                                                          s->atom_of_rowx.p, s->Gx.p, s->w_slot.p);
+      k_adjoint_mixed<<<s->rowsx / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, s->atom_of_rowx.p, s->Gx.p,
+                                                                    s->w_slot.p);
   }
 }
 

@@ -33,6 +33,8 @@ SlotView slot_view(const flare_state* s) {
   SlotView v;
   v.geom = s->geom.p;
   v.slice_base = s->slice_base.p;
+  v.rev = s->slot_rev.p;
+  v.w_in = s->w_in.p;
   v.rc = (float)s->model->r_cut;
   return v;
 }
@@ -762,7 +764,7 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
          s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
          s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
          s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_s.bytes() + s->slot_pair.bytes() +
-         s->slot_rev.bytes() + s->geom.bytes() + s->w_slot.bytes() + s->vir_int.bytes() + s->red_w.bytes();
+         s->slot_rev.bytes() + s->geom.bytes() + s->w_slot.bytes() + s->w_in.bytes() + s->vir_int.bytes() + s->red_w.bytes();
   }
   *bytes = b;
   return FLARE_OK;

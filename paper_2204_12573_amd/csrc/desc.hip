@@ -4,122 +4,69 @@
 //   d~_{(a,b),l}  = sum_m c_{a,l,m} c_{b,l,m}    (a <= b, packed)
 //   d             = d~ / |d~|
 //
-// This file holds the mixed-environment rows (544 components): one thread per row, the
-// H-channel densities in LDS (one column per thread) and the Pt half in registers.
-// Single-species rows are formed inside the fused quadratic-form kernel (fused.hip).
-// b2_same below is the single-species block of a row, used for the (Pt, Pt) block.
+// This file holds the mixed-environment rows (544 components, 16 lanes per row, see
+// mixed.h). Single-species rows are formed inside the fused quadratic-form kernel
+// (fused.hip).
 // Pair geometry: positions are FP64; Delta = (x_j - x_i) + s*L is formed in FP64 and
 // rounded to FP32 before the basis is evaluated.
-#include "basis.h"
-#include "pair.h"
+#include "mixed.h"
 #include "state.h"
 
 namespace flare {
 namespace {
 
-constexpr int NT = 128;
-constexpr int NTX = 64;
 
-// 36 packed radial pairs (na <= nb) of a single-species block: 4 l-values each.
-// nrm2 accumulates sum d~^2; out (optional) receives scale * d~ as float4 per pair.
-__device__ __forceinline__ void b2_same(const float (*c)[NLM], float4* out, float scale,
-                                        float& nrm2) {
-  int k = 0;
+// One mixed row per 16 lanes (mixed.h): channel densities into LDS, then the 136 B2
+// channel pairs spread over the row's lanes (pair P = L + 16q), the norm summed in FP64
+// across the lanes, and the normalised row written as float4 per pair.
+__global__ __launch_bounds__(MTHREADS) void k_desc_mixed(SlotView v, int rows1, const int* __restrict__ atom_of_row,
+                                                         float* __restrict__ D, float* __restrict__ nrm_out) {
+  __shared__ __attribute__((aligned(16))) float cs[MROWS * MSTRIDE];
+  const int rl = threadIdx.x >> 4, L = threadIdx.x & 15;
+  const int row = blockIdx.x * MROWS + rl;
+  const int i = atom_of_row[row];
+  float c[NLM];
 #pragma unroll
-  for (int na = 0; na < NR; ++na) {
+  for (int lm = 0; lm < NLM; ++lm) c[lm] = 0.f;
+  if (i >= 0) mixed_channel_density(v, rows1 + row, L, c);
+  float* crow = cs + rl * MSTRIDE;
 #pragma unroll
-    for (int nb = na; nb < NR; ++nb) {
-      float d0 = c[na][0] * c[nb][0];
-      float d1 = c[na][1] * c[nb][1] + c[na][2] * c[nb][2] + c[na][3] * c[nb][3];
+  for (int lm = 0; lm < NLM; ++lm) crow[cidx(L, lm)] = c[lm];
+  __syncthreads();
+  constexpr int NPAIR = ND / 4;           // 136 channel pairs
+  constexpr int NQP = (NPAIR + 15) / 16;  // 9 per lane
+  float4 d[NQP];
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQP; ++q) {
+    const int P = L + 16 * q;
+    d[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (P < NPAIR) {
+      int ca, cb;
+      mixed_pair_channels(P, ca, cb);
+      const float* x = crow + cidx(ca, 0);
+      const float* y = crow + cidx(cb, 0);
+      float d0 = x[0] * y[0];
+      float d1 = x[1] * y[1] + x[2] * y[2] + x[3] * y[3];
       float d2 = 0.f, d3 = 0.f;
 #pragma unroll
-      for (int lm = 4; lm < 9; ++lm) d2 += c[na][lm] * c[nb][lm];
+      for (int lm = 4; lm < 9; ++lm) d2 += x[lm] * y[lm];
 #pragma unroll
-      for (int lm = 9; lm < 16; ++lm) d3 += c[na][lm] * c[nb][lm];
-      nrm2 += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
-      if (out) out[k] = make_float4(d0 * scale, d1 * scale, d2 * scale, d3 * scale);
-      ++k;
+      for (int lm = 9; lm < 16; ++lm) d3 += x[lm] * y[lm];
+      d[q] = make_float4(d0, d1, d2, d3);
+      nrm2 += (double)(d0 * d0 + d1 * d1) + (double)(d2 * d2 + d3 * d3);
     }
   }
-}
-
-__device__ __forceinline__ float4 b2_pair(const float* a, const float* b) {
-  float d0 = a[0] * b[0];
-  float d1 = a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
-  float d2 = 0.f, d3 = 0.f;
-#pragma unroll
-  for (int lm = 4; lm < 9; ++lm) d2 += a[lm] * b[lm];
-#pragma unroll
-  for (int lm = 9; lm < 16; ++lm) d3 += a[lm] * b[lm];
-  return make_float4(d0, d1, d2, d3);
-}
-
-__global__ __launch_bounds__(NTX) void k_desc_mixed(SlotView v, int rows1, int rows,
-                                                    const int* __restrict__ atom_of_row,
-                                                    float* __restrict__ D,
-                                                    float* __restrict__ nrm_out) {
-  __shared__ float ch[NR * NLM][NTX];     // H-channel densities, one column per thread
-  const int t = threadIdx.x;
-  const int row = blockIdx.x * NTX + t;
-  if (row >= rows) return;
+  nrm2 = sum16d(nrm2);                    // the row's 16 lanes form one DPP row
+  const float nrm = (float)sqrt(nrm2);
+  const float scale = nrm > 0.f ? 1.f / nrm : 0.f;
   float4* out = reinterpret_cast<float4*>(D + (size_t)row * ND);
-  const int i = atom_of_row[row];
-  if (i < 0) {
-    for (int k = 0; k < ND / 4; ++k) out[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
+#pragma unroll
+  for (int q = 0; q < NQP; ++q) {
+    const int P = L + 16 * q;
+    if (P < NPAIR) out[P] = make_float4(d[q].x * scale, d[q].y * scale, d[q].z * scale, d[q].w * scale);
   }
-  float c[NR][NLM];
-#pragma unroll
-  for (int n = 0; n < NR; ++n)
-#pragma unroll
-    for (int lm = 0; lm < NLM; ++lm) c[n][lm] = 0.f;
-  accumulate_densities(v, rows1 + row, 0, c);
-#pragma unroll
-  for (int n = 0; n < NR; ++n)
-#pragma unroll
-    for (int lm = 0; lm < NLM; ++lm) {
-      ch[n * NLM + lm][t] = c[n][lm];
-      c[n][lm] = 0.f;
-    }
-  accumulate_densities(v, rows1 + row, 1, c);     // c now holds the Pt channels
-  float a[NLM], b[NLM];
-  float scale = 1.f;
-  for (int pass = 0; pass < 2; ++pass) {
-    float nrm2 = 0.f;
-    int k = 0;
-    // (H, H) block
-    for (int na = 0; na < NR; ++na) {
-#pragma unroll
-      for (int lm = 0; lm < NLM; ++lm) a[lm] = ch[na * NLM + lm][t];
-      for (int nb = na; nb < NR; ++nb) {
-#pragma unroll
-        for (int lm = 0; lm < NLM; ++lm) b[lm] = ch[nb * NLM + lm][t];
-        float4 d = b2_pair(a, b);
-        nrm2 += d.x * d.x + d.y * d.y + d.z * d.z + d.w * d.w;
-        if (pass) out[k] = make_float4(d.x * scale, d.y * scale, d.z * scale, d.w * scale);
-        ++k;
-      }
-    }
-    // (H, Pt) block
-    for (int na = 0; na < NR; ++na) {
-#pragma unroll
-      for (int lm = 0; lm < NLM; ++lm) a[lm] = ch[na * NLM + lm][t];
-#pragma unroll
-      for (int nb = 0; nb < NR; ++nb) {
-        float4 d = b2_pair(a, c[nb]);
-        nrm2 += d.x * d.x + d.y * d.y + d.z * d.z + d.w * d.w;
-        if (pass) out[k] = make_float4(d.x * scale, d.y * scale, d.z * scale, d.w * scale);
-        ++k;
-      }
-    }
-    // (Pt, Pt) block
-    b2_same(c, pass ? out + k : nullptr, scale, nrm2);
-    if (pass == 0) {
-      const float nrm = sqrtf(nrm2);
-      nrm_out[i] = nrm;
-      scale = nrm > 0.f ? 1.f / nrm : 0.f;
-    }
-  }
+  if (L == 0 && i >= 0) nrm_out[i] = nrm;
 }
 
 constexpr int NTG = 256;
@@ -230,8 +177,7 @@ void compute_descriptors_mixed(flare_state* s) {
   const SlotView v = slot_view(s);
   StageTimer tm(s, FLARE_T_DESCX);
   if (s->rowsx > 0)
-    k_desc_mixed<<<(s->rowsx + NTX - 1) / NTX, NTX, 0, s->stream>>>(v, s->rows1, s->rowsx, s->atom_of_rowx.p,
-                                                                    s->Dx.p, s->nrm);
+    k_desc_mixed<<<s->rowsx / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, s->atom_of_rowx.p, s->Dx.p, s->nrm);
 }
 
 void export_descriptors(flare_state* s, float* d_out, float* norm_out) {

@@ -44,7 +44,8 @@ struct FusedArgs {
   const uint64_t* W8[4]; // FP8 split form: s_b beta as [ks 5][cb 9][hi/lo' 2][lane 64] x 8 e4m3
   float bscale[4];       // FP8 split form: s_b per bucket (a power of two)
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
-  float* G;              // [tiles][144][128] (written when the forces are not formed here)
+  float* G;              // [tiles][144][128]: g (no forces here), or the densities of each
+                         // tile between its descriptor and adjoint phases (forces here)
   float4* w;             // per-slot adjoint terms (written when the forces are formed here)
   float* nrm;            // per atom
   float* e_int;
@@ -78,18 +79,19 @@ __device__ __forceinline__ void mfma_pass(const float* As, const float4* __restr
 #pragma unroll
     for (int i = 0; i < 2; ++i)
       a[i] = *reinterpret_cast<const float4*>(&As[(wave * 32 + i * 16 + l16) * AS + kc * 16 + 4 * grp]);
-#pragma unroll
-    for (int j = 0; j < NCB; ++j) {
-      if (TRI && j > kc) continue;      // lower-triangular W: rows k < column j vanish
-      const float4 b = cur[j];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b.x, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b.y, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, b.z, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, b.w, acc[i][j], 0, 0, 0);
-      }
-    }
+    // k-step outermost: consecutive MFMAs write different accumulators, so none waits
+    // for the previous result; each accumulator still sees k in increasing order
+#define FQ_STEP(C)                                                                           \
+  _Pragma("unroll") for (int j = 0; j < NCB; ++j) {                                         \
+    if (TRI && j > kc) continue; /* lower-triangular W: rows k < column j vanish */         \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i)                                           \
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].C, cur[j].C, acc[i][j], 0, 0, 0); \
+  }
+    FQ_STEP(x)
+    FQ_STEP(y)
+    FQ_STEP(z)
+    FQ_STEP(w)
+#undef FQ_STEP
   }
 }
 
@@ -136,19 +138,25 @@ __device__ __forceinline__ void mfma_pass_bf16(const float* As, const uint4* __r
 #pragma unroll
     for (int i = 0; i < 2; ++i)
       split8(&As[(wave * 32 + i * 16 + l16) * AS + ks * 32 + 8 * grp], ks == NKS - 1 && grp >= 2, ahi[i], alo[i]);
+    bf8 bhv[NCB], blv[NCB];
 #pragma unroll
     for (int j = 0; j < NCB; ++j) {
-      const uint4 bh = Wp[((ks * NCB + j) * 2 + 0) * 64];
-      const uint4 bl = Wp[((ks * NCB + j) * 2 + 1) * 64];
-      const bf8 bhv = __builtin_bit_cast(bf8, bh);
-      const bf8 blv = __builtin_bit_cast(bf8, bl);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhv, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blv, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhv, acc[i][j], 0, 0, 0);
-      }
+      bhv[j] = __builtin_bit_cast(bf8, Wp[((ks * NCB + j) * 2 + 0) * 64]);
+      blv[j] = __builtin_bit_cast(bf8, Wp[((ks * NCB + j) * 2 + 1) * 64]);
     }
+    // product outermost: consecutive MFMAs write different accumulators
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhv[j], acc[i][j], 0, 0, 0);
   }
 }
 
@@ -220,17 +228,25 @@ __device__ __forceinline__ void mfma_pass_fp8(const float* As, const float* rs, 
       }
       split8_fp8(x, a16[i], ah[i], al[i]);
     }
+    long bh[NCB], bl[NCB];
 #pragma unroll
     for (int j = 0; j < NCB; ++j) {
-      const long bh = (long)Wp[((ks * NCB + j) * 2 + 0) * 64];
-      const long bl = (long)Wp[((ks * NCB + j) * 2 + 1) * 64];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a16[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(al[i], bh, acc[i][j], 0, 0, 0);
-      }
+      bh[j] = (long)Wp[((ks * NCB + j) * 2 + 0) * 64];
+      bl[j] = (long)Wp[((ks * NCB + j) * 2 + 1) * 64];
     }
+    // product outermost: consecutive MFMAs write different accumulators
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a16[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(al[i], bh[j], acc[i][j], 0, 0, 0);
   }
 }
 
@@ -301,9 +317,11 @@ __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
 }
 
 // 1. descriptors of the tile's rows into the LDS tile (thread t of 256: row t/2, half t&1)
+// cstore (optional): the tile's densities are also written there, c[n][q] of thread t
+// at cstore[(8n + q) * 256 + t] (coalesced), for the adjoint phase of the same tile.
 template <int PREC>
 __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float* nrm_s, float* rsc_s, int row0,
-                                           int t) {
+                                           int t, float* cstore) {
   const int rl = t >> 1, h = t & 1;
   const int i = a.aor[row0 + rl];
   float c[NR][NQ];
@@ -312,6 +330,12 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
 #pragma unroll
     for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
   if (i >= 0) accumulate_half(a.v, row0 + rl, h, c);
+  if (cstore) {
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) cstore[(n * NQ + q) * FT + t] = c[n][q];
+  }
   // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
   // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
   double nrm2 = 0.0;    // |d~|^2 accumulated in FP64
@@ -408,16 +432,17 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
   }
 }
 
-// 4. adjoint in place: u = G^ c from the gradient tile, then the per-pair terms.
-__device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t) {
+// 4. adjoint in place: u = G^ c from the gradient tile, then the per-pair terms. The
+// densities come from cstore (written by desc_phase) instead of a second pass over the pairs.
+__device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t,
+                                              const float* cstore) {
   const int rl = t >> 1, h = t & 1;
   if (a.aor[row0 + rl] < 0) return;
   float c[NR][NQ];
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
-  accumulate_half(a.v, row0 + rl, h, c);
+    for (int q = 0; q < NQ; ++q) c[n][q] = cstore[(n * NQ + q) * FT + t];
   u_transform_half(As + rl * AS, 1, h, c);
   adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
 }
@@ -432,7 +457,7 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const int t = threadIdx.x;
-  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t);
+  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, nullptr);
   __syncthreads();
   if (a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
@@ -481,10 +506,16 @@ __global__ __launch_bounds__(PT, 1) void k_fused144_pp(FusedArgs a, int ntiles) 
     if (p >= 0) {
       const int m = p >> 1;
       if ((p & 1) == 0) {
-        if (m >= 1 && m - 1 < Mg) adjoint_phase(a, A, (wg + nwg * (2 * (m - 1) + g)) * FR, t);
+        if (m >= 1 && m - 1 < Mg) {
+          const int tp = wg + nwg * (2 * (m - 1) + g);
+          adjoint_phase(a, A, tp * FR, t, a.G + (size_t)tp * FR * ND1);
+        }
         // the lane pair of row r read only row r's gradients above and writes only row r below
         __builtin_amdgcn_wave_barrier();
-        if (m < Mg) desc_phase<PREC>(a, A, ns, rs, (wg + nwg * (2 * m + g)) * FR, t);
+        if (m < Mg) {
+          const int tn = wg + nwg * (2 * m + g);
+          desc_phase<PREC>(a, A, ns, rs, tn * FR, t, a.G + (size_t)tn * FR * ND1);
+        }
       } else if (m < Mg) {
         const int row0 = (wg + nwg * (2 * m + g)) * FR;
         forms_phase<PREC>(a, A, ns, rs, row0, t, tile_model(a, row0));

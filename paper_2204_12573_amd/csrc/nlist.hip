@@ -316,6 +316,30 @@ __global__ __launch_bounds__(NT) void k_assign_rows(int n, const int* __restrict
   else aorx[row] = i;
 }
 
+// Inside each tile of 128 rows (tiles never straddle a bucket), order the rows by
+// neighbour count, largest first, ties by the previous order: the 32-row slices of the
+// sliced layout then hold rows of similar length, so a wave's trip count over its slice
+// (the longest row) wastes few lanes. Rows stay within their tile, so the tile keeps its
+// spatial locality.
+__global__ __launch_bounds__(TILE_ROWS) void k_sort_tile_rows(int* __restrict__ aor,
+                                                              const int* __restrict__ cnt,
+                                                              int* __restrict__ row_of) {
+  __shared__ int key[TILE_ROWS];
+  const int r = threadIdx.x;
+  const int row0 = blockIdx.x * TILE_ROWS;
+  const int i = aor[row0 + r];
+  const int k = i >= 0 ? cnt[i] : -1;
+  key[r] = k;
+  __syncthreads();
+  int rank = 0;
+  for (int q = 0; q < TILE_ROWS; ++q) {
+    const int kq = key[q];
+    rank += (kq > k || (kq == k && q < r)) ? 1 : 0;
+  }
+  aor[row0 + rank] = i;
+  if (i >= 0) row_of[i] = row0 + rank;
+}
+
 // info[0] = total pairs, info[1..6] = bucket totals, info[7] = status
 __global__ void k_info(int n, const int* __restrict__ nl_off, const int* __restrict__ blk_scan,
                        int nblk, const int* __restrict__ status, int* __restrict__ info) {
@@ -431,6 +455,8 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev, s->d_status);
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
+    if (r1 > 0) k_sort_tile_rows<<<r1 / TILE_ROWS, TILE_ROWS, 0, st>>>(s->atom_of_row1.p, s->nl_cnt, s->row_of);
+    if (rx > 0) k_sort_tile_rows<<<rx / TILE_ROWS, TILE_ROWS, 0, st>>>(s->atom_of_rowx.p, s->nl_cnt, s->row_of);
   }
   // sliced layout: slice lengths, their prefix, then the slots
   s->n_slices = (r1 + rx) / 32;
@@ -457,6 +483,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->slot_rev.reserve(nslots + 1));
   HIPCHK(s->geom.reserve(nslots + 1));
   HIPCHK(s->w_slot.reserve(nslots + 1));
+  HIPCHK(s->w_in.reserve(nslots + 1));
   HIPCHK(hipMemsetAsync(s->slot_atom.p, 0xff, (nslots + 1) * sizeof(int), st));
   HIPCHK(hipMemsetAsync(s->slot_j.p, 0, (nslots + 1) * sizeof(int), st));
   HIPCHK(hipMemsetAsync(s->slot_s.p, 0, (nslots + 1) * sizeof(int), st));

@@ -11,13 +11,13 @@ namespace {
 constexpr int NT = 256;
 
 // Caller-order outputs, one thread per row. Forces by gathering the per-pair adjoint
-// terms over the row's slots: F_i = sum_k (w_slot(i,k) - w_rev(slot(i,k))) for the row's
-// own pairs k < count, in slot order (deterministic).
+// terms over the row's slots: F_i = sum_k (w(slot(i,k)) - w_in(slot(i,k))) for the row's
+// own pairs k < count, in slot order (deterministic); w_in holds each slot's reverse term.
 __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* __restrict__ aor1,
                                                 const int* __restrict__ aorx,
                                                 const int* __restrict__ slice_base,
                                                 const float4* __restrict__ w,
-                                                const int* __restrict__ slot_rev,
+                                                const float4* __restrict__ w_in,
                                                 const int* __restrict__ perm,
                                                 const int* __restrict__ cnt,
                                                 const int* __restrict__ sid,
@@ -37,31 +37,10 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* 
   if (fx) {
     const int base = slice_base[R >> 5], len = cnt[i];   // the row's own pairs (no padding)
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    int k = 0;
-    // four pairs per trip: the reverse indices, then all eight terms, are in flight together
-    for (; k + 4 <= len; k += 4) {
-      int sl[4], rv[4];
-      float4 wo[4], wr[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sl[u] = (base + k + u) * 32 + (R & 31);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) rv[u] = slot_rev[sl[u]];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        wo[u] = w[sl[u]];
-        wr[u] = w[rv[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        sx += wo[u].x - wr[u].x;
-        sy += wo[u].y - wr[u].y;
-        sz += wo[u].z - wr[u].z;
-      }
-    }
-    for (; k < len; ++k) {
+    for (int k = 0; k < len; ++k) {
       const int slot = (base + k) * 32 + (R & 31);
       const float4 wo = w[slot];
-      const float4 wr = w[slot_rev[slot]];
+      const float4 wr = w_in[slot];
       sx += wo.x - wr.x;
       sy += wo.y - wr.y;
       sz += wo.z - wr.z;
@@ -292,7 +271,7 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
   const int rows = s->rows1 + s->rowsx;
   if (rows > 0)
     k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
-                                                         s->slice_base.p, s->w_slot.p, s->slot_rev.p, s->perm,
+                                                         s->slice_base.p, s->w_slot.p, s->w_in.p, s->perm,
                                                          s->nl_cnt, s->sid, cell_scale, s->e_int, s->v_int, e_atom, fx, fy, fz, var_atom,
                                                          sigma_atom);
   k_outputs_empty<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->bucket, s->perm, e_atom, fx, fy, fz, var_atom,

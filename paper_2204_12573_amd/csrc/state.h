@@ -61,6 +61,8 @@ struct SlotView {
   const float4* geom;       // per slot: (u_x, u_y, u_z, r) of the pair, r = 0 outside the
                             // cutoff or padding; r < 0 marks an H neighbour, r > 0 Pt
   const int* slice_base;    // [slices + 1] in groups of 32 slots
+  const int* rev;           // per slot: slot of the reverse pair (padding: itself)
+  float4* w_in;             // per slot: the adjoint term of the reverse pair, scattered there
   float rc;
 };
 
@@ -180,6 +182,7 @@ struct flare_state {
   flare::DevBuf<int> slot_atom, slot_j, slot_s, slot_pair, slot_rev;
   flare::DevBuf<float4> geom;                        // per slot, per step
   flare::DevBuf<float4> w_slot;                      // per slot: de_i/dDelta (x, y, z, 0)
+  flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
   // virial (allocated at the first flare_virial call)
   flare::DevBuf<float> vir_int;                      // [9][max_atoms] per internal atom
   flare::DevBuf<double> red_w;                       // [tasks][9]
