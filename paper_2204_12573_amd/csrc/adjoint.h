@@ -128,22 +128,37 @@ __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int
   const int len = v.slice_base[(R >> 5) + 1] - base;
   const size_t s0 = (size_t)base * 32 + (R & 31);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 gnext = h < len ? v.geom[s0 + (size_t)h * 32] : zero;
-  int rnext = h < len ? v.rev[s0 + (size_t)h * 32] : 0;
-  for (int k = h; k < len; k += 2) {
-    const float4 gk = gnext;
-    const int rk = rnext;
-    if (k + 2 < len) {
-      gnext = v.geom[s0 + (size_t)(k + 2) * 32];
-      rnext = v.rev[s0 + (size_t)(k + 2) * 32];
+  // lane h takes slots k = h, h + 2, ...; the geometry and reverse index of its next two
+  // slots are in flight while one is evaluated (ring of two, unrolled)
+  float4 gb[2];
+  int rb[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int k = h + 2 * e;
+    gb[e] = k < len ? v.geom[s0 + (size_t)k * 32] : zero;
+    rb[e] = k < len ? v.rev[s0 + (size_t)k * 32] : 0;
+  }
+  for (int k0 = h; k0 < len; k0 += 4) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = k0 + 2 * e;
+      const float4 gk = gb[e];
+      const int rk = rb[e];
+      const int kn = k + 4;
+      if (kn < len) {
+        gb[e] = v.geom[s0 + (size_t)kn * 32];
+        rb[e] = v.rev[s0 + (size_t)kn * 32];
+      }
+      if (k < len) {
+        PairGeom pg;
+        int sp;
+        float wx = 0.f, wy = 0.f, wz = 0.f;
+        if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
+        const float4 wk = make_float4(wx, wy, wz, 0.f);
+        w[s0 + (size_t)k * 32] = wk;
+        v.w_in[rk] = wk;
+      }
     }
-    PairGeom pg;
-    int sp;
-    float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
-    const float4 wk = make_float4(wx, wy, wz, 0.f);
-    w[s0 + (size_t)k * 32] = wk;
-    v.w_in[rk] = wk;
   }
 }
 

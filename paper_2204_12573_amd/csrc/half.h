@@ -14,11 +14,10 @@ constexpr int NQ = 8;   // (l, m) indices per lane
 // c[n][q] += R_n Y_{8h+q} over the neighbours of row R inside the cutoff. All rows of a
 // wave share one slice, so the trip count is uniform across the wave.
 __device__ __forceinline__ void accumulate_half(const SlotView& v, int Rw, int h, float (*c)[NQ]) {
-  SLOT_STREAM_BEGIN(v, Rw);
-  for (int k = 0; k < ss_len; ++k) {
+  for_each_slot<6>(v, Rw, [&](const float4& g, int) {
     PairGeom pg;
     int sp;
-    if (!unpack_geom(SLOT_STREAM_NEXT(k), pg, sp)) continue;
+    if (!unpack_geom(g, pg, sp)) return;
     float R[NR], Y[NLM];
     radial(pg.r, v.rc, R);
     sph_harm(pg.ux, pg.uy, pg.uz, Y);
@@ -28,7 +27,7 @@ __device__ __forceinline__ void accumulate_half(const SlotView& v, int Rw, int h
 #pragma unroll
       for (int nn = 0; nn < NR; ++nn) c[nn][q] += R[nn] * y;
     }
-  }
+  });
 }
 
 // One B2 radial pair (a, b) of a single-species block: the four l-components, identical

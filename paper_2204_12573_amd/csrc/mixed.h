@@ -21,12 +21,11 @@ __device__ __forceinline__ int cidx(int a, int lm) { return a * NLM + (a >> 3) *
 // c[lm] = sum over the row's neighbours of species (L >> 3) of R_{L & 7}(r) Y_lm(r^).
 __device__ __forceinline__ void mixed_channel_density(const SlotView& v, int R, int L, float (&c)[NLM]) {
   const int s = L >> 3, n = L & 7;
-  SLOT_STREAM_BEGIN(v, R);
-  for (int k = 0; k < ss_len; ++k) {
+  for_each_slot<4>(v, R, [&](const float4& g, int) {
     PairGeom pg;
     int sp;
-    if (!unpack_geom(SLOT_STREAM_NEXT(k), pg, sp)) continue;
-    if (sp != s) continue;
+    if (!unpack_geom(g, pg, sp)) return;
+    if (sp != s) return;
     float Rn[NR], Y[NLM];
     radial(pg.r, v.rc, Rn);
     sph_harm(pg.ux, pg.uy, pg.uz, Y);
@@ -35,7 +34,7 @@ __device__ __forceinline__ void mixed_channel_density(const SlotView& v, int R, 
     for (int q = 1; q < NR; ++q) rn = n == q ? Rn[q] : rn;   // select, no dynamic register index
 #pragma unroll
     for (int lm = 0; lm < NLM; ++lm) c[lm] += rn * Y[lm];
-  }
+  });
 }
 
 // Channels (a, b) of packed B2 pair P of a 544-wide row: (H,H) pairs 0..35 (na <= nb,

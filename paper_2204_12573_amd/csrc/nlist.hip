@@ -209,19 +209,33 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
 // For every pair p = (i, j, s) find q = (j, i, -s) in j's list. The list is symmetric
 // because the FP64 distance test gives the same value for both orders (negating a
 // rounded difference is exact). A missing partner sets the species flag bit 8.
+// One thread per pair: a work-group takes the pairs of NT consecutive atoms, finds each
+// pair's atom by bisection in the group's offsets (in LDS), then scans j's list.
 __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ nl_off,
                                                 const int* __restrict__ nl_j,
                                                 const int32_t* __restrict__ nl_s,
                                                 int* __restrict__ rev, int* __restrict__ status) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  for (int p = nl_off[i]; p < nl_off[i + 1]; ++p) {
+  __shared__ int offs[NT + 1];
+  const int a0 = blockIdx.x * NT;
+  const int na = min(NT, n - a0);
+  for (int k = threadIdx.x; k <= na; k += NT) offs[k] = nl_off[a0 + k];
+  __syncthreads();
+  const int p0 = offs[0], p1 = offs[na];
+  for (int p = p0 + threadIdx.x; p < p1; p += NT) {
+    int lo = 0, hi = na;            // largest k with offs[k] <= p
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (offs[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int i = a0 + lo;
     const int j = nl_j[p];
     int sx, sy, sz;
     unpack_shift(nl_s[p], sx, sy, sz);
     const int32_t want = pack_shift(-sx, -sy, -sz);
     int found = -1;
-    for (int q = nl_off[j]; q < nl_off[j + 1]; ++q) {
+    const int q1 = nl_off[j + 1];
+    for (int q = nl_off[j]; q < q1; ++q) {
       if (nl_j[q] == i && nl_s[q] == want) {
         found = q;
         break;
@@ -495,18 +509,21 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   if (nslots > 0)
     k_rev_slots<<<(int)((nslots + NT - 1) / NT), NT, 0, st>>>(nslots, s->slot_atom.p, s->slot_pair.p, s->nl_rev,
                                                               s->slot_of_pair, s->slot_rev.p);
-  // reduction tasks: contiguous internal ranges of one cell, at most 16384 atoms each
+  // reduction tasks: contiguous internal ranges of one cell, at most 2048 atoms each (one
+  // work-group per task); cell c owns tasks [first_task[c], first_task[c + 1])
   s->tasks.clear();
+  s->first_task.assign(nc + 1, 0);
   for (int c = 0; c < nc; ++c) {
+    s->first_task[c] = (int)s->tasks.size();
     int a = s->struct_off[c], b = s->struct_off[c + 1];
     if (a == b) s->tasks.push_back({c, a, a});
-    for (int k = a; k < b; k += 16384) s->tasks.push_back({c, k, std::min(b, k + 16384)});
+    for (int k = a; k < b; k += 2048) s->tasks.push_back({c, k, std::min(b, k + 2048)});
   }
-  s->first_task.assign(nc, 0);
-  for (int k = (int)s->tasks.size() - 1; k >= 0; --k) s->first_task[s->tasks[k].cell] = k;
+  s->first_task[nc] = (int)s->tasks.size();
   HIPCHK(s->d_tasks.reserve(s->tasks.size()));
-  HIPCHK(s->d_first_task.reserve(nc));
-  HIPCHK(hipMemcpyAsync(s->d_first_task.p, s->first_task.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(s->d_first_task.reserve(nc + 1));
+  HIPCHK(hipMemcpyAsync(s->d_first_task.p, s->first_task.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice,
+                        st));
   HIPCHK(s->red_e.reserve(2 * s->tasks.size()));
   HIPCHK(s->red_s.reserve(s->tasks.size()));
   HIPCHK(hipMemcpyAsync(s->d_tasks.p, s->tasks.data(), s->tasks.size() * sizeof(RedTask),

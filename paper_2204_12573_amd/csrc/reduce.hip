@@ -126,24 +126,43 @@ __global__ __launch_bounds__(NT) void k_reduce_tasks(const RedTask* __restrict__
   }
 }
 
-// One thread per cell: fold its tasks in order.
-__global__ __launch_bounds__(NT) void k_reduce_cells(int ntask, const RedTask* __restrict__ tasks,
-                                                     const double* __restrict__ red_e,
+// One wave per cell: its tasks [first_task[c], first_task[c + 1]) are folded by the 64
+// lanes in a fixed stride, then combined in a fixed tree (deterministic).
+constexpr int NC = 64;
+
+__global__ __launch_bounds__(NC) void k_reduce_cells(const double* __restrict__ red_e,
                                                      const float* __restrict__ red_s,
-                                                     const int* __restrict__ first_task, int ncell,
+                                                     const int* __restrict__ first_task,
                                                      double* __restrict__ e_struct,
                                                      float* __restrict__ sigma_max) {
-  const int cell = blockIdx.x * NT + threadIdx.x;
-  if (cell >= ncell) return;
+  __shared__ double ss[NC], sc[NC];
+  __shared__ float sm[NC];
+  const int cell = blockIdx.x, t = threadIdx.x;
   double s = 0.0, c = 0.0;
   float mx = 0.f;
-  for (int k = first_task[cell]; k < ntask && tasks[k].cell == cell; ++k) {
+  for (int k = first_task[cell] + t; k < first_task[cell + 1]; k += NC) {
     two_sum_add(s, c, red_e[2 * k]);
     c += red_e[2 * k + 1];
     mx = fmaxf(mx, red_s[k]);
   }
-  if (e_struct) e_struct[cell] = s + c;
-  if (sigma_max) sigma_max[cell] = mx;
+  ss[t] = s;
+  sc[t] = c;
+  sm[t] = mx;
+  __syncthreads();
+  for (int h = NC / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      double s2 = ss[t], c2 = sc[t] + sc[t + h];
+      two_sum_add(s2, c2, ss[t + h]);
+      ss[t] = s2;
+      sc[t] = c2;
+      sm[t] = fmaxf(sm[t], sm[t + h]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (e_struct) e_struct[cell] = ss[0] + sc[0];
+    if (sigma_max) sigma_max[cell] = sm[0];
+  }
 }
 
 // Per-row virial W_i = -sum_k Delta_k (x) w_k over the row's own pairs (Delta = r u from
@@ -207,20 +226,28 @@ __global__ __launch_bounds__(NT) void k_virial_tasks(const RedTask* __restrict__
   if (threadIdx.x < 9) red_w[(size_t)blockIdx.x * 9 + threadIdx.x] = sw[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(NT) void k_virial_cells(int ntask, const RedTask* __restrict__ tasks,
-                                                     const double* __restrict__ red_w,
-                                                     const int* __restrict__ first_task, int ncell,
+__global__ __launch_bounds__(NC) void k_virial_cells(const double* __restrict__ red_w,
+                                                     const int* __restrict__ first_task,
                                                      double* __restrict__ out) {
-  const int cell = blockIdx.x * NT + threadIdx.x;
-  if (cell >= ncell) return;
+  __shared__ double sw[9][NC];
+  const int cell = blockIdx.x, t = threadIdx.x;
   double acc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0;
-  for (int k = first_task[cell]; k < ntask && tasks[k].cell == cell; ++k)
+  for (int k = first_task[cell] + t; k < first_task[cell + 1]; k += NC)
 #pragma unroll
     for (int c = 0; c < 9; ++c) acc[c] += red_w[(size_t)k * 9 + c];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) out[(size_t)cell * 9 + c] = acc[c];
+  for (int c = 0; c < 9; ++c) sw[c][t] = acc[c];
+  __syncthreads();
+  for (int h = NC / 2; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sw[c][t] += sw[c][t + h];
+    }
+    __syncthreads();
+  }
+  if (t < 9) out[(size_t)cell * 9 + t] = sw[t][0];
 }
 
 constexpr double KAPPA = 9.648533212e-3;   // (eV/A)/amu in A/fs^2
@@ -284,8 +311,9 @@ void reduce_cells(flare_state* s, double* e_struct, float* sigma_max) {
   if (nt == 0) return;
   k_reduce_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->e_int, s->v_int, e_struct != nullptr,
                                            sigma_max != nullptr, s->red_e.p, s->red_s.p);
-  k_reduce_cells<<<(s->n_struct + NT - 1) / NT, NT, 0, s->stream>>>(
-      nt, s->d_tasks.p, s->red_e.p, s->red_s.p, s->d_first_task.p, s->n_struct, e_struct, sigma_max);
+  if (s->n_struct > 0)
+    k_reduce_cells<<<s->n_struct, NC, 0, s->stream>>>(s->red_e.p, s->red_s.p, s->d_first_task.p, e_struct,
+                                                      sigma_max);
 }
 
 void virial_cells(flare_state* s, double* virial_struct) {
@@ -299,8 +327,7 @@ void virial_cells(flare_state* s, double* virial_struct) {
   if (nt > 0)
     k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->vir_int.p, n, s->red_w.p);
   if (s->n_struct > 0)
-    k_virial_cells<<<(s->n_struct + NT - 1) / NT, NT, 0, s->stream>>>(nt, s->d_tasks.p, s->red_w.p,
-                                                                      s->d_first_task.p, s->n_struct, virial_struct);
+    k_virial_cells<<<s->n_struct, NC, 0, s->stream>>>(s->red_w.p, s->d_first_task.p, virial_struct);
 }
 
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,

@@ -172,7 +172,7 @@ struct flare_state {
   flare::DevBuf<int> atom_of_row1, atom_of_rowx;
   flare::DevBuf<float> D1, G1, Dx, Gx, Yx, Px;       // descriptors, gradients, mixed Y, partials
   flare::DevBuf<flare::RedTask> d_tasks;
-  flare::DevBuf<int> d_first_task;                   // [n_struct] first task of each cell
+  flare::DevBuf<int> d_first_task;                   // [n_struct + 1] task range of each cell
   flare::DevBuf<double> red_e;                       // [tasks][2] (sum, compensation)
   flare::DevBuf<float> red_s;                        // [tasks]
   // sliced pair layout (grown at list builds)
