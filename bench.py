@@ -211,19 +211,24 @@ def main():
     for k, (ms, c) in tm.items():
         if c:
             log(f"  {k:9s} {ms/c*1e3:9.1f} us/launch x {c}")
+    vchol = model.variance_cholesky
     del ev, model
 
-    # dominant kernel: quadratic forms on the 144-wide rows (beta and Sigma, E+V)
+    # dominant kernel: quadratic forms on the 144-wide rows (beta and Sigma, E+V). Algorithmic
+    # flops per row: Y = beta d (2*144^2) and V = |L^T d|^2 through the triangular factor
+    # (144*145, one multiply-add per nonzero of L), or d^T Sigma d (2*144^2) without it.
     n144 = int(counts[:4].sum())
     n544 = int(counts[4:].sum())
     q_ms, q_cnt = tm["qform144"]
-    flops_per_launch = n144 * 2 * 2 * 144 * 144
+    flops_per_row = 2 * 144 * 144 + (144 * 145 if vchol else 2 * 144 * 144)
+    flops_per_launch = n144 * flops_per_row
     achieved = flops_per_launch / (q_ms / q_cnt * 1e-3)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_MFMA, "traffic": profiled_traffic(),
                 "kernel": "k_fused144_pp (144-wide rows: descriptors, D[Sigma] and D[beta] on FP32 MFMA, "
                           "adjoint terms; the MFMA work bounds it, the vector work runs beside it)",
-                "algorithmic_flop_per_launch": flops_per_launch, "avg_launch_us": q_ms / q_cnt * 1e3}
+                "algorithmic_flop_per_launch": flops_per_launch, "algorithmic_flop_per_row": flops_per_row,
+                "variance_form": "cholesky" if vchol else "full", "avg_launch_us": q_ms / q_cnt * 1e3}
     stage_us = {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm.items() if c}
     out = {
         "metric": METRIC,

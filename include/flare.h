@@ -55,10 +55,12 @@ extern "C" {
 /* ---- arithmetic of the quadratic forms ---- */
 /* The split forms change the energy contraction d.beta.d of the single-species rows
  * (144-wide) only: the operands are split into a high and a low part in a narrow format
- * and recombined in FP32 accumulators. In both split forms the variance d.Sigma.d is
- * computed as |L^T d|^2 with the FP64 Cholesky factor L of each Sigma block (stored FP32),
- * a sum of squares that does not cancel, and norms and per-structure sums stay FP64.
- * Mixed-environment rows (544-wide) keep FP32 products in all forms. */
+ * and recombined in FP32 accumulators. The variance d.Sigma.d is computed as |L^T d|^2
+ * with the FP64 Cholesky factor L of each Sigma block (stored FP32), a sum of squares
+ * that does not cancel, in every form when all Sigma blocks are positive definite (the
+ * split forms require it; the FP32 form falls back to the full matrix otherwise). Norms
+ * and per-structure sums stay FP64. Mixed-environment rows (544-wide) keep FP32 products
+ * in all forms. */
 #define FLARE_FP32        0  /* FP32 matrix cores, FP32 accumulation                          */
 #define FLARE_BF16_SPLIT  1  /* d and beta as BF16 hi + lo, three products per tile          */
 #define FLARE_FP8_SPLIT   2  /* OCP e4m3 hi + lo with power-of-two row and block scales      */
@@ -91,6 +93,13 @@ const char* flare_strerror(int code);
 int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, double r_cut,
                        const double* beta_host, const double* sigma_host, int precision);
 int flare_model_destroy(flare_model* model);
+/*
+ * How the model evaluates: *precision as passed at creation; *variance_cholesky = 1 when
+ * the variance is computed as |L^T d|^2 from the FP64 Cholesky factor L of every Sigma
+ * block (all blocks positive definite; always so in the split forms), 0 when the FP32
+ * form uses d^T Sigma d with the full matrix. Either pointer may be NULL. HOST pointers.
+ */
+int flare_model_info(const flare_model* model, int* precision, int* variance_cholesky);
 /* n_d of the model (544 for the supported sizes). */
 int flare_descriptor_dim(const flare_model* model, int* n_d);
 

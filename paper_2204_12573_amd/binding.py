@@ -47,6 +47,7 @@ SIGNATURES = {
     "flare_energy_forces": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "flare_forces": (_i, [_p, _p, _p, _p, _p]),
     "flare_virial": (_i, [_p, _p]),
+    "flare_model_info": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "flare_variance": (_i, [_p, _p, _p, _p]),
     "flare_memory_bytes": (_i, [_p, _p, ctypes.POINTER(_ll)]),
     "flare_md_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),

@@ -237,18 +237,63 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
       return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
     }
   }
+  // Cholesky factors of the Sigma blocks: V = |L^T d|^2, a sum of squares that does not
+  // cancel, and the zero upper triangle of L skips 36 of the 81 16x16 blocks of the
+  // 144-wide variance pass. The split forms need them; the FP32 form uses them when every
+  // block is positive definite and keeps the full Sigma otherwise.
+  const int nkc = ND1 / 16, ncb = ND1 / 16;
+  std::vector<std::vector<double>> L1(4), Lx(NS);
+  bool chol = true;
+  for (int b = 0; b < 4 && chol; ++b) {
+    const int s = b & 1;
+    L1[b] = sub_block(sigma_host + (size_t)s * ND * ND, b < 2 ? 0 : ND - ND1, ND1);
+    chol = cholesky(L1[b], ND1);
+  }
+  for (int s = 0; s < NS && chol; ++s) {
+    Lx[s].assign(sigma_host + (size_t)s * ND * ND, sigma_host + (size_t)(s + 1) * ND * ND);
+    chol = cholesky(Lx[s], ND);
+  }
+  if (!chol && precision != FLARE_FP32) {
+    set_error("Sigma is not positive definite (needed by the split forms)");
+    flare_model_destroy(m);
+    return FLARE_E_ARG;
+  }
+  m->vchol = chol;
+  if (chol) {
+    for (int b = 0; b < 4; ++b) {
+      // FP32 fragments of L replace the Sigma part (part 1) of Wf
+      std::vector<float> f((size_t)nkc * ncb * 64 * 4);
+      for (int kc = 0; kc < nkc; ++kc)
+        for (int cb = 0; cb < ncb; ++cb)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int t = 0; t < 4; ++t) {
+              const int k = kc * 16 + 4 * (lane / 16) + t, col = cb * 16 + lane % 16;
+              f[(((size_t)kc * ncb + cb) * 64 + lane) * 4 + t] = (float)L1[b][(size_t)k * ND1 + col];
+            }
+      hipError_t e = hipMemcpy(m->Wf[b] + (size_t)nkc * ncb * 64 * 4, f.data(), f.size() * sizeof(float),
+                               hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        set_error(std::string("model upload: ") + hipGetErrorString(e));
+        flare_model_destroy(m);
+        return FLARE_E_HIP;
+      }
+    }
+    for (int s = 0; s < NS; ++s) {
+      std::vector<float> lt((size_t)ND * ND);   // row n = column n of L
+      for (int n = 0; n < ND; ++n)
+        for (int k = 0; k < ND; ++k) lt[(size_t)n * ND + k] = (float)Lx[s][(size_t)k * ND + n];
+      int rc = upload((void**)&m->Lx[s], lt.data(), lt.size() * sizeof(float));
+      if (rc != FLARE_OK) {
+        flare_model_destroy(m);
+        return rc;
+      }
+    }
+  }
   if (precision == FLARE_BF16_SPLIT || precision == FLARE_FP8_SPLIT) {
-    const int nkc = ND1 / 16, ncb = ND1 / 16;
     for (int b = 0; b < 4; ++b) {
       const int s = b & 1;
       const int st = b < 2 ? 0 : ND - ND1;
       std::vector<double> beta = sub_block(beta_host + (size_t)s * ND * ND, st, ND1);
-      std::vector<double> L = sub_block(sigma_host + (size_t)s * ND * ND, st, ND1);
-      if (!cholesky(L, ND1)) {
-        set_error("Sigma block is not positive definite (needed by the split form)");
-        flare_model_destroy(m);
-        return FLARE_E_ARG;
-      }
       int rc = FLARE_OK;
       if (precision == FLARE_BF16_SPLIT) {
         const size_t per = (size_t)5 * ncb * 2 * 64 * 8;
@@ -290,41 +335,16 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
         flare_model_destroy(m);
         return rc;
       }
-      // FP32 fragments of L replace the Sigma part (part 1) of Wf
-      std::vector<float> f((size_t)nkc * ncb * 64 * 4);
-      for (int kc = 0; kc < nkc; ++kc)
-        for (int cb = 0; cb < ncb; ++cb)
-          for (int lane = 0; lane < 64; ++lane)
-            for (int t = 0; t < 4; ++t) {
-              const int k = kc * 16 + 4 * (lane / 16) + t, col = cb * 16 + lane % 16;
-              f[(((size_t)kc * ncb + cb) * 64 + lane) * 4 + t] = (float)L[(size_t)k * ND1 + col];
-            }
-      hipError_t e = hipMemcpy(m->Wf[b] + (size_t)nkc * ncb * 64 * 4, f.data(), f.size() * sizeof(float),
-                               hipMemcpyHostToDevice);
-      if (e != hipSuccess) {
-        set_error(std::string("model upload: ") + hipGetErrorString(e));
-        flare_model_destroy(m);
-        return FLARE_E_HIP;
-      }
-    }
-    for (int s = 0; s < NS; ++s) {
-      std::vector<double> L(sigma_host + (size_t)s * ND * ND, sigma_host + (size_t)(s + 1) * ND * ND);
-      if (!cholesky(L, ND)) {
-        set_error("Sigma is not positive definite (needed by the split form)");
-        flare_model_destroy(m);
-        return FLARE_E_ARG;
-      }
-      std::vector<float> lt((size_t)ND * ND);   // row n = column n of L
-      for (int n = 0; n < ND; ++n)
-        for (int k = 0; k < ND; ++k) lt[(size_t)n * ND + k] = (float)L[(size_t)k * ND + n];
-      int rc = upload((void**)&m->Lx[s], lt.data(), lt.size() * sizeof(float));
-      if (rc != FLARE_OK) {
-        flare_model_destroy(m);
-        return rc;
-      }
     }
   }
   *out = m;
+  return FLARE_OK;
+}
+
+int flare_model_info(const flare_model* m, int* precision, int* variance_cholesky) {
+  ARG(m, "null model");
+  if (precision) *precision = m->precision;
+  if (variance_cholesky) *variance_cholesky = m->vchol ? 1 : 0;
   return FLARE_OK;
 }
 
@@ -754,7 +774,7 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
     b += 4LL * 2 * ND1 * ND1 * sizeof(float);
     if (m->precision == FLARE_BF16_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * 8 * sizeof(uint16_t);
     if (m->precision == FLARE_FP8_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * sizeof(uint64_t);
-    if (m->precision != FLARE_FP32) b += 2LL * ND * ND * sizeof(float);
+    if (m->vchol) b += 2LL * ND * ND * sizeof(float);
   }
   if (s) {
     b += s->fixed_bytes;

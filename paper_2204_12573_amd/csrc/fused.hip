@@ -44,6 +44,7 @@ struct FusedArgs {
   const uint64_t* W8[4]; // FP8 split form: s_b beta as [ks 5][cb 9][hi/lo' 2][lane 64] x 8 e4m3
   float bscale[4];       // FP8 split form: s_b per bucket (a power of two)
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
+  int vchol;             // part 1 of Wf holds the Cholesky factor L: V = |L^T d|^2
   float* G;              // [tiles][144][128]: g (no forces here), or the densities of each
                          // tile between its descriptor and adjoint phases (forces here)
   float4* w;             // per-slot adjoint terms (written when the forces are formed here)
@@ -376,7 +377,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
   f4 acc[2][NCB];
   float dots[2][4];
   if (a.mode & 2) {
-    if (PREC != FLARE_FP32) {
+    if (PREC != FLARE_FP32 || a.vchol) {
       mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);   // Z = D L on FP32 cores, L lower-triangular
       row_sumsq(acc, dots);
     } else {
@@ -546,6 +547,7 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     a.W8[k] = s->model->W8[k];
     a.bscale[k] = s->model->beta_scale[k];
   }
+  a.vchol = s->model->vchol ? 1 : 0;
   a.G = s->G1.p;
   a.w = s->w_slot.p;
   a.nrm = s->nrm;

@@ -36,6 +36,7 @@ struct QArgs {
   float* P;              // [rows][4]       partial row-dots, split path
   int mode;              // bit 0: beta part, bit 1: Sigma part
   int sumsq;             // Sigma part given as its Cholesky factor L: V = |d L|^2
+  int tri;               // W is lower-triangular L: K chunks above a column tile are zero
   int pbase;             // first partial slot written by this launch
   int nbk;               // buckets in this launch
   int row0[4];           // first row of each bucket (padded to TM)
@@ -107,10 +108,12 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
 #pragma unroll
     for (int j = 0; j < CB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  QF_GLOAD(0);
-  QF_LSTORE(0);
+  // with W = L (row n of W = column n of L, zero for k < n) the chunks k < first column vanish
+  const int c0 = q.tri ? (ntile * NC) / KC : 0;
+  QF_GLOAD(c0);
+  QF_LSTORE(c0 & 1);
   __syncthreads();
-  for (int c = 0; c < NCHUNK; ++c) {
+  for (int c = c0; c < NCHUNK; ++c) {
     const int buf = c & 1;
     if (c + 1 < NCHUNK) QF_GLOAD(c + 1);
     float4 a[RB];
@@ -255,7 +258,7 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   }
   // split form: the Sigma columns come from L (V = |d L|^2); with both parts the kernel
   // reads the beta rows of W then continues into L through a second launch
-  q.sumsq = m->precision != FLARE_FP32 ? 1 : 0;
+  q.sumsq = m->vchol ? 1 : 0;
   q.D = s->Dx.p;
   q.G = s->Gx.p;
   q.aor = s->atom_of_rowx.p;
@@ -273,6 +276,7 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
     QArgs qv = q;
     qv.mode = 2;
     qv.pbase = (mode & 1) ? 2 : 0;
+    qv.tri = 1;
     for (int k = 0; k < 2; ++k) qv.W[k] = m->Lx[k];
     k_qform<ND, 17, false, 1><<<dim3(rows / 64, 2), NTQ, 0, s->stream>>>(qv);
   } else {

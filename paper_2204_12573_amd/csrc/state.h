@@ -82,6 +82,8 @@ struct RedTask {
 struct flare_model {
   int device = 0;
   int precision = FLARE_FP32;
+  // variances from Cholesky factors (part 1 of Wf holds L, Lx the 544-wide factors)
+  bool vchol = false;
   double r_cut = 0.0;
   // Per bucket: [2*nb][nb] row-major; rows 0..nb-1 hold the beta sub-block and rows
   // nb..2nb-1 the Sigma sub-block of the central species, restricted to the bucket's

@@ -30,10 +30,17 @@ class Model:
         d = ctypes.c_int()
         B.check(lib.flare_descriptor_dim(h, ctypes.byref(d)))
         self.n_desc = d.value
+        p, c = ctypes.c_int(), ctypes.c_int()
+        B.check(lib.flare_model_info(h, ctypes.byref(p), ctypes.byref(c)))
+        self.precision = p.value
+        self.variance_cholesky = bool(c.value)   # V = |L^T d|^2 (else the full Sigma)
 
     def __del__(self):
         if getattr(self, "handle", None):
-            B.load().flare_model_destroy(self.handle)
+            try:
+                B.load().flare_model_destroy(self.handle)
+            except (AttributeError, TypeError):   # interpreter shutdown: module already gone
+                pass
             self.handle = None
 
 

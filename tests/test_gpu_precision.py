@@ -58,9 +58,12 @@ def test_split_form_random_models(case, prec):
 
 def test_near_cancelling_variance():
     """Sigma_s = gamma_s of a sparse GP whose sparse set contains half the environments:
-    V = sigma^2 - (a term of nearly the same size). FP32 d^T gamma d loses about
-    log10(sigma^2/V) digits; |L^T d|^2 loses about half as many (its error follows the
-    FP32 rounding of d through L, of size sqrt(sigma^2/V))."""
+    V = sigma^2 - (a term of nearly the same size). A direct FP32 d^T gamma d loses about
+    log10(sigma^2/V) digits; |L^T d|^2 with the FP64 Cholesky factor (what the library
+    evaluates whenever the Sigma blocks are positive definite, in every form) loses about
+    half as many (its error follows the FP32 rounding of d through L, of size sqrt(sigma^2/V)).
+    The direct product is formed here with torch FP32 on the exported descriptors."""
+    import torch
     st = S.config_tiny()
     beta, _ = S.random_model(DEFAULT.n_desc)
     d = oev.evaluate(st.pos, st.species, st.box, beta, beta, want_forces=False).d
@@ -69,12 +72,38 @@ def test_near_cancelling_variance():
     ref = oev.evaluate(st.pos, st.species, st.box, beta, gamma)
     out = {}
     for name, prec in [("fp32", Bd.FP32), ("split", Bd.BF16_SPLIT), ("fp8", Bd.FP8_SPLIT)]:
-        res = gpu_eval(st.pos, st.species, st.box, beta, gamma, precision=prec)
+        res = gpu_eval(st.pos, st.species, st.box, beta, gamma, precision=prec, want_d=(name == "fp32"))
         out[name] = float(np.max(np.abs(res["var"] - ref.v) / ref.v))
+        if name == "fp32":
+            torch.backends.cuda.matmul.allow_tf32 = False
+            dd = torch.from_numpy(res["d"]).cuda()
+            g = torch.from_numpy(gamma.astype(np.float32)).cuda()
+            sp = torch.from_numpy(st.species.astype(np.int64)).cuda()
+            v_direct = ((dd @ g[0]) * dd).sum(1) * (sp == 0) + ((dd @ g[1]) * dd).sum(1) * (sp == 1)
+            out["direct_fp32"] = float(np.max(np.abs(v_direct.cpu().numpy() - ref.v) / ref.v))
     print("pointwise relative error of V:", out, "V/sigma^2 range:", ref.v.min() / sigma2, ref.v.max() / sigma2)
     assert ref.v.min() < 1e-3 * sigma2              # genuinely near-cancelling
-    assert out["split"] <= 2e-4 and out["fp8"] <= 2e-4
-    assert out["split"] < out["fp32"] / 5
+    for name in ("fp32", "split", "fp8"):
+        assert out[name] <= 2e-4
+        assert out[name] < out["direct_fp32"] / 5
+
+
+def test_fp32_full_sigma_when_not_positive_definite():
+    """A rank-deficient Sigma has no Cholesky factor: the FP32 form then evaluates d^T Sigma d
+    with the full matrix (the split forms refuse such a model)."""
+    st = S.config_tiny()
+    beta, _ = S.random_model(DEFAULT.n_desc)
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((2, DEFAULT.n_desc, 40))
+    sigma = 1e-3 * np.einsum("sik,sjk->sij", a, a) / 40      # PSD, rank 40
+    print("case: rank-deficient Sigma, FP32", flush=True)
+    res = gpu_eval(st.pos, st.species, st.box, beta, sigma, precision=Bd.FP32)
+    ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
+    errs = _errs(res, ref)
+    print(errs)
+    assert errs["e"] <= 1e-5 and errs["f"] <= 1e-5 and errs["sigma"] <= 1e-5
+    with pytest.raises(Bd.FlareError):
+        gpu_eval(st.pos, st.species, st.box, beta, sigma, precision=Bd.BF16_SPLIT)
 
 
 @pytest.mark.parametrize("prec", PREC)
