@@ -1,10 +1,10 @@
-// Mapped quadratic forms over atoms (paper, Eq. 1 and Eq. 2 after the exact mapping of
-// Section V.B): for the descriptor rows D of one environment bucket,
-//   Y = D [beta_b | Sigma_b]        (dense GEMM on the FP32 matrix cores, FP32 accumulate)
-//   e_i = sum_k Y_ik D_ik  over the beta columns,   V_i = the same over the Sigma columns
-//   g_i = (2/|d~_i|) (Y_i - e_i d_i)               (de_i/dd~_i, used by the adjoint)
-// beta_b / Sigma_b are the central species' matrices restricted to the bucket's
-// descriptor block (144 x 144 for single-species environments, 544 x 544 otherwise).
+// Mapped quadratic forms of the mixed-environment rows (paper, Eq. 1 and Eq. 2 after the
+// exact mapping of Section V.B): for the 544-wide descriptor rows D of a bucket,
+//   Y = D beta_s (dense GEMM on the FP32 matrix cores, FP32 accumulate), e_i = Y_i . D_i,
+//   V_i = D_i . Sigma_s D_i, or |L_s^T D_i|^2 with the Cholesky factor of Sigma_s,
+//   g_i = (2/|d~_i|) (Y_i - e_i d_i)  (de_i/dd~_i, used by the adjoint; k_qform_finish).
+// A launch covers column tiles of 272: the beta part first, then the Sigma part; each
+// tile writes its partial row sums, the beta tiles also Y.
 //
 // Tiling: a work-group of 4 waves owns 64 RB rows; each wave owns RB 16-row blocks x CB
 // 16-column blocks, accumulated by v_mfma_f32_16x16x4_f32. K advances in
@@ -27,24 +27,19 @@ constexpr int LDSW = KC + 4;    // padded LDS row (floats)
 
 struct QArgs {
   const float* D;        // [rows][KD]
-  float* G;              // [rows][KD]      gradient (beta part), fused path
   const int* aor;        // atom of row (-1 padding)
-  const float* nrm;      // |d~| per atom
-  float* e_int;          // per atom
-  float* v_int;          // per atom
-  float* Y;              // [rows][KD]      beta-part products, split path
-  float* P;              // [rows][4]       partial row-dots, split path
+  float* Y;              // [rows][KD]      beta-part products
+  float* P;              // [rows][4]       partial row sums of each column tile
   int mode;              // bit 0: beta part, bit 1: Sigma part
   int sumsq;             // Sigma part given as its Cholesky factor L: V = |d L|^2
-  int tri;               // W is lower-triangular L: K chunks above a column tile are zero
-  int pbase;             // first partial slot written by this launch
   int nbk;               // buckets in this launch
   int row0[4];           // first row of each bucket (padded to TM)
   int row1[4];           // one past its last padded row
   const float* W[4];     // [(parts)*KD][KD] row n = column n of [beta | Sigma]
+  const float* L[4];     // sumsq: [KD][KD] row n = column n of the Cholesky factor of Sigma
 };
 
-template <int KD, int CB, bool FUSED, int RB>
+template <int KD, int CB, int RB>
 __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
   constexpr int TM = 4 * RB * 16;              // rows per work-group
   constexpr int NC = CB * 16;                  // columns per work-group
@@ -56,12 +51,16 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
   const int tile = blockIdx.x;
   const int ntile = blockIdx.y;
   const int row0 = tile * TM;
+  // column tiles: the beta part first (if any), then the Sigma part, from L when sumsq
+  const int nbeta = (q.mode & 1) ? KD / NC : 0;
+  const bool lpart = q.sumsq && ntile >= nbeta;
   // bucket of this tile (static indexing keeps the argument arrays out of scratch)
-  const float* Wb = q.W[0];
+  const float* Wb = lpart ? q.L[0] : q.W[0];
 #pragma unroll
   for (int k = 1; k < 4; ++k)
-    if (k < q.nbk && row0 >= q.row0[k] && row0 < q.row1[k]) Wb = q.W[k];
-  const float* __restrict__ W = Wb + (size_t)ntile * NC * KD;
+    if (k < q.nbk && row0 >= q.row0[k] && row0 < q.row1[k]) Wb = lpart ? q.L[k] : q.W[k];
+  const int ct = lpart ? ntile - nbeta : ntile;
+  const float* __restrict__ W = Wb + (size_t)ct * NC * KD;
   const float* __restrict__ D = q.D;
 
   const int t = threadIdx.x;
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
     for (int j = 0; j < CB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   // with W = L (row n of W = column n of L, zero for k < n) the chunks k < first column vanish
-  const int c0 = q.tri ? (ntile * NC) / KC : 0;
+  const int c0 = lpart ? (ct * NC) / KC : 0;
   QF_GLOAD(c0);
   QF_LSTORE(c0 & 1);
   __syncthreads();
@@ -163,30 +162,11 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row0 + wave * RB * 16 + i * 16 + 4 * grp + r;
-      const int atom = q.aor[row];
-      if (FUSED) {
-        if (atom >= 0 && l16 == 0) {
-          if (has_e) q.e_int[atom] = pe[r];
-          if (q.mode & 2) q.v_int[atom] = pv[r];
-        }
-        if (has_e) {
-          const float nv = atom >= 0 ? q.nrm[atom] : 0.f;
-          const float s2 = nv > 0.f ? 2.f / nv : 0.f;
-          const float* drow = D + (size_t)row * KD;
-          float* grow = q.G + (size_t)row * KD;
+      if (l16 == 0) q.P[(size_t)row * 4 + ntile] = has_e && col_base < KD ? pe[r] : pv[r];
+      if (has_e && col_base < KD) {
+        float* yrow = q.Y + (size_t)row * KD;
 #pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            const int col = j * 16 + l16;
-            if (col < KD) grow[col] = s2 * (acc[i][j][r] - pe[r] * drow[col]);
-          }
-        }
-      } else {
-        if (l16 == 0) q.P[(size_t)row * 4 + q.pbase + ntile] = has_e && col_base < KD ? pe[r] : pv[r];
-        if (has_e && col_base < KD) {
-          float* yrow = q.Y + (size_t)row * KD;
-#pragma unroll
-          for (int j = 0; j < CB; ++j) yrow[col_base + j * 16 + l16] = acc[i][j][r];
-        }
+        for (int j = 0; j < CB; ++j) yrow[col_base + j * 16 + l16] = acc[i][j][r];
       }
     }
   }
@@ -245,9 +225,6 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   const flare_model* m = s->model;
   QArgs q{};
   q.mode = mode;
-  q.nrm = s->nrm;
-  q.e_int = s->e_int;
-  q.v_int = s->v_int;
   q.nbk = 2;
   for (int k = 0; k < 2; ++k) {
     const int bk = 4 + k;
@@ -256,32 +233,16 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
     q.row1[k] = s->bucket_row0[bk] + padded;
     q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)ND * ND);
   }
-  // split form: the Sigma columns come from L (V = |d L|^2); with both parts the kernel
-  // reads the beta rows of W then continues into L through a second launch
+  // with Cholesky factors the Sigma columns come from L (V = |d L|^2)
   q.sumsq = m->vchol ? 1 : 0;
+  for (int k = 0; k < 2; ++k) q.L[k] = m->Lx[k];
   q.D = s->Dx.p;
-  q.G = s->Gx.p;
   q.aor = s->atom_of_rowx.p;
   q.Y = s->Yx.p;
   q.P = s->Px.p;
   const int parts = ((mode & 1) ? 1 : 0) + ((mode & 2) ? 1 : 0);
   const int ntiles = 2 * parts;   // 272 columns per tile
-  if (q.sumsq && (mode & 2)) {
-    // beta tiles (if any) from W, Sigma tiles from L, partials in the same slots
-    if (mode & 1) {
-      QArgs qe = q;
-      qe.mode = 1;
-      k_qform<ND, 17, false, 1><<<dim3(rows / 64, 2), NTQ, 0, s->stream>>>(qe);
-    }
-    QArgs qv = q;
-    qv.mode = 2;
-    qv.pbase = (mode & 1) ? 2 : 0;
-    qv.tri = 1;
-    for (int k = 0; k < 2; ++k) qv.W[k] = m->Lx[k];
-    k_qform<ND, 17, false, 1><<<dim3(rows / 64, 2), NTQ, 0, s->stream>>>(qv);
-  } else {
-    k_qform<ND, 17, false, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
-  }
+  k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
   k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
                                                         s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int);
 }
