@@ -36,30 +36,33 @@ __device__ __forceinline__ void poly_grad_dot(const float* A, float x, float y, 
 
 // w = de_i/dDelta for one pair from the adjoint densities u[n][lm] of the neighbour's
 // species (all 16 (l, m) in one thread).
+// The radial sums are taken per (l, m): A_lm = sum_n u_{n,lm} R_n and B_lm = sum_n
+// u_{n,lm} R_n', so that sum_n (R_n' Z_n - R_n Zl_n / r) = sum_lm Y_lm (B_lm - (l/r) A_lm).
 template <class U>
 __device__ __forceinline__ void pair_force(const PairGeom& pg, float rc, U u, float& wx, float& wy,
                                            float& wz) {
   float R[NR], dR[NR], Y[NLM];
   radial_d(pg.r, rc, R, dR);
   sph_harm(pg.ux, pg.uy, pg.uz, Y);
-  float A[NLM];
+  float A[NLM], B[NLM];
 #pragma unroll
-  for (int lm = 0; lm < NLM; ++lm) A[lm] = 0.f;
-  float s1 = 0.f;
-  const float inv_r = 1.f / pg.r;
+  for (int lm = 0; lm < NLM; ++lm) {
+    A[lm] = 0.f;
+    B[lm] = 0.f;
+  }
 #pragma unroll
-  for (int n = 0; n < NR; ++n) {
-    float S[LMAX + 1] = {0.f, 0.f, 0.f, 0.f};
+  for (int n = 0; n < NR; ++n)
 #pragma unroll
     for (int lm = 0; lm < NLM; ++lm) {
       const float un = u(n, lm);
-      S[lm_l(lm)] += un * Y[lm];
       A[lm] += un * R[n];
+      B[lm] += un * dR[n];
     }
-    const float z = S[0] + S[1] + S[2] + S[3];
-    const float zl = S[1] + 2.f * S[2] + 3.f * S[3];
-    s1 += dR[n] * z - R[n] * zl * inv_r;
-  }
+  const float inv_r = __builtin_amdgcn_rcpf(pg.r);   // 1 ulp; r >= the shortest pair distance
+  const float il[LMAX + 1] = {0.f, inv_r, 2.f * inv_r, 3.f * inv_r};
+  float s1 = 0.f;
+#pragma unroll
+  for (int lm = 0; lm < NLM; ++lm) s1 = fmaf(Y[lm], fmaf(-il[lm_l(lm)], A[lm], B[lm]), s1);
   float gx, gy, gz;
   poly_grad_dot(A, pg.ux, pg.uy, pg.uz, gx, gy, gz);
   wx = pg.ux * s1 + gx * inv_r;

@@ -69,9 +69,10 @@ __device__ __forceinline__ void sph_harm_poly_grad(float x, float y, float z, fl
 
 __device__ __forceinline__ int lm_l(int lm) { return lm == 0 ? 0 : (lm < 4 ? 1 : (lm < 9 ? 2 : 3)); }
 
-// R_n(r), n = 0..NR-1
+// R_n(r), n = 0..NR-1. x = r (2/r_c) - 1: the factor 2/r_c is loop-invariant for the
+// callers, which evaluate it once.
 __device__ __forceinline__ void radial(float r, float rc, float* R) {
-  const float x = 2.f * r / rc - 1.f;
+  const float x = r * (2.f / rc) - 1.f;
   const float fc = (rc - r) * (rc - r);
   float t0 = 1.f, t1 = x;
   R[0] = fc;
@@ -85,13 +86,14 @@ __device__ __forceinline__ void radial(float r, float rc, float* R) {
   }
 }
 
-// R_n(r) and dR_n/dr
+// R_n(r) and dR_n/dr = T_n'(x) (2/r_c) f_c + T_n(x) f_c', with T_n' = n U_{n-1}
 __device__ __forceinline__ void radial_d(float r, float rc, float* R, float* dR) {
-  const float x = 2.f * r / rc - 1.f;
+  const float dxdr = 2.f / rc;
+  const float x = r * dxdr - 1.f;
   const float q = rc - r;
   const float fc = q * q;
   const float dfc = -2.f * q;
-  const float dxdr = 2.f / rc;
+  const float cf = dxdr * fc;
   float T[NR], U[NR];
   T[0] = 1.f;
   T[1] = x;
@@ -107,7 +109,7 @@ __device__ __forceinline__ void radial_d(float r, float rc, float* R, float* dR)
 #pragma unroll
   for (int n = 1; n < NR; ++n) {
     R[n] = T[n] * fc;
-    dR[n] = (float)n * U[n - 1] * dxdr * fc + T[n] * dfc;
+    dR[n] = ((float)n * cf) * U[n - 1] + T[n] * dfc;
   }
 }
 

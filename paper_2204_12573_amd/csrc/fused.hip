@@ -19,6 +19,8 @@
 //      gradient tile in LDS and write the per-pair terms w (adjoint.h): g never goes to
 //      HBM. The forces variant runs as a persistent ping-pong kernel (see k_fused144_pp).
 // Inside a 16-wide K chunk, k-step t of lane group q uses k = 4q + t for A and B alike.
+#include <type_traits>
+
 #include "adjoint.h"
 #include "state.h"
 
@@ -54,6 +56,9 @@ struct FusedArgs {
   float* D_out;          // optional [rows][144] normalised descriptors
 };
 
+// TRI: W = L lower-triangular, blocks of chunk kc with column block j > kc vanish. The
+// chunks then run from the last (all 9 column blocks) to the first (1 block), so the
+// loads of the next chunk are always covered by the larger MFMA work of the current one.
 template <int PART, bool TRI = false>
 __device__ __forceinline__ void mfma_pass(const float* As, const float4* __restrict__ W, int wave, int lane,
                                           f4 (&acc)[2][NCB]) {
@@ -64,24 +69,30 @@ __device__ __forceinline__ void mfma_pass(const float* As, const float4* __restr
     for (int j = 0; j < NCB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const float4* Wp = W + (size_t)PART * NKC * NCB * 64 + lane;
   float4 bA[NCB], bB[NCB];
+  constexpr int K0 = TRI ? NKC - 1 : 0;
 #pragma unroll
   for (int j = 0; j < NCB; ++j)
-    if (!TRI || j == 0) bA[j] = Wp[j * 64];
+    if (!TRI || j <= K0) bA[j] = Wp[(K0 * NCB + j) * 64];
 #pragma unroll
-  for (int kc = 0; kc < NKC; ++kc) {
-    float4* cur = (kc & 1) ? bB : bA;
-    float4* nxt = (kc & 1) ? bA : bB;
-    if (kc + 1 < NKC) {
+  for (int it = 0; it < NKC; ++it) {
+    const int kc = TRI ? NKC - 1 - it : it;      // chunk of this iteration
+    const int kn = TRI ? kc - 1 : kc + 1;        // chunk of the next
+    float4* cur = (it & 1) ? bB : bA;
+    float4* nxt = (it & 1) ? bA : bB;
+    if (it + 1 < NKC) {
 #pragma unroll
       for (int j = 0; j < NCB; ++j)
-        if (!TRI || j <= kc + 1) nxt[j] = Wp[((kc + 1) * NCB + j) * 64];
+        if (!TRI || j <= kn) nxt[j] = Wp[(kn * NCB + j) * 64];
     }
     float4 a[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
       a[i] = *reinterpret_cast<const float4*>(&As[(wave * 32 + i * 16 + l16) * AS + kc * 16 + 4 * grp]);
+    // keep the next chunk's loads ahead of this chunk's MFMAs (the scheduler would
+    // otherwise sink them next to their use to shorten live ranges)
+    __builtin_amdgcn_sched_barrier(0);
     // k-step outermost: consecutive MFMAs write different accumulators, so none waits
-    // for the previous result; each accumulator still sees k in increasing order
+    // for the previous result
 #define FQ_STEP(C)                                                                           \
   _Pragma("unroll") for (int j = 0; j < NCB; ++j) {                                         \
     if (TRI && j > kc) continue; /* lower-triangular W: rows k < column j vanish */         \
@@ -270,19 +281,30 @@ __global__ __launch_bounds__(256) void k_fp8_fragments(const float* __restrict__
   out[((size_t)g * 2 + 1) * 64 + lane] = (uint64_t)fp8x8(r);
 }
 
-// Sum of squares of the 8 rows a lane touches (Z = D L, V = |z|^2), accumulated in FP64.
+// Sum of squares of the 8 rows a lane touches (Z = D L, V = |z|^2): the terms are all
+// non-negative, so there is no cancellation; the split forms accumulate in FP64 (the
+// precision form keeps its variance sums FP64), the FP32 form in FP32 (relative rounding
+// below 1e-6 for 144 terms).
+template <bool F64>
 __device__ __forceinline__ void row_sumsq(const f4 (&acc)[2][NCB], float (&out)[2][4]) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      double s = 0.0;
+      if (F64) {
+        double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < NCB; ++j) {
-        const double z = (double)acc[i][j][r];
-        s += z * z;
+        for (int j = 0; j < NCB; ++j) {
+          const double z = (double)acc[i][j][r];
+          s += z * z;
+        }
+        out[i][r] = (float)sum16d(s);
+      } else {
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) s = fmaf(acc[i][j][r], acc[i][j][r], s);
+        out[i][r] = sum16(s);
       }
-      out[i][r] = (float)sum16d(s);
     }
 }
 
@@ -339,7 +361,10 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
   }
   // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
   // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
-  double nrm2 = 0.0;    // |d~|^2 accumulated in FP64
+  // |d~|^2: FP64 in the split forms (their norms stay FP64), FP32 in the FP32 form (144
+  // non-negative terms)
+  typedef typename std::conditional<PREC == FLARE_FP32, float, double>::type NormT;
+  NormT nrm2 = 0;
   float amax = 0.f;     // max |d~_k| (FP8 row scale)
   float* rowp = As + rl * AS + 2 * h;
   int k = 0;
@@ -348,13 +373,13 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
 #pragma unroll
     for (int nb = na; nb < NR; ++nb) {
       const float4 d = b2_half(c[na], c[nb], h);
-      nrm2 += (double)(d.x * d.x + d.y * d.y) + (double)(d.z * d.z + d.w * d.w);
+      nrm2 += (NormT)(d.x * d.x + d.y * d.y) + (NormT)(d.z * d.z + d.w * d.w);
       const float2 mine = h ? make_float2(d.z, d.w) : make_float2(d.x, d.y);
       if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
       *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
       ++k;
     }
-  const float nrm = (float)sqrt(nrm2);
+  const float nrm = (float)sqrt(nrm2);   // sqrtf in the FP32 form
   if (PREC == FLARE_FP8_SPLIT) {
     amax = fmaxf(amax, xor1(amax));
     int ex = 0;
@@ -379,7 +404,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
   if (a.mode & 2) {
     if (PREC != FLARE_FP32 || a.vchol) {
       mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);   // Z = D L on FP32 cores, L lower-triangular
-      row_sumsq(acc, dots);
+      row_sumsq<PREC != FLARE_FP32>(acc, dots);
     } else {
       mfma_pass<1>(As, tm.Wf, wave, lane, acc);
       row_dots(As, acc, wave, lane, dots);
@@ -450,7 +475,11 @@ __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* A
 
 // One tile per work-group, phases in sequence (descriptor export, energies or variances
 // without forces: g leaves as G[tile][k][row]).
-template <int PREC>
+// One tile per work-group, phases in sequence, two work-groups per CU. Without FORCES
+// (descriptor export, energies or variances alone) g leaves as G[tile][k][row]; with
+// FORCES the tile's densities are parked in its slab of G between the descriptor and the
+// adjoint phases and the adjoint runs on the gradient tile in LDS.
+template <int PREC, bool FORCES>
 __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) float As[FR * AS];
   __shared__ float nrm_s[FR];
@@ -458,9 +487,10 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const int t = threadIdx.x;
-  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, nullptr);
+  float* slab = a.G + (size_t)tile * ND1 * FR;
+  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, FORCES ? slab : nullptr);
   __syncthreads();
-  if (a.D_out) {
+  if (!FORCES && a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
       const int r = idx / ND1, k = idx % ND1;
       const float nv = nrm_s[r];
@@ -470,10 +500,13 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   forms_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, tile_model(a, row0));
   if (a.mode & 1) {
     __syncthreads();
-    float* G = a.G + (size_t)tile * ND1 * FR;
-    for (int idx = t; idx < FR * ND1; idx += FT) {
-      const int k = idx >> 7, r = idx & (FR - 1);
-      G[idx] = As[r * AS + k];
+    if (FORCES) {
+      adjoint_phase(a, As, row0, t, slab);
+    } else {
+      for (int idx = t; idx < FR * ND1; idx += FT) {
+        const int k = idx >> 7, r = idx & (FR - 1);
+        slab[idx] = As[r * AS + k];
+      }
     }
   }
 }
@@ -528,6 +561,8 @@ __global__ __launch_bounds__(PT, 1) void k_fused144_pp(FusedArgs a, int ntiles) 
 
 }  // namespace
 
+constexpr bool kSequentialForces = false;
+
 void make_fp8_fragments(const float* vals, int groups, uint64_t* out) {
   k_fp8_fragments<<<(groups * 64 + 255) / 256, 256>>>(vals, groups, out);
 }
@@ -556,6 +591,15 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   a.D_out = d_out;
   const int ntiles = s->rows1 / FR;
   a.mode = mode & 3;
+  if ((mode & 5) == 5 && kSequentialForces) {
+    if (s->model->precision == FLARE_BF16_SPLIT)
+      k_fused144<FLARE_BF16_SPLIT, true><<<ntiles, FT, 0, s->stream>>>(a);
+    else if (s->model->precision == FLARE_FP8_SPLIT)
+      k_fused144<FLARE_FP8_SPLIT, true><<<ntiles, FT, 0, s->stream>>>(a);
+    else
+      k_fused144<FLARE_FP32, true><<<ntiles, FT, 0, s->stream>>>(a);
+    return;
+  }
   if ((mode & 5) == 5) {
     // energies + forces: persistent ping-pong kernel, one work-group per CU
     const int grid = ntiles < 256 ? ntiles : 256;
@@ -568,11 +612,11 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     return;
   }
   if (s->model->precision == FLARE_BF16_SPLIT)
-    k_fused144<FLARE_BF16_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
+    k_fused144<FLARE_BF16_SPLIT, false><<<ntiles, FT, 0, s->stream>>>(a);
   else if (s->model->precision == FLARE_FP8_SPLIT)
-    k_fused144<FLARE_FP8_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
+    k_fused144<FLARE_FP8_SPLIT, false><<<ntiles, FT, 0, s->stream>>>(a);
   else
-    k_fused144<FLARE_FP32><<<ntiles, FT, 0, s->stream>>>(a);
+    k_fused144<FLARE_FP32, false><<<ntiles, FT, 0, s->stream>>>(a);
 }
 
 }  // namespace flare
