@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 METRIC = "M atom-steps/s/GPU (E+F+σ) plain FP32 vs mixed @ force err; p50/p99 serve latency"
 PEAK_FP32_MFMA = 157.3e12      # dense FP32 matrix FLOP/s, MI355X
 PEAK_HBM = 8.0e12              # B/s
+PEAK_FP32_VALU = 78.6e12       # FP32 vector FMA without packed instructions
+# algorithmic vector work beside the quadratic forms (flop): per pair inside the cutoff,
+# densities (basis + 8x16 accumulate) and the adjoint term; per 144-wide row, the B2
+# contraction and the adjoint transform u = G^ c
+VALU_FLOP_DENS, VALU_FLOP_ADJ, VALU_FLOP_B2, VALU_FLOP_U = 320, 600, 1152, 2048
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_fused144_pp_h2_pt111_1M_fp32.txt")
@@ -101,6 +106,28 @@ def md_throughput(engine, torch, st, beta, sigma, steps, warmup, precision):
     tm = ev.read_timers(reset=True)
     ev.timers(False)
     return ev, model, el, tm
+
+
+def valu_work(engine, st):
+    """Pairs inside the cutoff whose centre has a single-species environment (the rows of
+    the fused kernel), from the library's own list of the initial positions."""
+    import numpy as np
+    model = engine.Model(np.zeros((2, 544, 544)), np.zeros((2, 544, 544)))
+    ev = engine.Evaluator(model, max_atoms=st.n, max_pairs=12 * st.n)
+    p, s = engine.to_device(st.pos, st.species)
+    ev.neighbors(p, s, [0, st.n], st.box, 0.2)
+    off, j, sh = ev.export_list()
+    del ev, model
+    cnt = np.diff(off)
+    i = np.repeat(np.arange(st.n), cnt)
+    d = st.pos[j] + sh * st.box - st.pos[i]
+    inside = (d * d).sum(1) < 4.5 ** 2
+    # environment class over the listed pairs, as the library classifies rows
+    spj = st.species[j]
+    n_h = np.bincount(i, weights=(spj == 0), minlength=st.n)
+    n_pt = np.bincount(i, weights=(spj == 1), minlength=st.n)
+    single = (n_h > 0) ^ (n_pt > 0)
+    return {"pairs144": int(np.count_nonzero(inside & single[i]))}
 
 
 def sample_errors(engine, torch, st, beta, sigma, precision, tg, ref):
@@ -213,6 +240,7 @@ def main():
             log(f"  {k:9s} {ms/c*1e3:9.1f} us/launch x {c}")
     vchol = model.variance_cholesky
     del ev, model
+    work = valu_work(engine, st)
 
     # dominant kernel: quadratic forms on the 144-wide rows (beta and Sigma, E+V). Algorithmic
     # flops per row: Y = beta d (2*144^2) and V = |L^T d|^2 through the triangular factor
@@ -229,6 +257,16 @@ def main():
                           "adjoint terms; the MFMA work bounds it, the vector work runs beside it)",
                 "algorithmic_flop_per_launch": flops_per_launch, "algorithmic_flop_per_row": flops_per_row,
                 "variance_form": "cholesky" if vchol else "full", "avg_launch_us": q_ms / q_cnt * 1e3}
+    # FP32 matrix instructions and FP32 vector instructions share one datapath on gfx950
+    # (measured: a wave issuing MFMAs and a wave issuing FMAs on the same SIMD take the sum
+    # of their separate times), so the kernel's lower bound is the MFMA time at the matrix
+    # peak plus the vector work at the non-packed vector peak.
+    valu_flops = work["pairs144"] * (VALU_FLOP_DENS + VALU_FLOP_ADJ) + n144 * (VALU_FLOP_B2 + VALU_FLOP_U)
+    t_min = flops_per_launch / PEAK_FP32_MFMA + valu_flops / PEAK_FP32_VALU
+    roofline["alu_shared"] = {"mfma_flop": flops_per_launch, "valu_flop": int(valu_flops),
+                              "pairs_in_cutoff_144": int(work["pairs144"]),
+                              "t_min_us": t_min * 1e6, "frac": t_min / (q_ms / q_cnt * 1e-3),
+                              "valu_peak_TFLOPs": PEAK_FP32_VALU / 1e12}
     stage_us = {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm.items() if c}
     out = {
         "metric": METRIC,
