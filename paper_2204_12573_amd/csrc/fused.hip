@@ -475,11 +475,9 @@ __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* A
 
 // One tile per work-group, phases in sequence (descriptor export, energies or variances
 // without forces: g leaves as G[tile][k][row]).
-// One tile per work-group, phases in sequence, two work-groups per CU. Without FORCES
-// (descriptor export, energies or variances alone) g leaves as G[tile][k][row]; with
-// FORCES the tile's densities are parked in its slab of G between the descriptor and the
-// adjoint phases and the adjoint runs on the gradient tile in LDS.
-template <int PREC, bool FORCES>
+// One tile per work-group, phases in sequence (descriptor export, energies or variances
+// without forces: g leaves as G[tile][k][row] for the separate adjoint kernel).
+template <int PREC>
 __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) float As[FR * AS];
   __shared__ float nrm_s[FR];
@@ -487,10 +485,9 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const int t = threadIdx.x;
-  float* slab = a.G + (size_t)tile * ND1 * FR;
-  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, FORCES ? slab : nullptr);
+  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, nullptr);
   __syncthreads();
-  if (!FORCES && a.D_out) {
+  if (a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
       const int r = idx / ND1, k = idx % ND1;
       const float nv = nrm_s[r];
@@ -500,13 +497,10 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   forms_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, tile_model(a, row0));
   if (a.mode & 1) {
     __syncthreads();
-    if (FORCES) {
-      adjoint_phase(a, As, row0, t, slab);
-    } else {
-      for (int idx = t; idx < FR * ND1; idx += FT) {
-        const int k = idx >> 7, r = idx & (FR - 1);
-        slab[idx] = As[r * AS + k];
-      }
+    float* G = a.G + (size_t)tile * ND1 * FR;
+    for (int idx = t; idx < FR * ND1; idx += FT) {
+      const int k = idx >> 7, r = idx & (FR - 1);
+      G[idx] = As[r * AS + k];
     }
   }
 }
@@ -561,8 +555,6 @@ __global__ __launch_bounds__(PT, 1) void k_fused144_pp(FusedArgs a, int ntiles) 
 
 }  // namespace
 
-constexpr bool kSequentialForces = false;
-
 void make_fp8_fragments(const float* vals, int groups, uint64_t* out) {
   k_fp8_fragments<<<(groups * 64 + 255) / 256, 256>>>(vals, groups, out);
 }
@@ -591,15 +583,6 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   a.D_out = d_out;
   const int ntiles = s->rows1 / FR;
   a.mode = mode & 3;
-  if ((mode & 5) == 5 && kSequentialForces) {
-    if (s->model->precision == FLARE_BF16_SPLIT)
-      k_fused144<FLARE_BF16_SPLIT, true><<<ntiles, FT, 0, s->stream>>>(a);
-    else if (s->model->precision == FLARE_FP8_SPLIT)
-      k_fused144<FLARE_FP8_SPLIT, true><<<ntiles, FT, 0, s->stream>>>(a);
-    else
-      k_fused144<FLARE_FP32, true><<<ntiles, FT, 0, s->stream>>>(a);
-    return;
-  }
   if ((mode & 5) == 5) {
     // energies + forces: persistent ping-pong kernel, one work-group per CU
     const int grid = ntiles < 256 ? ntiles : 256;
@@ -612,11 +595,11 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     return;
   }
   if (s->model->precision == FLARE_BF16_SPLIT)
-    k_fused144<FLARE_BF16_SPLIT, false><<<ntiles, FT, 0, s->stream>>>(a);
+    k_fused144<FLARE_BF16_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
   else if (s->model->precision == FLARE_FP8_SPLIT)
-    k_fused144<FLARE_FP8_SPLIT, false><<<ntiles, FT, 0, s->stream>>>(a);
+    k_fused144<FLARE_FP8_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
   else
-    k_fused144<FLARE_FP32, false><<<ntiles, FT, 0, s->stream>>>(a);
+    k_fused144<FLARE_FP32><<<ntiles, FT, 0, s->stream>>>(a);
 }
 
 }  // namespace flare
