@@ -67,38 +67,41 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
   const int lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, grp = lane >> 4;
 
-  // global -> register staging: A 512 float4 (2 per thread), B NC*4 float4
+  // global -> register staging of one K chunk: A TM*KC/4 float4, B NC*KC/4 float4 (the
+  // last B round is partial); kept in named registers (an indexed array ends in scratch)
   constexpr int A_F4 = TM * KC / 4;
   constexpr int B_F4 = NC * KC / 4;
-  constexpr int A_PER = A_F4 / NTQ;
-  constexpr int B_PER = (B_F4 + NTQ - 1) / NTQ;
-  float4 ra[A_PER], rb[B_PER];
-
+  static_assert(A_F4 == NTQ, "one A float4 per thread");
+  static_assert(B_F4 > 4 * NTQ && B_F4 <= 5 * NTQ, "four full B rounds and a partial one");
+  float4 ra, rb0, rb1, rb2, rb3, rb4;
+  const bool b4 = t + 4 * NTQ < B_F4;
+  auto bsrc = [&](int u, int k0) {
+    const int idx = t + u * NTQ;
+    return reinterpret_cast<const float4*>(W + (size_t)(idx >> 2) * KD + k0 + (idx & 3) * 4);
+  };
+  auto bdst = [&](int u, int buf) {
+    const int idx = t + u * NTQ;
+    return reinterpret_cast<float4*>(&Bs[buf][(idx >> 2) * LDSW + (idx & 3) * 4]);
+  };
 #define QF_GLOAD(chunk)                                                                       \
   do {                                                                                        \
     const int k0_ = (chunk) * KC;                                                             \
-    _Pragma("unroll") for (int u = 0; u < A_PER; ++u) {                                       \
-      const int idx = t + u * NTQ;                                                            \
-      ra[u] = *reinterpret_cast<const float4*>(D + (size_t)(row0 + (idx >> 2)) * KD + k0_ +   \
-                                               (idx & 3) * 4);                                \
-    }                                                                                         \
-    _Pragma("unroll") for (int u = 0; u < B_PER; ++u) {                                       \
-      int idx = t + u * NTQ;                                                                  \
-      idx = idx < B_F4 ? idx : B_F4 - 1;                                                      \
-      rb[u] = *reinterpret_cast<const float4*>(W + (size_t)(idx >> 2) * KD + k0_ + (idx & 3) * 4); \
-    }                                                                                         \
+    ra = *reinterpret_cast<const float4*>(D + (size_t)(row0 + (t >> 2)) * KD + k0_ + (t & 3) * 4); \
+    rb0 = *bsrc(0, k0_);                                                                      \
+    rb1 = *bsrc(1, k0_);                                                                      \
+    rb2 = *bsrc(2, k0_);                                                                      \
+    rb3 = *bsrc(3, k0_);                                                                      \
+    if (b4) rb4 = *bsrc(4, k0_);                                                              \
   } while (0)
 
 #define QF_LSTORE(buf)                                                                        \
   do {                                                                                        \
-    _Pragma("unroll") for (int u = 0; u < A_PER; ++u) {                                       \
-      const int idx = t + u * NTQ;                                                            \
-      *reinterpret_cast<float4*>(&As[buf][(idx >> 2) * LDSW + (idx & 3) * 4]) = ra[u];        \
-    }                                                                                         \
-    _Pragma("unroll") for (int u = 0; u < B_PER; ++u) {                                       \
-      const int idx = t + u * NTQ;                                                            \
-      if (idx < B_F4) *reinterpret_cast<float4*>(&Bs[buf][(idx >> 2) * LDSW + (idx & 3) * 4]) = rb[u]; \
-    }                                                                                         \
+    *reinterpret_cast<float4*>(&As[buf][(t >> 2) * LDSW + (t & 3) * 4]) = ra;                 \
+    *bdst(0, buf) = rb0;                                                                      \
+    *bdst(1, buf) = rb1;                                                                      \
+    *bdst(2, buf) = rb2;                                                                      \
+    *bdst(3, buf) = rb3;                                                                      \
+    if (b4) *bdst(4, buf) = rb4;                                                              \
   } while (0)
 
   f4 acc[RB][CB];
@@ -119,17 +122,22 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
 #pragma unroll
     for (int i = 0; i < RB; ++i)
       a[i] = *reinterpret_cast<const float4*>(&As[buf][(wave * RB * 16 + i * 16 + l16) * LDSW + 4 * grp]);
+    float4 bv[CB];
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      const float4 bv = *reinterpret_cast<const float4*>(&Bs[buf][(j * 16 + l16) * LDSW + 4 * grp]);
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, bv.x, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, bv.y, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, bv.z, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, bv.w, acc[i][j], 0, 0, 0);
-      }
-    }
+    for (int j = 0; j < CB; ++j) bv[j] = *reinterpret_cast<const float4*>(&Bs[buf][(j * 16 + l16) * LDSW + 4 * grp]);
+    // k-step outermost (consecutive MFMAs write different accumulators); with W = L the
+    // column block ct*CB + j has no entries in chunks c below it
+#define QF_STEP(C)                                                                              \
+  _Pragma("unroll") for (int j = 0; j < CB; ++j) {                                             \
+    if (lpart && c < ct * CB + j) continue;                                                    \
+    _Pragma("unroll") for (int i = 0; i < RB; ++i)                                             \
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].C, bv[j].C, acc[i][j], 0, 0, 0);   \
+  }
+    QF_STEP(x)
+    QF_STEP(y)
+    QF_STEP(z)
+    QF_STEP(w)
+#undef QF_STEP
     if (c + 1 < NCHUNK) QF_LSTORE(buf ^ 1);
     __syncthreads();
   }
