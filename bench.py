@@ -253,8 +253,8 @@ def main():
     achieved = flops_per_launch / (q_ms / q_cnt * 1e-3)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_MFMA, "traffic": profiled_traffic(),
-                "kernel": "k_fused144_pp (144-wide rows: descriptors, D[Sigma] and D[beta] on FP32 MFMA, "
-                          "adjoint terms; the MFMA work bounds it, the vector work runs beside it)",
+                "kernel": "k_fused144_pp (144-wide rows: descriptors, D[L] and D[beta] on FP32 MFMA, adjoint "
+                          "terms; FP32 matrix and vector instructions share the SIMD datapath, see alu_shared)",
                 "algorithmic_flop_per_launch": flops_per_launch, "algorithmic_flop_per_row": flops_per_row,
                 "variance_form": "cholesky" if vchol else "full", "avg_launch_us": q_ms / q_cnt * 1e3}
     # FP32 matrix instructions and FP32 vector instructions share one datapath on gfx950
