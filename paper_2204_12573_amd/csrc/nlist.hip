@@ -135,6 +135,11 @@ __device__ inline void block_bucket_counts(int b, int* __restrict__ blk, int nbl
   if (threadIdx.x < NBUCKET) blk[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// The counting pass (FILL = false) also keeps the first PAIR_CACHE pairs of every atom in
+// cache[c * n + i] (j, packed shift); the filling pass copies them for atoms whose count
+// fits and repeats the search only for the others.
+constexpr int PAIR_CACHE = 24;
+
 template <bool FILL>
 __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict__ grids,
                                               const int* __restrict__ sid,
@@ -146,10 +151,22 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
                                               int* __restrict__ envmask,
                                               int* __restrict__ bucket, int* __restrict__ blk,
                                               int nblk, const int* __restrict__ nl_off,
-                                              int* __restrict__ nl_j, int32_t* __restrict__ nl_s) {
+                                              int* __restrict__ nl_j, int32_t* __restrict__ nl_s,
+                                              int2* __restrict__ cache) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * NT + threadIdx.x;
   int b_out = -1;
+  if (FILL && i < n) {
+    const int o = nl_off[i], c = nl_off[i + 1] - o;
+    if (c <= PAIR_CACHE) {
+      for (int k = 0; k < c; ++k) {
+        const int2 e = cache[(size_t)k * n + i];
+        nl_j[o + k] = e.x;
+        nl_s[o + k] = e.y;
+      }
+      return;
+    }
+  }
   if (i < n) {
     const CellGrid g = grids[sid[i]];
     const int local = bin[i] - g.bin_base;
@@ -188,6 +205,8 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
               if (FILL) {
                 nl_j[o + cnt] = j;
                 nl_s[o + cnt] = pack_shift(sx, sy, sz);
+              } else if (cnt < PAIR_CACHE) {
+                cache[(size_t)cnt * n + i] = make_int2(j, pack_shift(sx, sy, sz));
               }
               mask |= 1 << sp[j];
               ++cnt;
@@ -261,28 +280,38 @@ __global__ __launch_bounds__(NT) void k_slice_len(int n, const int* __restrict__
   atomicMax(&slice_len[global_row(b, row_of[i], rows1) >> 5], cnt[i]);
 }
 
-__global__ __launch_bounds__(NT) void k_fill_slots(int n, const int* __restrict__ bucket,
-                                                   const int* __restrict__ row_of,
+// One thread per row: the row's own pairs into its slots, the rest of its slice length
+// (and every slot of a padding row) marked empty. Writes of a slice's 32 rows are
+// contiguous for each k.
+__global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const int* __restrict__ aor1,
+                                                   const int* __restrict__ aorx,
                                                    const int* __restrict__ nl_off,
                                                    const int* __restrict__ nl_j,
-                                                   const int32_t* __restrict__ nl_s, int rows1,
+                                                   const int32_t* __restrict__ nl_s,
                                                    const int* __restrict__ slice_base,
                                                    int* __restrict__ slot_atom, int* __restrict__ slot_j,
                                                    int* __restrict__ slot_s, int* __restrict__ slot_pair,
                                                    int* __restrict__ slot_of_pair) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  const int b = bucket[i];
-  if (b < 0) return;
-  const int R = global_row(b, row_of[i], rows1);
-  const int p0 = nl_off[i], p1 = nl_off[i + 1];
-  for (int p = p0; p < p1; ++p) {
-    const int slot = slot_of(slice_base, R, p - p0);
-    slot_atom[slot] = i;
-    slot_j[slot] = nl_j[p];
-    slot_s[slot] = nl_s[p];
-    slot_pair[slot] = p;
-    slot_of_pair[p] = slot;
+  const int R = blockIdx.x * NT + threadIdx.x;
+  if (R >= rows) return;
+  const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
+  const int base = slice_base[R >> 5], len = slice_base[(R >> 5) + 1] - base;
+  const int p0 = i >= 0 ? nl_off[i] : 0, own = i >= 0 ? nl_off[i + 1] - p0 : 0;
+  for (int k = 0; k < len; ++k) {
+    const int slot = (base + k) * 32 + (R & 31);
+    if (k < own) {
+      const int p = p0 + k;
+      slot_atom[slot] = i;
+      slot_j[slot] = nl_j[p];
+      slot_s[slot] = nl_s[p];
+      slot_pair[slot] = p;
+      slot_of_pair[p] = slot;
+    } else {
+      slot_atom[slot] = -1;
+      slot_j[slot] = 0;
+      slot_s[slot] = 0;
+      slot_pair[slot] = 0;
+    }
   }
 }
 
@@ -411,10 +440,11 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
                                              species, s->perm, s->sp, s->sid, s->bin, s->w, s->off);
   }
   const double rl2 = s->r_list * s->r_list;
+  HIPCHK(s->pair_cache.reserve((size_t)PAIR_CACHE * n + 1));
   if (n > 0) {
     k_pairs<false><<<nblk, NT, 0, st>>>(n, s->d_grids.p, s->sid, s->bin, s->w, s->sp, s->bin_start.p,
                                          rl2, s->nl_cnt, s->envmask, s->bucket, s->blk_bucket.p, nblk,
-                                         nullptr, nullptr, nullptr);
+                                         nullptr, nullptr, nullptr, s->pair_cache.p);
   }
   scan_exclusive(s->nl_cnt, s->nl_off, n, s->scan_scratch.p, st);
   scan_exclusive(s->blk_bucket.p, s->blk_bucket_scan.p, NBUCKET * nblk, s->scan_scratch.p, st);
@@ -465,7 +495,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   if (n > 0) {
     k_pairs<true><<<nblk, NT, 0, st>>>(n, s->d_grids.p, s->sid, s->bin, s->w, s->sp, s->bin_start.p,
                                         rl2, nullptr, nullptr, nullptr, nullptr, nblk, s->nl_off,
-                                        s->nl_j, s->nl_s);
+                                        s->nl_j, s->nl_s, s->pair_cache.p);
     k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev, s->d_status);
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
@@ -498,14 +528,10 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->geom.reserve(nslots + 1));
   HIPCHK(s->w_slot.reserve(nslots + 1));
   HIPCHK(s->w_in.reserve(nslots + 1));
-  HIPCHK(hipMemsetAsync(s->slot_atom.p, 0xff, (nslots + 1) * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->slot_j.p, 0, (nslots + 1) * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->slot_s.p, 0, (nslots + 1) * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->slot_pair.p, 0, (nslots + 1) * sizeof(int), st));
-  if (n > 0) {
-    k_fill_slots<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, s->nl_off, s->nl_j, s->nl_s, r1, s->slice_base.p,
-                                      s->slot_atom.p, s->slot_j.p, s->slot_s.p, s->slot_pair.p, s->slot_of_pair);
-  }
+  if (r1 + rx > 0)
+    k_fill_slots<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p,
+                                                        s->nl_off, s->nl_j, s->nl_s, s->slice_base.p, s->slot_atom.p,
+                                                        s->slot_j.p, s->slot_s.p, s->slot_pair.p, s->slot_of_pair);
   if (nslots > 0)
     k_rev_slots<<<(int)((nslots + NT - 1) / NT), NT, 0, st>>>(nslots, s->slot_atom.p, s->slot_pair.p, s->nl_rev,
                                                               s->slot_of_pair, s->slot_rev.p);

@@ -185,6 +185,7 @@ struct flare_state {
   flare::DevBuf<float4> geom;                        // per slot, per step
   flare::DevBuf<float4> w_slot;                      // per slot: de_i/dDelta (x, y, z, 0)
   flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
+  flare::DevBuf<int2> pair_cache;                    // list build: first pairs of each atom
   // virial (allocated at the first flare_virial call)
   flare::DevBuf<float> vir_int;                      // [9][max_atoms] per internal atom
   flare::DevBuf<double> red_w;                       // [tasks][9]

@@ -59,7 +59,7 @@ class Footprint:
 
     def bytes(self, n_atoms):
         n, p = self.atoms_pairs(n_atoms)
-        per_atom = 4 * 16 + 8 * 12 + 4 * 6            # int arrays, FP64 SoA, FP32 outputs
+        per_atom = 4 * 16 + 8 * 12 + 4 * 6 + 8 * 24   # int arrays, FP64 SoA, FP32 outputs, pair cache
         per_pair = 4 * 4                                # j, shift, reverse, slot of pair
         per_slot = 4 * 5 + 16 * 2                       # slot ints, geometry, adjoint term
         rows = 2 * 144 * 4                              # descriptor + gradient per 144-wide row
