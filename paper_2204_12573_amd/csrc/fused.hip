@@ -107,6 +107,52 @@ __device__ __forceinline__ void mfma_pass(const float* As, const float4* __restr
   }
 }
 
+// The same passes with one register buffer of B fragments: the fragment of column block j
+// for the next chunk is loaded as soon as the last k-step of the current chunk has used it
+// (36 VGPRs fewer; the remaining MFMAs of the chunk cover the load).
+template <int PART, bool TRI = false>
+__device__ __forceinline__ void mfma_pass_sb(const float* As, const float4* __restrict__ W, int wave, int lane,
+                                             f4 (&acc)[2][NCB]) {
+  const int l16 = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const float4* Wp = W + (size_t)PART * NKC * NCB * 64 + lane;
+  float4 b[NCB];
+  constexpr int K0 = TRI ? NKC - 1 : 0;
+#pragma unroll
+  for (int j = 0; j < NCB; ++j)
+    if (!TRI || j <= K0) b[j] = Wp[(K0 * NCB + j) * 64];
+#pragma unroll
+  for (int it = 0; it < NKC; ++it) {
+    const int kc = TRI ? NKC - 1 - it : it;
+    const int kn = TRI ? kc - 1 : kc + 1;
+    float4 a[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const float4*>(&As[(wave * 32 + i * 16 + l16) * AS + kc * 16 + 4 * grp]);
+#define FQ_STEP(C)                                                                           \
+  _Pragma("unroll") for (int j = 0; j < NCB; ++j) {                                         \
+    if (TRI && j > kc) continue;                                                            \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i)                                           \
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].C, b[j].C, acc[i][j], 0, 0, 0); \
+  }
+    FQ_STEP(x)
+    FQ_STEP(y)
+    FQ_STEP(z)
+#undef FQ_STEP
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+      if (TRI && j > kc) continue;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, b[j].w, acc[i][j], 0, 0, 0);
+      if (it + 1 < NKC && (!TRI || j <= kn)) b[j] = Wp[(kn * NCB + j) * 64];
+    }
+  }
+}
+
 // Split form of the energy pass on v_mfma_f32_16x16x32_bf16: D = D_hi + D_lo and
 // beta = beta_hi + beta_lo in BF16, Y = D_hi beta_hi + D_hi beta_lo + D_lo beta_hi with FP32
 // accumulation (the dropped D_lo beta_lo is ~2^-16 relative). K = 144 runs as five 32-wide
@@ -369,16 +415,18 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
   float* rowp = As + rl * AS + 2 * h;
   int k = 0;
 #pragma unroll
-  for (int na = 0; na < NR; ++na)
+  for (int na = 0; na < NR; ++na) {
 #pragma unroll
     for (int nb = na; nb < NR; ++nb) {
-      const float4 d = b2_half(c[na], c[nb], h);
-      nrm2 += (NormT)(d.x * d.x + d.y * d.y) + (NormT)(d.z * d.z + d.w * d.w);
-      const float2 mine = h ? make_float2(d.z, d.w) : make_float2(d.x, d.y);
+      const float2 mine = b2_half(c[na], c[nb], h);    // this lane's two components
+      nrm2 += (NormT)(mine.x * mine.x + mine.y * mine.y);
       if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
       *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
       ++k;
     }
+  }
+  if (PREC == FLARE_FP32) nrm2 += xor1((float)nrm2);    // the row's other half
+  else nrm2 += xor1d((double)nrm2);
   const float nrm = (float)sqrt(nrm2);   // sqrtf in the FP32 form
   if (PREC == FLARE_FP8_SPLIT) {
     amax = fmaxf(amax, xor1(amax));
@@ -394,7 +442,8 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
 
 // 2/3. quadratic forms and epilogue on a complete descriptor tile; leaves g in the tile
 // when the energy pass runs. Wave w of the 4 owns rows 32w .. 32w + 31.
-template <int PREC>
+// SB: B fragments single-buffered (mfma_pass_sb), for register-limited callers
+template <int PREC, bool SB = false>
 __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const float* nrm_s,
                                             const float* rsc_s, int row0, int t, const TileModel& tm) {
   const int lane = t & 63, wave = t >> 6;
@@ -403,10 +452,13 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
   float dots[2][4];
   if (a.mode & 2) {
     if (PREC != FLARE_FP32 || a.vchol) {
-      mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);   // Z = D L on FP32 cores, L lower-triangular
+      // Z = D L on FP32 cores, L lower-triangular
+      if (SB) mfma_pass_sb<1, true>(As, tm.Wf, wave, lane, acc);
+      else mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);
       row_sumsq<PREC != FLARE_FP32>(acc, dots);
     } else {
-      mfma_pass<1>(As, tm.Wf, wave, lane, acc);
+      if (SB) mfma_pass_sb<1>(As, tm.Wf, wave, lane, acc);
+      else mfma_pass<1>(As, tm.Wf, wave, lane, acc);
       row_dots(As, acc, wave, lane, dots);
     }
     if (l16 == 0) {
@@ -436,7 +488,8 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
           for (int j = 0; j < NCB; ++j) acc[i][j][r] *= inv;
         }
     } else {
-      mfma_pass<0>(As, tm.Wf, wave, lane, acc);
+      if (SB) mfma_pass_sb<0>(As, tm.Wf, wave, lane, acc);
+      else mfma_pass<0>(As, tm.Wf, wave, lane, acc);
     }
     row_dots(As, acc, wave, lane, dots);
 #pragma unroll
@@ -473,8 +526,6 @@ __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* A
   adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
 }
 
-// One tile per work-group, phases in sequence (descriptor export, energies or variances
-// without forces: g leaves as G[tile][k][row]).
 // One tile per work-group, phases in sequence (descriptor export, energies or variances
 // without forces: g leaves as G[tile][k][row] for the separate adjoint kernel).
 template <int PREC>
@@ -546,7 +597,7 @@ __global__ __launch_bounds__(PT, 1) void k_fused144_pp(FusedArgs a, int ntiles) 
         }
       } else if (m < Mg) {
         const int row0 = (wg + nwg * (2 * m + g)) * FR;
-        forms_phase<PREC>(a, A, ns, rs, row0, t, tile_model(a, row0));
+        forms_phase<PREC, true>(a, A, ns, rs, row0, t, tile_model(a, row0));
       }
     }
     __syncthreads();

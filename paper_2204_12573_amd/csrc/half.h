@@ -14,7 +14,7 @@ constexpr int NQ = 8;   // (l, m) indices per lane
 // c[n][q] += R_n Y_{8h+q} over the neighbours of row R inside the cutoff. All rows of a
 // wave share one slice, so the trip count is uniform across the wave.
 __device__ __forceinline__ void accumulate_half(const SlotView& v, int Rw, int h, float (*c)[NQ]) {
-  for_each_slot<6>(v, Rw, [&](const float4& g, int) {
+  for_each_slot<4>(v, Rw, [&](const float4& g, int) {
     PairGeom pg;
     int sp;
     if (!unpack_geom(g, pg, sp)) return;
@@ -30,20 +30,17 @@ __device__ __forceinline__ void accumulate_half(const SlotView& v, int Rw, int h
   });
 }
 
-// One B2 radial pair (a, b) of a single-species block: the four l-components, identical
-// in both lanes of the row. prod_q = c_a,q c_b,q; lane h = 0 holds l = 0 (q0), l = 1
-// (q1..3) and part of l = 2 (q4..7); lane h = 1 the rest of l = 2 (q0) and l = 3 (q1..7).
-__device__ __forceinline__ float4 b2_half(const float* ca, const float* cb, int h) {
+// One B2 radial pair (a, b) of a single-species block, split between the two lanes of
+// the row: lane 0 returns the components l = 0, 1, lane 1 the components l = 2, 3 (the
+// lane's half of the packed float4 at 4k). Products c_a,q c_b,q: lane 0 holds l = 0 (q0),
+// l = 1 (q1..3) and part of l = 2 (q4..7); lane 1 the rest of l = 2 (q0) and l = 3
+// (q1..7). One cross-lane move per pair brings lane 0's part of l = 2 to lane 1.
+__device__ __forceinline__ float2 b2_half(const float* ca, const float* cb, int h) {
   const float v0 = ca[0] * cb[0];
   const float v1 = ca[1] * cb[1] + ca[2] * cb[2] + ca[3] * cb[3];
   const float v2 = ca[4] * cb[4] + ca[5] * cb[5] + ca[6] * cb[6] + ca[7] * cb[7];
-  const float p0 = xor1(v0);
-  const float p1 = xor1(v1);
-  const float p2 = xor1(v2);
-  // (u*) = values of lane h = 0, (w*) = values of lane h = 1
-  const float u0 = h ? p0 : v0, u1 = h ? p1 : v1, u2 = h ? p2 : v2;
-  const float w0 = h ? v0 : p0, w1 = h ? v1 : p1, w2 = h ? v2 : p2;
-  return make_float4(u0, u1, u2 + w0, w1 + w2);
+  const float x = xor1(v2);            // lane 1 receives lane 0's part of l = 2
+  return h ? make_float2(v0 + x, v1 + v2) : make_float2(v0, v1);
 }
 
 }  // namespace flare
