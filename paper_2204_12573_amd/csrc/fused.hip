@@ -15,9 +15,10 @@
 //      tile;
 //   4. either g is copied out coalesced as G[tile][k][row] (the layout the standalone
 //      adjoint kernel reads with one lane pair per row), or, when the forces are wanted
-//      now, the lane pairs recompute their row's densities, form u = G^ c from the
-//      gradient tile in LDS and write the per-pair terms w (adjoint.h): g never goes to
-//      HBM. The forces variant runs as a persistent ping-pong kernel (see k_fused144_pp).
+//      now, the lane pairs take their row's densities back (parked in G by step 1), form
+//      u = G^ c from the gradient tile in LDS and write the per-pair terms w (adjoint.h):
+//      g never goes to HBM. The forces variant runs with every wave on its own 32-row
+//      sub-tiles (k_fused144_w): each of the steps touches only the wave's own rows.
 // Inside a 16-wide K chunk, k-step t of lane group q uses k = 4q + t for A and B alike.
 #include <type_traits>
 
@@ -390,7 +391,7 @@ __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
 // at cstore[(8n + q) * 256 + t] (coalesced), for the adjoint phase of the same tile.
 template <int PREC>
 __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float* nrm_s, float* rsc_s, int row0,
-                                           int t, float* cstore) {
+                                           int t, float* cstore, int cstride = FT) {
   const int rl = t >> 1, h = t & 1;
   const int i = a.aor[row0 + rl];
   float c[NR][NQ];
@@ -403,7 +404,7 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
 #pragma unroll
     for (int n = 0; n < NR; ++n)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) cstore[(n * NQ + q) * FT + t] = c[n][q];
+      for (int q = 0; q < NQ; ++q) cstore[(n * NQ + q) * cstride + t] = c[n][q];
   }
   // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
   // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
@@ -514,14 +515,14 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 // 4. adjoint in place: u = G^ c from the gradient tile, then the per-pair terms. The
 // densities come from cstore (written by desc_phase) instead of a second pass over the pairs.
 __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t,
-                                              const float* cstore) {
+                                              const float* cstore, int cstride = FT) {
   const int rl = t >> 1, h = t & 1;
   if (a.aor[row0 + rl] < 0) return;
   float c[NR][NQ];
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) c[n][q] = cstore[(n * NQ + q) * FT + t];
+    for (int q = 0; q < NQ; ++q) c[n][q] = cstore[(n * NQ + q) * cstride + t];
   u_transform_half(As + rl * AS, 1, h, c);
   adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
 }
@@ -556,51 +557,47 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   }
 }
 
-// Energies, forces (and variances) with the matrix cores and the vector units busy at
-// the same time. One persistent work-group per CU, two groups of 4 waves, each with its
-// own LDS tile. The WG's tiles are wg, wg + nwg, ...; group g takes every other one. In
-// each step one group runs the quadratic forms of its tile (MFMA) while the other runs
-// the adjoint of its previous tile and the descriptors of its next (VALU); a barrier
-// ends the step and the roles swap. Group g's local step p = s - g: even p = 2m runs the
-// adjoint of local tile m - 1 and the descriptors of tile m, odd p = 2m + 1 the forms of
-// tile m. Every thread executes every step's barrier.
-constexpr int PT = 2 * FT;
+// Energies, forces (and variances) with every wave on its own: a wave's rows are touched
+// only by that wave in all three phases (desc_phase: lane pair per row; forms_phase: wave
+// w of a tile owns rows 32w..32w+31; adjoint_phase: lane pair per row), so each wave takes
+// 32-row sub-tiles (its index, then + the number of waves in the grid) and runs
+// descriptors, forms and adjoint on them back to back, with no work-group barrier. The two
+// waves that share a SIMD drift apart, so their vector and matrix work interleave on the
+// shared datapath. Densities are parked in the sub-tile's slice of G (64 lanes x 64 floats
+// fit in its 32 x 144).
+constexpr int WR = 32;          // rows per wave sub-tile
+constexpr int WW = 8;           // waves per work-group
+
+// Between two phases of a wave: orders its LDS accesses (other lanes of the wave read what
+// this lane wrote; the hardware keeps one wave's LDS operations in order) and keeps the
+// compiler from moving memory operations or other work from one phase into the next.
+__device__ __forceinline__ void wave_phase_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
 
 template <int PREC>
-__global__ __launch_bounds__(PT, 1) void k_fused144_pp(FusedArgs a, int ntiles) {
-  __shared__ __attribute__((aligned(16))) float As[2][FR * AS];
-  __shared__ float nrm_s[2][FR];
-  __shared__ float rsc_s[2][FR];
-  const int g = threadIdx.x / FT, t = threadIdx.x % FT;
-  const int wg = blockIdx.x, nwg = gridDim.x;
-  const int J = wg < ntiles ? (ntiles - wg + nwg - 1) / nwg : 0;   // tiles of this work-group
-  const int M0 = (J + 1) / 2, M1 = J / 2;
-  const int Mg = g ? M1 : M0;
-  const int nsteps = max(2 * M0 + 1, 2 * M1 + 2);
-  float* A = As[g];
-  float* ns = nrm_s[g];
-  float* rs = rsc_s[g];
-  for (int s = 0; s < nsteps; ++s) {
-    const int p = s - g;
-    if (p >= 0) {
-      const int m = p >> 1;
-      if ((p & 1) == 0) {
-        if (m >= 1 && m - 1 < Mg) {
-          const int tp = wg + nwg * (2 * (m - 1) + g);
-          adjoint_phase(a, A, tp * FR, t, a.G + (size_t)tp * FR * ND1);
-        }
-        // the lane pair of row r read only row r's gradients above and writes only row r below
-        __builtin_amdgcn_wave_barrier();
-        if (m < Mg) {
-          const int tn = wg + nwg * (2 * m + g);
-          desc_phase<PREC>(a, A, ns, rs, tn * FR, t, a.G + (size_t)tn * FR * ND1);
-        }
-      } else if (m < Mg) {
-        const int row0 = (wg + nwg * (2 * m + g)) * FR;
-        forms_phase<PREC, true>(a, A, ns, rs, row0, t, tile_model(a, row0));
-      }
-    }
-    __syncthreads();
+__global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub) {
+  __shared__ __attribute__((aligned(16))) float As[WW][WR * AS];
+  __shared__ float nrm_s[WW][WR];
+  __shared__ float rsc_s[WW][WR];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = gridDim.x * WW;
+  float* A = As[wv];
+  float* ns = nrm_s[wv];
+  float* rs = rsc_s[wv];
+  for (int st = blockIdx.x * WW + wv; st < nsub; st += nw) {
+    const int row0 = st * WR;
+    float* cs = a.G + (size_t)st * WR * ND1;
+    desc_phase<PREC>(a, A, ns, rs, row0, lane, cs, 64);
+    wave_phase_fence();
+    forms_phase<PREC, false>(a, A, ns, rs, row0, lane, tile_model(a, row0));
+    wave_phase_fence();
+    adjoint_phase(a, A, row0, lane, cs, 64);
+    wave_phase_fence();
   }
 }
 
@@ -635,14 +632,15 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   const int ntiles = s->rows1 / FR;
   a.mode = mode & 3;
   if ((mode & 5) == 5) {
-    // energies + forces: persistent ping-pong kernel, one work-group per CU
-    const int grid = ntiles < 256 ? ntiles : 256;
+    // energies + forces: persistent work-groups, one per CU, waves independent
+    const int nsub = s->rows1 / WR;
+    const int grid = std::min(256, (nsub + WW - 1) / WW);
     if (s->model->precision == FLARE_BF16_SPLIT)
-      k_fused144_pp<FLARE_BF16_SPLIT><<<grid, PT, 0, s->stream>>>(a, ntiles);
+      k_fused144_w<FLARE_BF16_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
     else if (s->model->precision == FLARE_FP8_SPLIT)
-      k_fused144_pp<FLARE_FP8_SPLIT><<<grid, PT, 0, s->stream>>>(a, ntiles);
+      k_fused144_w<FLARE_FP8_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
     else
-      k_fused144_pp<FLARE_FP32><<<grid, PT, 0, s->stream>>>(a, ntiles);
+      k_fused144_w<FLARE_FP32><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
     return;
   }
   if (s->model->precision == FLARE_BF16_SPLIT)

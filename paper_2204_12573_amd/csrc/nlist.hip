@@ -383,6 +383,14 @@ __global__ __launch_bounds__(TILE_ROWS) void k_sort_tile_rows(int* __restrict__ 
   if (i >= 0) row_of[i] = row0 + rank;
 }
 
+// The per-atom counts are non-negative and each is below 2^31, so their int32 prefix sum
+// has run past 2^31 - 1 exactly when one of its entries is negative: then the list does
+// not fit any state (status bit 512).
+__global__ __launch_bounds__(NT) void k_off_check(int n, const int* __restrict__ nl_off, int* __restrict__ status) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i <= n && nl_off[i] < 0) atomicOr(status, 512);
+}
+
 // info[0] = total pairs, info[1..6] = bucket totals, info[7] = status
 __global__ void k_info(int n, const int* __restrict__ nl_off, const int* __restrict__ blk_scan,
                        int nblk, const int* __restrict__ status, int* __restrict__ info) {
@@ -448,6 +456,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   }
   scan_exclusive(s->nl_cnt, s->nl_off, n, s->scan_scratch.p, st);
   scan_exclusive(s->blk_bucket.p, s->blk_bucket_scan.p, NBUCKET * nblk, s->scan_scratch.p, st);
+  k_off_check<<<grid_of(n + 1), NT, 0, st>>>(n, s->nl_off, s->d_status);
   k_info<<<1, 64, 0, st>>>(n, s->nl_off, s->blk_bucket_scan.p, nblk, s->d_status, s->d_info);
   HIPCHK(hipMemcpyAsync(s->h_info, s->d_info, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -461,8 +470,10 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     return FLARE_E_NONFINITE;
   }
   const long long pairs = (long long)(unsigned)s->h_info[0];
-  if (pairs > s->max_pairs) {
-    set_error("list needs " + std::to_string(pairs) + " pairs, state holds " + std::to_string(s->max_pairs));
+  if ((flags & 512) || pairs > s->max_pairs) {
+    set_error((flags & 512) ? std::string("list needs more than 2^31 pairs")
+                            : "list needs " + std::to_string(pairs) + " pairs, state holds " +
+                                  std::to_string(s->max_pairs));
     return FLARE_E_CAPACITY;
   }
   s->n_pairs = pairs;
@@ -519,6 +530,10 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     return FLARE_E_HIP;
   }
   const long long nslots = 32LL * s->h_info[9];
+  if (nslots > 0x7fffffffLL) {
+    set_error("sliced pair layout needs " + std::to_string(nslots) + " slots, more than int32 indexes");
+    return FLARE_E_CAPACITY;
+  }
   s->n_slots = nslots;
   HIPCHK(s->slot_atom.reserve(nslots + 1));
   HIPCHK(s->slot_j.reserve(nslots + 1));
