@@ -31,7 +31,7 @@ PEAK_FP32_VALU = 78.6e12       # FP32 vector FMA without packed instructions
 VALU_FLOP_DENS, VALU_FLOP_ADJ, VALU_FLOP_B2, VALU_FLOP_U = 320, 600, 1152, 2048
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_fused144_pp_h2_pt111_1M_fp32.txt")
+PROFILE = os.path.join(ROOT, "profiles", "k_fused144_w_h2_pt111_1M_fp32.txt")
 
 
 def kernel_sources_sha():
@@ -43,7 +43,7 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def profiled_traffic(kernel="k_fused144_pp<0>"):
+def profiled_traffic(kernel="k_fused144_w<0>"):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
     try:
@@ -250,23 +250,28 @@ def main():
     q_ms, q_cnt = tm["qform144"]
     flops_per_row = 2 * 144 * 144 + (144 * 145 if vchol else 2 * 144 * 144)
     flops_per_launch = n144 * flops_per_row
-    achieved = flops_per_launch / (q_ms / q_cnt * 1e-3)
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA, "traffic": profiled_traffic(),
-                "kernel": "k_fused144_pp (144-wide rows: descriptors, D[L] and D[beta] on FP32 MFMA, adjoint "
-                          "terms; FP32 matrix and vector instructions share the SIMD datapath, see alu_shared)",
-                "algorithmic_flop_per_launch": flops_per_launch, "algorithmic_flop_per_row": flops_per_row,
-                "variance_form": "cholesky" if vchol else "full", "avg_launch_us": q_ms / q_cnt * 1e3}
+    t_launch = q_ms / q_cnt * 1e-3
     # FP32 matrix instructions and FP32 vector instructions share one datapath on gfx950
     # (measured: a wave issuing MFMAs and a wave issuing FMAs on the same SIMD take the sum
-    # of their separate times), so the kernel's lower bound is the MFMA time at the matrix
-    # peak plus the vector work at the non-packed vector peak.
+    # of their separate times), so the kernel is bound by that datapath: its time is at
+    # least the MFMA work at the matrix peak plus the vector work at the non-packed vector
+    # peak. The bound's peak is the blend of the two for this kernel's mix of work.
     valu_flops = work["pairs144"] * (VALU_FLOP_DENS + VALU_FLOP_ADJ) + n144 * (VALU_FLOP_B2 + VALU_FLOP_U)
     t_min = flops_per_launch / PEAK_FP32_MFMA + valu_flops / PEAK_FP32_VALU
-    roofline["alu_shared"] = {"mfma_flop": flops_per_launch, "valu_flop": int(valu_flops),
-                              "pairs_in_cutoff_144": int(work["pairs144"]),
-                              "t_min_us": t_min * 1e6, "frac": t_min / (q_ms / q_cnt * 1e-3),
-                              "valu_peak_TFLOPs": PEAK_FP32_VALU / 1e12}
+    total = flops_per_launch + valu_flops
+    roofline = {"bound": "alu", "achieved": total / t_launch / 1e12, "peak": total / t_min / 1e12,
+                "unit": "TFLOP/s", "frac": t_min / t_launch, "traffic": profiled_traffic(),
+                "kernel": "k_fused144_w (144-wide rows: descriptors, D[L] and D[beta] on FP32 MFMA, adjoint "
+                          "terms; FP32 matrix and vector instructions share the SIMD datapath)",
+                "peak_derivation": "blend of the FP32 MFMA peak (157.3 TFLOP/s) and the non-packed FP32 vector "
+                                   "peak (78.6 TFLOP/s = 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz) "
+                                   "weighted by this kernel's matrix and vector flops",
+                "mfma_flop_per_launch": flops_per_launch, "mfma_flop_per_row": flops_per_row,
+                "valu_flop_per_launch": int(valu_flops), "pairs_in_cutoff_144": int(work["pairs144"]),
+                "t_min_us": t_min * 1e6, "avg_launch_us": t_launch * 1e6,
+                "variance_form": "cholesky" if vchol else "full",
+                "mfma_only": {"achieved": flops_per_launch / t_launch / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                              "frac": flops_per_launch / t_launch / PEAK_FP32_MFMA}}
     stage_us = {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm.items() if c}
     out = {
         "metric": METRIC,
