@@ -303,6 +303,9 @@ def main():
         ev3, m3, el3, tm3 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
                                           binding.FP8_SPLIT)
         del ev3, m3
+        ev6, m6, el6, tm6 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
+                                          binding.BF16X6_SPLIT)
+        del ev6, m6
         log("errors vs the FP64 oracle on a 300-atom sample ...")
         rng = np.random.default_rng(12)
         ztop = 23 * S.DZ
@@ -323,6 +326,13 @@ def main():
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm3.items() if c},
             "note": "energy pass OCP e4m3 x3 with power-of-two row and block scales (d and beta split "
                     "hi/lo'), variance as in the BF16 form; mixed-environment rows FP32"}
+        out["mixed_bf16x6_split"] = {
+            "value": round(n * args.steps / el6 / 1e6, 3), "ms_per_step": round(el6 / args.steps * 1e3, 4),
+            "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.BF16X6_SPLIT, tg, ref),
+            "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm6.items() if c},
+            "note": "both passes on BF16 matrix cores with d, beta and L split into three BF16 parts "
+                    "(x0 + x1 + x2 = the FP32 value), six of the nine part products, FP32 accumulation "
+                    "(FP32-level error); FP64 norms and sums; mixed-environment rows FP32"}
         log("serving ...")
         out["serving"] = serving(engine, torch, beta, sigma, args.serve_requests, 2000.0)
         log("autograd (256 cells) ...")

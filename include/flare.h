@@ -53,9 +53,12 @@ extern "C" {
 #define FLARE_E_UNSUPPORTED -9  /* model sizes this build has no kernels for                    */
 
 /* ---- arithmetic of the quadratic forms ---- */
-/* The split forms change the energy contraction d.beta.d of the single-species rows
- * (144-wide) only: the operands are split into a high and a low part in a narrow format
- * and recombined in FP32 accumulators. The variance d.Sigma.d is computed as |L^T d|^2
+/* The two-part split forms (BF16, FP8) change the energy contraction d.beta.d of the
+ * single-species rows (144-wide) only: the operands are split into a high and a low part
+ * in a narrow format and recombined in FP32 accumulators. The three-way BF16 form splits
+ * d, beta and L into three BF16 parts each (together the 24 significant bits of the FP32
+ * value) and keeps six of the nine part products in both passes, so its error is that of
+ * FP32 arithmetic. The variance d.Sigma.d is computed as |L^T d|^2
  * with the FP64 Cholesky factor L of each Sigma block (stored FP32), a sum of squares
  * that does not cancel, in every form when all Sigma blocks are positive definite (the
  * split forms require it; the FP32 form falls back to the full matrix otherwise). Norms
@@ -64,6 +67,7 @@ extern "C" {
 #define FLARE_FP32        0  /* FP32 matrix cores, FP32 accumulation                          */
 #define FLARE_BF16_SPLIT  1  /* d and beta as BF16 hi + lo, three products per tile          */
 #define FLARE_FP8_SPLIT   2  /* OCP e4m3 hi + lo with power-of-two row and block scales      */
+#define FLARE_BF16X6_SPLIT 3 /* d, beta and L as three BF16 parts, six products: FP32 error  */
 
 /* ---- device status bits (flare_status) ---- */
 #define FLARE_FLAG_NONFINITE  1  /* a position was NaN/inf                                     */
@@ -85,9 +89,9 @@ const char* flare_strerror(int code);
  *   block the radial pairs (n_a, n_b) row-major (n_a <= n_b when s1 == s2), l fastest.
  *   n_d = n_species*n_rad*(n_species*n_rad+1)/2 * (l_max+1).
  * This build has kernels for n_species = 2, n_rad = 8, l_max = 3 (n_d = 544); other
- * sizes return FLARE_E_UNSUPPORTED. precision: FLARE_FP32, FLARE_BF16_SPLIT or
- * FLARE_FP8_SPLIT; the split forms need every 144 x 144 single-species block of Sigma
- * positive definite (FLARE_E_ARG otherwise).
+ * sizes return FLARE_E_UNSUPPORTED. precision: FLARE_FP32, FLARE_BF16_SPLIT,
+ * FLARE_FP8_SPLIT or FLARE_BF16X6_SPLIT; the split forms need every 144 x 144
+ * single-species block of Sigma positive definite (FLARE_E_ARG otherwise).
  * The library copies the matrices to device memory it owns. Runs on the current device.
  */
 int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, double r_cut,

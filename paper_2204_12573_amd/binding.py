@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
 
 OK, E_ARG, E_SPECIES, E_BOX, E_CAPACITY, E_NONFINITE, E_STALE, E_OOM, E_HIP, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-FP32, BF16_SPLIT, FP8_SPLIT = 0, 1, 2
+FP32, BF16_SPLIT, FP8_SPLIT, BF16X6_SPLIT = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_SPECIES, FLAG_DISPLACED = 1, 2, 4
 
 

@@ -160,6 +160,28 @@ void bf16_fragments(const std::vector<double>& M, uint16_t* out /* [5][9][2][64]
         }
 }
 
+// Three-way BF16 fragments of one 144-block: B[k][n] = M[k][n] rounded to FP32, then
+// x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1) (both remainders exact in FP32).
+// Layout [ks 5][cb 9][part 3][lane 64][8], K padded to 160 with zeros.
+void bf16x3_fragments(const std::vector<double>& M, uint16_t* out /* [5][9][3][64][8] */) {
+  const int nks = 5, ncb = ND1 / 16;
+  for (int ks = 0; ks < nks; ++ks)
+    for (int cb = 0; cb < ncb; ++cb)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 8; ++t) {
+          const int k = ks * 32 + 8 * (lane / 16) + t, n = cb * 16 + lane % 16;
+          const float v = k < ND1 ? (float)M[(size_t)k * ND1 + n] : 0.f;
+          const uint16_t x0 = bf16_rne(v);
+          const float r1 = v - bf16_to_f32(x0);
+          const uint16_t x1 = bf16_rne(r1);
+          const uint16_t x2 = bf16_rne(r1 - bf16_to_f32(x1));
+          const size_t base = ((((size_t)ks * ncb + cb) * 3) * 64 + lane) * 8 + t;
+          out[base] = x0;
+          out[base + 64 * 8] = x1;
+          out[base + 2 * 64 * 8] = x2;
+        }
+}
+
 }  // namespace
 
 extern "C" {
@@ -191,8 +213,9 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
     set_error("this build has kernels for n_species=2, n_rad=8, l_max=3 only");
     return FLARE_E_UNSUPPORTED;
   }
-  if (precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT && precision != FLARE_FP8_SPLIT) {
-    set_error("precision must be FLARE_FP32, FLARE_BF16_SPLIT or FLARE_FP8_SPLIT");
+  if (precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT && precision != FLARE_FP8_SPLIT &&
+      precision != FLARE_BF16X6_SPLIT) {
+    set_error("precision must be FLARE_FP32, FLARE_BF16_SPLIT, FLARE_FP8_SPLIT or FLARE_BF16X6_SPLIT");
     return FLARE_E_UNSUPPORTED;
   }
   flare_model* m = new (std::nothrow) flare_model();
@@ -289,6 +312,24 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
       }
     }
   }
+  if (precision == FLARE_BF16X6_SPLIT) {
+    for (int b = 0; b < 4; ++b) {
+      const int s = b & 1;
+      const int st = b < 2 ? 0 : ND - ND1;
+      std::vector<double> beta = sub_block(beta_host + (size_t)s * ND * ND, st, ND1);
+      std::vector<uint16_t> frag((size_t)5 * ncb * 3 * 64 * 8);
+      bf16x3_fragments(beta, frag.data());
+      int rc = upload((void**)&m->W6[b], frag.data(), frag.size() * sizeof(uint16_t));
+      if (rc == FLARE_OK) {
+        bf16x3_fragments(L1[b], frag.data());      // B[k][n] = L[k][n], lower-triangular
+        rc = upload((void**)&m->L6[b], frag.data(), frag.size() * sizeof(uint16_t));
+      }
+      if (rc != FLARE_OK) {
+        flare_model_destroy(m);
+        return rc;
+      }
+    }
+  }
   if (precision == FLARE_BF16_SPLIT || precision == FLARE_FP8_SPLIT) {
     for (int b = 0; b < 4; ++b) {
       const int s = b & 1;
@@ -356,6 +397,8 @@ int flare_model_destroy(flare_model* m) {
     if (m->Wf[b]) (void)hipFree(m->Wf[b]);
     if (m->Wb[b]) (void)hipFree(m->Wb[b]);
     if (m->W8[b]) (void)hipFree(m->W8[b]);
+    if (m->W6[b]) (void)hipFree(m->W6[b]);
+    if (m->L6[b]) (void)hipFree(m->L6[b]);
   }
   for (int k = 0; k < 2; ++k)
     if (m->Lx[k]) (void)hipFree(m->Lx[k]);
@@ -776,6 +819,7 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
     b += 4LL * 2 * ND1 * ND1 * sizeof(float);
     if (m->precision == FLARE_BF16_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * 8 * sizeof(uint16_t);
     if (m->precision == FLARE_FP8_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * sizeof(uint64_t);
+    if (m->precision == FLARE_BF16X6_SPLIT) b += 2 * 4LL * 5 * 9 * 3 * 64 * 8 * sizeof(uint16_t);
     if (m->vchol) b += 2LL * ND * ND * sizeof(float);
   }
   if (s) {

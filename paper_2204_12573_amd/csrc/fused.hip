@@ -46,6 +46,8 @@ struct FusedArgs {
   const uint4* Wb[4];    // split form: beta as [ks 5][cb 9][hi/lo 2][lane 64] x 8 bf16
   const uint64_t* W8[4]; // FP8 split form: s_b beta as [ks 5][cb 9][hi/lo' 2][lane 64] x 8 e4m3
   float bscale[4];       // FP8 split form: s_b per bucket (a power of two)
+  const uint4* W6[4];    // three-way BF16 form: beta as [ks 5][cb 9][part 3][lane 64] x 8 bf16
+  const uint4* L6[4];    // three-way BF16 form: L, same layout
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
   int vchol;             // part 1 of Wf holds the Cholesky factor L: V = |L^T d|^2
   float* G;              // [tiles][144][128]: g (no forces here), or the densities of each
@@ -219,6 +221,128 @@ __device__ __forceinline__ void mfma_pass_bf16(const float* As, const uint4* __r
   }
 }
 
+// Three-way BF16 form of both passes: x = x0 + x1 + x2 holds all 24 significant bits of
+// an FP32 value exactly (x0 and x1 round the remainder of the previous parts to 8 bits,
+// the remainders are exact in FP32, and the last one fits 8 bits), and the same for the
+// model matrix. Of the nine part
+// products the six with a part-index sum <= 2 are formed on v_mfma_f32_16x16x32_bf16
+// (exact products, FP32 accumulation); the dropped x1 w2 + x2 w1 + x2 w2 are below
+// 2^-23 |x||w|, the size of an FP32 rounding. K = 144 runs as five 32-wide steps
+// as in the two-way form; column blocks go in groups of three so that the six products
+// of a block are five other MFMAs apart. TRI: W = L lower-triangular, the blocks with
+// 16 j > 32 ks + 31 vanish.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// two FP32 values to a packed BF16 pair (round to nearest even), and back
+__device__ __forceinline__ unsigned int pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned int, __builtin_convertvector((f2v){a, b}, bf2));
+}
+__device__ __forceinline__ float bf16_lo(unsigned int p) { return __builtin_bit_cast(float, p << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned int p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
+
+// x0 = bf16(v), x1 = bf16(v - x0), x2 = v - x0 - x1: the last remainder has at most 8
+// significant bits, so its BF16 pattern is the upper half of its FP32 pattern (exact)
+__device__ __forceinline__ void split8x3(const float4 (&u)[2], bf8& x0, bf8& x1, bf8& x2) {
+  const float v[8] = {u[0].x, u[0].y, u[0].z, u[0].w, u[1].x, u[1].y, u[1].z, u[1].w};
+  u4v p0, p1, p2;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    p0[t] = pk_bf16(v[2 * t], v[2 * t + 1]);
+    const float ra = v[2 * t] - bf16_lo(p0[t]), rb = v[2 * t + 1] - bf16_hi(p0[t]);
+    p1[t] = pk_bf16(ra, rb);
+    const float sa = ra - bf16_lo(p1[t]), sb = rb - bf16_hi(p1[t]);
+    p2[t] = __builtin_amdgcn_perm(__builtin_bit_cast(unsigned int, sb), __builtin_bit_cast(unsigned int, sa),
+                                  0x07060302u);
+  }
+  x0 = __builtin_bit_cast(bf8, p0);
+  x1 = __builtin_bit_cast(bf8, p1);
+  x2 = __builtin_bit_cast(bf8, p2);
+}
+
+// A operand of K step ks for row block i: 8 FP32 values (zeros past K = 144)
+__device__ __forceinline__ void load_a8(const float* As, int wave, int l16, int grp, int i, int ks,
+                                        float4 (&u)[2]) {
+  if (ks == NKS - 1 && grp >= 2) {
+    u[0] = u[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    const float* p = &As[(wave * 32 + i * 16 + l16) * AS + ks * 32 + 8 * grp];
+    u[0] = *reinterpret_cast<const float4*>(p);
+    u[1] = *reinterpret_cast<const float4*>(p + 4);
+  }
+}
+
+// Steps (ks, jg) in order; with TRI only the groups with 3 jg <= 2 ks + 1. One register
+// buffer of B fragments: the products run B part 2 first and part 0 last, and each part's
+// fragments for the next step are loaded as soon as its last product here is issued; the
+// next K step's A values are loaded at the start of a K step's last group.
+template <bool TRI>
+__host__ __device__ constexpr bool x6_active(int ks, int jg) {
+  return !TRI || 3 * jg <= 2 * ks + 1;
+}
+
+template <bool TRI>
+__device__ __forceinline__ void mfma_pass_bf16x6(const float* As, const uint4* __restrict__ W, int wave,
+                                                 int lane, f4 (&acc)[2][NCB]) {
+  const int l16 = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const uint4* Wp = W + lane;
+  bf8 b[3][3];              // [block of the group][part]
+  float4 araw[2][2];
+  bf8 a[3][2];              // [part][row block]
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt)
+      if (!TRI || jj <= 1) b[jj][pt] = __builtin_bit_cast(bf8, Wp[(jj * 3 + pt) * 64]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) load_a8(As, wave, l16, grp, i, 0, araw[i]);
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) split8x3(araw[i], a[0][i], a[1][i], a[2][i]);
+#pragma unroll
+    for (int jg = 0; jg < NCB / 3; ++jg) {
+      if (!x6_active<TRI>(ks, jg)) continue;
+      // the next active step
+      const bool same = jg + 1 < NCB / 3 && x6_active<TRI>(ks, jg + 1);
+      const int nks = same ? ks : ks + 1, njg = same ? jg + 1 : 0;
+      const bool more = nks < NKS;
+      if (more && !same) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) load_a8(As, wave, l16, grp, i, nks, araw[i]);
+      }
+#define X6_PROD(PA, PB)                                                                       \
+  _Pragma("unroll") for (int jj = 0; jj < 3; ++jj) {                                          \
+    if (TRI && 3 * jg + jj > 2 * ks + 1) continue;                                            \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) acc[i][3 * jg + jj] =                       \
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA][i], b[jj][PB], acc[i][3 * jg + jj], 0, 0, 0); \
+  }
+#define X6_NEXT(PT)                                                                           \
+  if (more) {                                                                                 \
+    _Pragma("unroll") for (int jj = 0; jj < 3; ++jj)                                          \
+      if (!TRI || 3 * njg + jj <= 2 * nks + 1)                                                \
+        b[jj][PT] = __builtin_bit_cast(bf8, Wp[((nks * NCB + 3 * njg + jj) * 3 + PT) * 64]);   \
+  }
+      X6_PROD(0, 2)
+      X6_NEXT(2)
+      X6_PROD(1, 1)
+      X6_PROD(0, 1)
+      X6_NEXT(1)
+      X6_PROD(2, 0)
+      X6_PROD(1, 0)
+      X6_PROD(0, 0)
+      X6_NEXT(0)
+#undef X6_PROD
+#undef X6_NEXT
+    }
+  }
+}
+
 // FP8 split form on v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3, 3 mantissa bits). Each row is
 // pre-scaled by a power of two s_r so that |s_r d~| < 16, and beta by s_b so that
 // |s_b beta| < 16. With x = s_r d~ = x_hi + x_lo and b = s_b beta = b_hi + b_lo, the
@@ -376,13 +500,16 @@ struct TileModel {
   const float4* Wf;
   const uint4* Wb;
   const uint64_t* W8;
+  const uint4* W6;
+  const uint4* L6;
   float bsc;
 };
 __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
-  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.bscale[0]};
+  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.W6[0], a.L6[0], a.bscale[0]};
 #pragma unroll
   for (int k = 1; k < 4; ++k)   // static indexing keeps the argument arrays out of scratch
-    if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k]) m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.bscale[k]};
+    if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k])
+      m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.W6[k], a.L6[k], a.bscale[k]};
   return m;
 }
 
@@ -452,7 +579,11 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
   f4 acc[2][NCB];
   float dots[2][4];
   if (a.mode & 2) {
-    if (PREC != FLARE_FP32 || a.vchol) {
+    if (PREC == FLARE_BF16X6_SPLIT) {
+      // Z = D L from the three-way BF16 parts of D and L
+      mfma_pass_bf16x6<true>(As, tm.L6, wave, lane, acc);
+      row_sumsq<true>(acc, dots);
+    } else if (PREC != FLARE_FP32 || a.vchol) {
       // Z = D L on FP32 cores, L lower-triangular
       if (SB) mfma_pass_sb<1, true>(As, tm.Wf, wave, lane, acc);
       else mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);
@@ -477,6 +608,8 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
   if (a.mode & 1) {
     if (PREC == FLARE_BF16_SPLIT) {
       mfma_pass_bf16<0>(As, tm.Wb, wave, lane, acc);
+    } else if (PREC == FLARE_BF16X6_SPLIT) {
+      mfma_pass_bf16x6<false>(As, tm.W6, wave, lane, acc);
     } else if (PREC == FLARE_FP8_SPLIT) {
       mfma_pass_fp8(As, rsc_s, tm.W8, wave, lane, acc);
       // undo the power-of-two scales: Y~ = acc / (16 s_r s_b), exact
@@ -620,6 +753,8 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     a.Wf[k] = reinterpret_cast<const float4*>(s->model->Wf[k]);
     a.Wb[k] = reinterpret_cast<const uint4*>(s->model->Wb[k]);
     a.W8[k] = s->model->W8[k];
+    a.W6[k] = reinterpret_cast<const uint4*>(s->model->W6[k]);
+    a.L6[k] = reinterpret_cast<const uint4*>(s->model->L6[k]);
     a.bscale[k] = s->model->beta_scale[k];
   }
   a.vchol = s->model->vchol ? 1 : 0;
@@ -637,6 +772,8 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     const int grid = std::min(256, (nsub + WW - 1) / WW);
     if (s->model->precision == FLARE_BF16_SPLIT)
       k_fused144_w<FLARE_BF16_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
+    else if (s->model->precision == FLARE_BF16X6_SPLIT)
+      k_fused144_w<FLARE_BF16X6_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
     else if (s->model->precision == FLARE_FP8_SPLIT)
       k_fused144_w<FLARE_FP8_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
     else
@@ -645,6 +782,8 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   }
   if (s->model->precision == FLARE_BF16_SPLIT)
     k_fused144<FLARE_BF16_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
+  else if (s->model->precision == FLARE_BF16X6_SPLIT)
+    k_fused144<FLARE_BF16X6_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
   else if (s->model->precision == FLARE_FP8_SPLIT)
     k_fused144<FLARE_FP8_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
   else

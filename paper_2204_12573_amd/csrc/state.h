@@ -101,6 +101,10 @@ struct flare_model {
   // instruction the kernel uses for d; lo' = fp8(16 (x - hi)). s_b = 2^k keeps |s_b beta| <= 16.
   uint64_t* W8[4] = {};
   float beta_scale[4] = {1.f, 1.f, 1.f, 1.f};
+  // Three-way BF16 form (precision FLARE_BF16X6_SPLIT): beta and the Cholesky factor L as
+  // [K step 5][column block 9][part 3][lane 64] x 8 bf16, parts x0 + x1 + x2 = FP32 value.
+  uint16_t* W6[4] = {};
+  uint16_t* L6[4] = {};
   // Mixed buckets in the split form: L of the 544 x 544 Sigma_s, [544][544] FP32, stored
   // like W (row n = column n of L).
   float* Lx[2] = {};

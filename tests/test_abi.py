@@ -46,4 +46,4 @@ def test_host_only_calls():
     assert lib.flare_model_create(ctypes.byref(h), 3, 8, 3, 4.5, dummy, dummy, 0) == binding.E_UNSUPPORTED
     assert lib.flare_neighbors(None, 1, None, None, None, None, 1, None, None, 0.2) == binding.E_ARG
     assert lib.flare_virial(None, None) == binding.E_ARG
-    assert lib.flare_model_create(ctypes.byref(h), 2, 8, 3, 4.5, dummy, dummy, 3) == binding.E_UNSUPPORTED
+    assert lib.flare_model_create(ctypes.byref(h), 2, 8, 3, 4.5, dummy, dummy, 4) == binding.E_UNSUPPORTED

@@ -9,8 +9,10 @@ dropped lo*lo product is ~2^-16 of a term, so E and F land near 1e-5 of their sc
 power-of-two scales keeping every operand normal, each term 16 x b is represented to
 3 * 2^-8 of |x||b| (two rounded lo' parts and the dropped lo*lo), so the worst case is
 about 1.2e-2 of sum_kl |d_k||beta_kl||d_l| / |d|^2; random rounding errors average down
-and the test asks for 1e-2 of the largest energy and force. The variance of both split
-forms never touches the narrow formats."""
+and the test asks for 1e-2 of the largest energy and force. The variance of these two
+split forms never touches the narrow formats. The three-way BF16 form splits d, beta and
+L into three BF16 parts (together the 24 bits of the FP32 value) and drops only part
+products below 2^-23 of a term, so it is held to the FP32 bar, 1e-5, in E, F and sigma."""
 import numpy as np
 import pytest
 
@@ -25,8 +27,10 @@ pytestmark = pytest.mark.gpu
 SPLIT_TOL_E = 1e-4     # energies, forces of the BF16 split form (BF16 x 3 products)
 SPLIT_TOL_S = 1e-5     # sigma of the split forms (sum of squares, no cancellation)
 FP8_TOL_E = 1e-2       # energies, forces of the FP8 split form (e4m3 x 3 products)
-TOL_E = {Bd.BF16_SPLIT: SPLIT_TOL_E, Bd.FP8_SPLIT: FP8_TOL_E}
-PREC = [pytest.param(Bd.BF16_SPLIT, id="bf16"), pytest.param(Bd.FP8_SPLIT, id="fp8")]
+X6_TOL_E = 1e-5        # three-way BF16 form: the FP32 bar
+TOL_E = {Bd.BF16_SPLIT: SPLIT_TOL_E, Bd.FP8_SPLIT: FP8_TOL_E, Bd.BF16X6_SPLIT: X6_TOL_E}
+PREC = [pytest.param(Bd.BF16_SPLIT, id="bf16"), pytest.param(Bd.FP8_SPLIT, id="fp8"),
+        pytest.param(Bd.BF16X6_SPLIT, id="bf16x6")]
 
 
 def _errs(res, ref):
@@ -71,7 +75,8 @@ def test_near_cancelling_variance():
     gamma = np.stack([sgp.gamma_mapped(d[(st.species == s)][::2], sigma2, noise) for s in (0, 1)])
     ref = oev.evaluate(st.pos, st.species, st.box, beta, gamma)
     out = {}
-    for name, prec in [("fp32", Bd.FP32), ("split", Bd.BF16_SPLIT), ("fp8", Bd.FP8_SPLIT)]:
+    for name, prec in [("fp32", Bd.FP32), ("split", Bd.BF16_SPLIT), ("fp8", Bd.FP8_SPLIT),
+                       ("bf16x6", Bd.BF16X6_SPLIT)]:
         res = gpu_eval(st.pos, st.species, st.box, beta, gamma, precision=prec, want_d=(name == "fp32"))
         out[name] = float(np.max(np.abs(res["var"] - ref.v) / ref.v))
         if name == "fp32":
@@ -83,7 +88,7 @@ def test_near_cancelling_variance():
             out["direct_fp32"] = float(np.max(np.abs(v_direct.cpu().numpy() - ref.v) / ref.v))
     print("pointwise relative error of V:", out, "V/sigma^2 range:", ref.v.min() / sigma2, ref.v.max() / sigma2)
     assert ref.v.min() < 1e-3 * sigma2              # genuinely near-cancelling
-    for name in ("fp32", "split", "fp8"):
+    for name in ("fp32", "split", "fp8", "bf16x6"):
         assert out[name] <= 2e-4
         assert out[name] < out["direct_fp32"] / 5
 
