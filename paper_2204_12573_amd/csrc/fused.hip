@@ -166,6 +166,17 @@ __device__ __forceinline__ void mfma_pass_sb(const float* As, const float4* __re
 // squares whose error follows the rounding of d, not the size of the cancelled terms.
 constexpr int NKS = 5;
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// two FP32 values to a packed BF16 pair (round to nearest even), and back
+__device__ __forceinline__ unsigned int pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned int, __builtin_convertvector((f2v){a, b}, bf2));
+}
+__device__ __forceinline__ float bf16_lo(unsigned int p) { return __builtin_bit_cast(float, p << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned int p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
+
 __device__ __forceinline__ void split8(const float* p, bool zero, bf8& hi, bf8& lo) {
   float v[8];
   if (zero) {
@@ -177,11 +188,14 @@ __device__ __forceinline__ void split8(const float* p, bool zero, bf8& hi, bf8& 
     v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
     v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
   }
+  u4v ph, pl;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    hi[t] = (__bf16)v[t];
-    lo[t] = (__bf16)(v[t] - (float)hi[t]);
+  for (int t = 0; t < 4; ++t) {
+    ph[t] = pk_bf16(v[2 * t], v[2 * t + 1]);
+    pl[t] = pk_bf16(v[2 * t] - bf16_lo(ph[t]), v[2 * t + 1] - bf16_hi(ph[t]));
   }
+  hi = __builtin_bit_cast(bf8, ph);
+  lo = __builtin_bit_cast(bf8, pl);
 }
 
 template <int PART>
@@ -231,17 +245,6 @@ __device__ __forceinline__ void mfma_pass_bf16(const float* As, const uint4* __r
 // as in the two-way form; column blocks go in groups of three so that the six products
 // of a block are five other MFMAs apart. TRI: W = L lower-triangular, the blocks with
 // 16 j > 32 ks + 31 vanish.
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-
-// two FP32 values to a packed BF16 pair (round to nearest even), and back
-__device__ __forceinline__ unsigned int pk_bf16(float a, float b) {
-  return __builtin_bit_cast(unsigned int, __builtin_convertvector((f2v){a, b}, bf2));
-}
-__device__ __forceinline__ float bf16_lo(unsigned int p) { return __builtin_bit_cast(float, p << 16); }
-__device__ __forceinline__ float bf16_hi(unsigned int p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
-
 // x0 = bf16(v), x1 = bf16(v - x0), x2 = v - x0 - x1: the last remainder has at most 8
 // significant bits, so its BF16 pattern is the upper half of its FP32 pattern (exact)
 __device__ __forceinline__ void split8x3(const float4 (&u)[2], bf8& x0, bf8& x1, bf8& x2) {
