@@ -121,18 +121,25 @@ __global__ __launch_bounds__(NT) void k_to_internal(int n, const int* __restrict
   for (int ax = 0; ax < 3; ++ax) off[(size_t)ax * n + i] = o_off[(size_t)ax * n + a];
 }
 
-// Per-wave ballot counts of each bucket, combined per block into blk[b * nblk + block].
-__device__ inline void block_bucket_counts(int b, int* __restrict__ blk, int nblk) {
-  __shared__ int cnt[NBUCKET];
-  if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+// Row order inside a bucket: by neighbour count, largest first (counts of NCK - 1 and more
+// share the last class), ties by internal index. The 32-row slices of the sliced layout
+// then hold rows of nearly equal length, so a wave's trip count over its slice (the
+// longest row) wastes few lanes. (Measured: ordering only inside 128-row tiles, or inside
+// windows of 4096 atoms, keeps more spatial locality for the per-slot gathers but leaves
+// enough padding in the slices to cost more in the fused kernel than it saves there.)
+// Sort key of an atom in bucket b with count c: b * NCK + (NCK - 1 - min(c, NCK - 1)).
+constexpr int NCK = 64;
+constexpr int NKEY = NBUCKET * NCK;
+__device__ inline int row_key(int b, int c) { return b * NCK + (NCK - 1 - min(c, NCK - 1)); }
+
+// Per-block counts of each sort key, blk[key * nblk + block] (key < 0: no row).
+__device__ inline void block_key_counts(int key, int* __restrict__ blk, int nblk) {
+  __shared__ int cnt[NKEY];
+  for (int k = threadIdx.x; k < NKEY; k += NT) cnt[k] = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  for (int k = 0; k < NBUCKET; ++k) {
-    unsigned long long m = __ballot(b == k);
-    if (lane == 0 && m) atomicAdd(&cnt[k], __popcll(m));
-  }
+  if (key >= 0) atomicAdd(&cnt[key], 1);
   __syncthreads();
-  if (threadIdx.x < NBUCKET) blk[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+  for (int k = threadIdx.x; k < NKEY; k += NT) blk[(size_t)k * nblk + blockIdx.x] = cnt[k];
 }
 
 // The counting pass (FILL = false) also keeps the first PAIR_CACHE pairs of every atom in
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
                                               int2* __restrict__ cache) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * NT + threadIdx.x;
-  int b_out = -1;
+  int key_out = -1;
   if (FILL && i < n) {
     const int o = nl_off[i], c = nl_off[i + 1] - o;
     if (c <= PAIR_CACHE) {
@@ -218,11 +225,12 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
     if (!FILL) {
       cnt_out[i] = cnt;
       envmask[i] = mask;
-      b_out = bucket_of(sp[i], mask);
-      bucket[i] = b_out;
+      const int b = bucket_of(sp[i], mask);
+      bucket[i] = b;
+      if (b >= 0) key_out = row_key(b, cnt);
     }
   }
-  if (!FILL) block_bucket_counts(b_out, blk, nblk);
+  if (!FILL) block_key_counts(key_out, blk, nblk);
 }
 
 // For every pair p = (i, j, s) find q = (j, i, -s) in j's list. The list is symmetric
@@ -330,57 +338,31 @@ struct Row0 {
   int r[NBUCKET];
 };
 
+// Rows of each bucket in key order (see row_key); the rank among equal keys follows the
+// internal index (block scan of the key counts, then the rank inside the block).
 __global__ __launch_bounds__(NT) void k_assign_rows(int n, const int* __restrict__ bucket,
+                                                    const int* __restrict__ cnt,
                                                     const int* __restrict__ blk_scan, int nblk,
                                                     Row0 row0, int* __restrict__ row_of,
                                                     int* __restrict__ aor1,
                                                     int* __restrict__ aorx) {
-  __shared__ int wcnt[NT / 64][NBUCKET];
+  __shared__ int keys[NT];
   const int i = blockIdx.x * NT + threadIdx.x;
   const int b = i < n ? bucket[i] : -1;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int rank = 0;
-  for (int k = 0; k < NBUCKET; ++k) {
-    unsigned long long m = __ballot(b == k);
-    if (b == k) rank = __popcll(m & lt);
-    if (lane == 0) wcnt[wv][k] = __popcll(m);
-  }
+  const int key = b >= 0 ? row_key(b, cnt[i]) : -1;
+  keys[threadIdx.x] = key;
   __syncthreads();
   if (i >= n) return;
   if (b < 0) {
     row_of[i] = -1;
     return;
   }
-  for (int v = 0; v < wv; ++v) rank += wcnt[v][b];
-  const int row = row0.r[b] + (blk_scan[b * nblk + blockIdx.x] - blk_scan[b * nblk]) + rank;
+  int rank = 0;
+  for (int q = 0; q < (int)threadIdx.x; ++q) rank += keys[q] == key ? 1 : 0;
+  const int row = row0.r[b] + (blk_scan[(size_t)key * nblk + blockIdx.x] - blk_scan[(size_t)b * NCK * nblk]) + rank;
   row_of[i] = row;
   if (b < 4) aor1[row] = i;
   else aorx[row] = i;
-}
-
-// Inside each tile of 128 rows (tiles never straddle a bucket), order the rows by
-// neighbour count, largest first, ties by the previous order: the 32-row slices of the
-// sliced layout then hold rows of similar length, so a wave's trip count over its slice
-// (the longest row) wastes few lanes. Rows stay within their tile, so the tile keeps its
-// spatial locality.
-__global__ __launch_bounds__(TILE_ROWS) void k_sort_tile_rows(int* __restrict__ aor,
-                                                              const int* __restrict__ cnt,
-                                                              int* __restrict__ row_of) {
-  __shared__ int key[TILE_ROWS];
-  const int r = threadIdx.x;
-  const int row0 = blockIdx.x * TILE_ROWS;
-  const int i = aor[row0 + r];
-  const int k = i >= 0 ? cnt[i] : -1;
-  key[r] = k;
-  __syncthreads();
-  int rank = 0;
-  for (int q = 0; q < TILE_ROWS; ++q) {
-    const int kq = key[q];
-    rank += (kq > k || (kq == k && q < r)) ? 1 : 0;
-  }
-  aor[row0 + rank] = i;
-  if (i >= 0) row_of[i] = row0 + rank;
 }
 
 // The per-atom counts are non-negative and each is below 2^31, so their int32 prefix sum
@@ -396,7 +378,8 @@ __global__ void k_info(int n, const int* __restrict__ nl_off, const int* __restr
                        int nblk, const int* __restrict__ status, int* __restrict__ info) {
   if (threadIdx.x == 0) {
     info[0] = nl_off[n];
-    for (int b = 0; b < NBUCKET; ++b) info[1 + b] = blk_scan[(b + 1) * nblk] - blk_scan[b * nblk];
+    for (int b = 0; b < NBUCKET; ++b)
+      info[1 + b] = blk_scan[(size_t)(b + 1) * NCK * nblk] - blk_scan[(size_t)b * NCK * nblk];
     info[7] = *status;
   }
 }
@@ -428,9 +411,9 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->bin_start.reserve(nbins + 1));
   HIPCHK(s->bin_fill.reserve(nbins + 1));
   const int nblk = grid_of(n);
-  HIPCHK(s->blk_bucket.reserve((size_t)NBUCKET * nblk + 1));
-  HIPCHK(s->blk_bucket_scan.reserve((size_t)NBUCKET * nblk + 1));
-  long long scan_n = std::max<long long>({(long long)nbins, (long long)n, (long long)NBUCKET * nblk});
+  HIPCHK(s->blk_bucket.reserve((size_t)NKEY * nblk + 1));
+  HIPCHK(s->blk_bucket_scan.reserve((size_t)NKEY * nblk + 1));
+  long long scan_n = std::max<long long>({(long long)nbins, (long long)n, (long long)NKEY * nblk});
   HIPCHK(s->scan_scratch.reserve(scan_scratch_ints(scan_n)));
   HIPCHK(hipMemsetAsync(s->d_status, 0, sizeof(int), st));
   if (n > 0) {
@@ -455,7 +438,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
                                          nullptr, nullptr, nullptr, s->pair_cache.p);
   }
   scan_exclusive(s->nl_cnt, s->nl_off, n, s->scan_scratch.p, st);
-  scan_exclusive(s->blk_bucket.p, s->blk_bucket_scan.p, NBUCKET * nblk, s->scan_scratch.p, st);
+  scan_exclusive(s->blk_bucket.p, s->blk_bucket_scan.p, NKEY * nblk, s->scan_scratch.p, st);
   k_off_check<<<grid_of(n + 1), NT, 0, st>>>(n, s->nl_off, s->d_status);
   k_info<<<1, 64, 0, st>>>(n, s->nl_off, s->blk_bucket_scan.p, nblk, s->d_status, s->d_info);
   HIPCHK(hipMemcpyAsync(s->h_info, s->d_info, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -508,10 +491,8 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
                                         rl2, nullptr, nullptr, nullptr, nullptr, nblk, s->nl_off,
                                         s->nl_j, s->nl_s, s->pair_cache.p);
     k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev, s->d_status);
-    k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->blk_bucket_scan.p, nblk, row0, s->row_of,
+    k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->nl_cnt, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
-    if (r1 > 0) k_sort_tile_rows<<<r1 / TILE_ROWS, TILE_ROWS, 0, st>>>(s->atom_of_row1.p, s->nl_cnt, s->row_of);
-    if (rx > 0) k_sort_tile_rows<<<rx / TILE_ROWS, TILE_ROWS, 0, st>>>(s->atom_of_rowx.p, s->nl_cnt, s->row_of);
   }
   // sliced layout: slice lengths, their prefix, then the slots
   s->n_slices = (r1 + rx) / 32;
