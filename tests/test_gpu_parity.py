@@ -187,3 +187,41 @@ def test_repeat_is_bitwise_equal(model):
     b = gpu_eval(st.pos, st.species, st.box, beta, sigma)
     for key in ["e", "f", "sigma", "E"]:
         np.testing.assert_array_equal(a[key], b[key])
+
+
+def _fcc(a, n, rng, jitter):
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    cells = np.array([[i, j, k] for i in range(n) for j in range(n) for k in range(n)], float)
+    pos = ((cells[:, None, :] + base[None, :, :]).reshape(-1, 3)) * a
+    return pos + rng.normal(0.0, jitter, pos.shape), np.full(3, n * a)
+
+
+def test_dense_cells_long_rows(model):
+    # compressed fcc cells: 60-80 neighbours per atom, beyond the largest neighbour-count
+    # class of the row ordering (63), in a single-species cell (144-wide rows) and a
+    # random H/Pt cell (544-wide rows), batched together
+    beta, sigma = model
+    rng = np.random.default_rng(8)
+    p1, b1 = _fcc(2.9, 3, rng, 0.05)
+    p2, b2 = _fcc(3.0, 3, rng, 0.05)
+    s1 = np.ones(len(p1), np.int32)
+    s2 = rng.integers(0, 2, len(p2)).astype(np.int32)
+    pos = np.concatenate([S._wrap(p1, b1), S._wrap(p2, b2)])
+    species = np.concatenate([s1, s2])
+    offsets = np.array([0, len(p1), len(p1) + len(p2)], np.int32)
+    print("case: dense fcc cells, 108 + 108 atoms", flush=True)
+    res = gpu_eval(pos, species, np.stack([b1, b2]), beta, sigma, offsets=offsets, max_pairs=100 * len(species))
+    off, j, s = res["ev"].export_list()
+    counts = np.diff(off)
+    assert counts[:len(p1)].max() > 63 and counts[len(p1):].max() > 63
+    for k, (pk, sk, bk) in enumerate([(p1, s1, b1), (p2, s2, b2)]):
+        lo, hi = offsets[k], offsets[k + 1]
+        pk = S._wrap(pk, bk)
+        i0, j0, s0 = onl.brute_force(pk, bk, 4.7)
+        np.testing.assert_array_equal(j[off[lo]:off[hi]], j0 + lo)
+        np.testing.assert_array_equal(s[off[lo]:off[hi]], s0)
+        ref = oev.evaluate(pk, sk, bk, beta, sigma)
+        sub = {key: (res[key][lo:hi] if isinstance(res[key], np.ndarray) and res[key].ndim >= 1
+                     and len(res[key]) == len(species) else res[key]) for key in res}
+        print(_compare(sub, ref))
+        assert abs(res["E"][k] - ref.energy) <= TOL * abs(ref.energy)
