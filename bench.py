@@ -25,10 +25,15 @@ METRIC = "M atom-steps/s/GPU (E+F+σ) plain FP32 vs mixed @ force err; p50/p99 s
 PEAK_FP32_MFMA = 157.3e12      # dense FP32 matrix FLOP/s, MI355X
 PEAK_HBM = 8.0e12              # B/s
 PEAK_FP32_VALU = 78.6e12       # FP32 vector FMA without packed instructions
-# algorithmic vector work beside the quadratic forms (flop): per pair inside the cutoff,
-# densities (basis + 8x16 accumulate) and the adjoint term; per 144-wide row, the B2
-# contraction and the adjoint transform u = G^ c
-VALU_FLOP_DENS, VALU_FLOP_ADJ, VALU_FLOP_B2, VALU_FLOP_U = 320, 600, 1152, 2048
+# algorithmic vector work beside the quadratic forms (flop). Per pair inside the cutoff:
+# densities = radial basis (24) + 16 harmonics (35) + 8x16 multiply-adds (256) = 320 with
+# rounding; adjoint term = radial basis and derivative (75) + harmonics (35) + A_lm, B_lm
+# (512) + the radial sum (64) + the harmonic gradient contraction (135) + assembly (9) =
+# 830. Per 144-wide row: B2 contraction 36 x 16 multiply-adds (1152), |d~|^2 (288), the
+# epilogue e = Y.d, g = s(Y - e d), V = |z|^2 (1000), the adjoint transform u = G^ c
+# (8 x 8 x 16 multiply-adds = 2048).
+VALU_FLOP_DENS, VALU_FLOP_ADJ = 320, 830
+VALU_FLOP_B2, VALU_FLOP_NORM, VALU_FLOP_EPI, VALU_FLOP_U = 1152, 288, 1000, 2048
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_fused144_w_h2_pt111_1M_fp32.txt")
@@ -256,7 +261,8 @@ def main():
     # of their separate times), so the kernel is bound by that datapath: its time is at
     # least the MFMA work at the matrix peak plus the vector work at the non-packed vector
     # peak. The bound's peak is the blend of the two for this kernel's mix of work.
-    valu_flops = work["pairs144"] * (VALU_FLOP_DENS + VALU_FLOP_ADJ) + n144 * (VALU_FLOP_B2 + VALU_FLOP_U)
+    valu_flops = work["pairs144"] * (VALU_FLOP_DENS + VALU_FLOP_ADJ) + n144 * (
+        VALU_FLOP_B2 + VALU_FLOP_NORM + VALU_FLOP_EPI + VALU_FLOP_U)
     t_min = flops_per_launch / PEAK_FP32_MFMA + valu_flops / PEAK_FP32_VALU
     total = flops_per_launch + valu_flops
     roofline = {"bound": "alu", "achieved": total / t_launch / 1e12, "peak": total / t_min / 1e12,
