@@ -12,7 +12,8 @@ Every function is the plain definition from the paper, written for clarity over 
   * mapped mean and variance as quadratic forms d^T beta d and d^T gamma d (Eq. 1, Eq. 2);
   * forces as -dE/dr formed through the explicit descriptor gradient (the direct
     route that the force reordering of Section V.B avoids), and by central differences;
-  * velocity-Verlet NVE for the short MD checks.
+  * velocity-Verlet NVE and Nose-Hoover NVT for the short MD checks, hydrogen
+    coordination numbers and reaction events of the production runs (Section VI.A).
 
 Readings of what the paper leaves open (radial basis, cutoff shape, packing order,
 one model per central species, ...) are listed in the design notes and in the
