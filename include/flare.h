@@ -222,6 +222,50 @@ int flare_md_second_half(flare_state* state, double* vx, double* vy, double* vz,
                          const int32_t* species, const double* masses_host, double dt);
 
 /*
+ * Nose-Hoover NVT halves (the paper's production runs, Section VI.A: 450 K). One
+ * thermostat variable zeta per cell, no chain:
+ *   dv/dt = KAPPA F/m - zeta v,  dzeta/dt = (2K / (N_f k_B T) - 1) / tau^2,  deta/dt = zeta,
+ * N_f = max(3 N_cell - 3, 1), k_B = 8.617333262e-5 eV/K, K the cell's kinetic energy (eV).
+ *   first:  zeta += dt/2 G(K); v *= exp(-zeta dt/2); eta += zeta dt/2;
+ *           v += dt/2 KAPPA F/m; x += dt v
+ *   second: v += dt/2 KAPPA F/m; v *= exp(-zeta dt/2); eta += zeta dt/2; K = sum m v^2/2;
+ *           zeta += dt/2 G(K)
+ * (time-reversible; H' = E_pot + K + Q zeta^2/2 + N_f k_B T eta with Q = N_f k_B T tau^2
+ * is conserved to O(dt^2)).
+ *   thermo       DEVICE FP64 [n_struct][3] = (zeta [1/fs], eta, K [eV]) per cell, owned by
+ *                the caller: zero zeta and eta to start, and fill K with flare_kinetic.
+ *   t_target     K; tau: damping time in fs (> 0; a large tau decouples the thermostat).
+ * Arrays as in flare_md_*_half. K is summed in FP64 (compensated) over fixed atom ranges
+ * of each cell (deterministic, independent of the other cells).
+ */
+int flare_nvt_first_half(flare_state* state, double* x, double* y, double* z, double* vx,
+                         double* vy, double* vz, const float* fx, const float* fy,
+                         const float* fz, const int32_t* species, const double* masses_host,
+                         double dt, double t_target, double tau, double* thermo);
+int flare_nvt_second_half(flare_state* state, double* vx, double* vy, double* vz,
+                          const float* fx, const float* fy, const float* fz,
+                          const int32_t* species, const double* masses_host, double dt,
+                          double t_target, double tau, double* thermo);
+/* Kinetic energy per cell into thermo[c][2] (eV); velocities unchanged. */
+int flare_kinetic(flare_state* state, double* vx, double* vy, double* vz, const int32_t* species,
+                  const double* masses_host, double* thermo);
+
+/*
+ * Hydrogen coordination numbers (Section VI.A): coord[a] = 1 when atom a is H and another
+ * H atom is within 1 A (squared FP64 distance of the positions staged by the last
+ * flare_descriptors, below 1), else 0 (always 0 for other species). A change 1 -> 0
+ * between two snapshots is a dissociation, 0 -> 1 a recombination.
+ *   coord       DEVICE int32 [n_atoms], caller order (written)
+ *   coord_prev  DEVICE int32 [n_atoms] of an earlier snapshot, or NULL
+ *   events      DEVICE int64 [n_struct][2] (dissociations, recombinations) per cell
+ *               between coord_prev and coord, or NULL (both or neither)
+ * Needs the list to cover 1 A (it does: r_list > r_cut > 1 A) and descriptors staged
+ * for the current positions (FLARE_E_STALE otherwise).
+ */
+int flare_coordination(flare_state* state, int32_t* coord, const int32_t* coord_prev,
+                       int64_t* events);
+
+/*
  * Stage timers. When enabled, the library records a pair of HIP events on the state's
  * stream around each stage it launches; flare_timers_read (SYNCHRONISING) returns the
  * accumulated milliseconds and launch counts per stage (HOST outputs, FLARE_NTIMERS

@@ -52,6 +52,10 @@ SIGNATURES = {
     "flare_memory_bytes": (_i, [_p, _p, ctypes.POINTER(_ll)]),
     "flare_md_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
     "flare_md_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
+    "flare_nvt_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d, _d, _p]),
+    "flare_nvt_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d, _d, _p]),
+    "flare_kinetic": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "flare_coordination": (_i, [_p, _p, _p, _p]),
     "flare_timers_enable": (_i, [_p, _i]),
     "flare_timers_read": (_i, [_p, _p, _p, _i]),
     "flare_status": (_i, [_p, _p]),

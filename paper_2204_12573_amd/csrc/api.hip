@@ -811,6 +811,70 @@ int flare_md_second_half(flare_state* s, double* vx, double* vy, double* vz, con
   return FLARE_OK;
 }
 
+int flare_nvt_first_half(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                         const float* fx, const float* fy, const float* fz, const int32_t* species,
+                         const double* masses_host, double dt, double t_target, double tau, double* thermo) {
+  ARG(s && masses_host && thermo, "null pointer");
+  if (!s->have_list) {
+    set_error("integrator needs the atom count of a neighbour list");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (x && y && z && vx && vy && vz && fx && fy && fz && species), "null device array");
+  ARG(masses_host[0] > 0 && masses_host[1] > 0, "masses must be positive");
+  ARG(std::isfinite(dt) && t_target > 0 && tau > 0, "dt finite, t_target and tau positive");
+  {
+    StageTimer tm(s, FLARE_T_MD);
+    nvt_first(s, x, y, z, vx, vy, vz, fx, fy, fz, species, masses_host, dt, t_target, tau, thermo);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_nvt_second_half(flare_state* s, double* vx, double* vy, double* vz, const float* fx, const float* fy,
+                          const float* fz, const int32_t* species, const double* masses_host, double dt,
+                          double t_target, double tau, double* thermo) {
+  ARG(s && masses_host && thermo, "null pointer");
+  if (!s->have_list) {
+    set_error("integrator needs the atom count of a neighbour list");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (vx && vy && vz && fx && fy && fz && species), "null device array");
+  ARG(masses_host[0] > 0 && masses_host[1] > 0, "masses must be positive");
+  ARG(std::isfinite(dt) && t_target > 0 && tau > 0, "dt finite, t_target and tau positive");
+  {
+    StageTimer tm(s, FLARE_T_MD);
+    nvt_second(s, vx, vy, vz, fx, fy, fz, species, masses_host, dt, t_target, tau, thermo, true);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_kinetic(flare_state* s, double* vx, double* vy, double* vz, const int32_t* species,
+                  const double* masses_host, double* thermo) {
+  ARG(s && masses_host && thermo, "null pointer");
+  if (!s->have_list) {
+    set_error("flare_kinetic needs the cell layout of a neighbour list");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (vx && vy && vz && species), "null device array");
+  ARG(masses_host[0] > 0 && masses_host[1] > 0, "masses must be positive");
+  nvt_second(s, vx, vy, vz, nullptr, nullptr, nullptr, species, masses_host, 0.0, 1.0, 1.0, thermo, false);
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_coordination(flare_state* s, int32_t* coord, const int32_t* coord_prev, int64_t* events) {
+  ARG(s && coord, "null pointer");
+  ARG((coord_prev == nullptr) == (events == nullptr), "pass coord_prev and events together");
+  if (!s->have_desc) {
+    set_error("flare_coordination needs positions staged by flare_descriptors");
+    return FLARE_E_STALE;
+  }
+  coordination(s, coord, coord_prev, events);
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
 int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* bytes) {
   ARG(bytes, "null pointer");
   long long b = 0;

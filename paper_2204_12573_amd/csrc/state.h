@@ -235,6 +235,14 @@ void md_first(flare_state* s, double* x, double* y, double* z, double* vx, doubl
 void md_second(flare_state* s, double* vx, double* vy, double* vz, const float* fx,
                const float* fy, const float* fz, const int32_t* species, double inv_m0,
                double inv_m1, double dt);
+// Nose-Hoover halves, kinetic energy, coordination (thermo.hip)
+void nvt_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+               const float* fx, const float* fy, const float* fz, const int32_t* species, const double* masses,
+               double dt, double t0, double tau, double* thermo);
+void nvt_second(flare_state* s, double* vx, double* vy, double* vz, const float* fx, const float* fy,
+                const float* fz, const int32_t* species, const double* masses, double dt, double t0, double tau,
+                double* thermo, bool update);
+void coordination(flare_state* s, int32_t* coord, const int32_t* prev, int64_t* events);
 void set_error(const std::string& msg);
 // FP8 fragments from FP32 values in fragment order [groups][lane 64][8] (fused.hip)
 void make_fp8_fragments(const float* vals, int groups, uint64_t* out);

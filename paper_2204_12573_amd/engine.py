@@ -200,6 +200,41 @@ class Evaluator:
                                                   B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species),
                                                   B.ptr(MASSES), float(dt)))
 
+    # ---- Nose-Hoover NVT and coordination (production runs) ----
+    def new_thermostat(self, vel):
+        """Per-cell thermostat state (zeta, eta, K) on the device, zeta = eta = 0 and K of vel."""
+        thermo = torch.zeros((self.n_struct, 3), dtype=torch.float64, device=self.device)
+        self.kinetic(vel, thermo)
+        return thermo
+
+    def kinetic(self, vel, thermo):
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_kinetic(self.handle, B.ptr(vel[0]), B.ptr(vel[1]), B.ptr(vel[2]),
+                                           B.ptr(self.species), B.ptr(MASSES), B.ptr(thermo)))
+
+    def nvt_first_half(self, pos, vel, f, dt, t_target, tau, thermo):
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_nvt_first_half(self.handle, B.ptr(pos[0]), B.ptr(pos[1]), B.ptr(pos[2]),
+                                                  B.ptr(vel[0]), B.ptr(vel[1]), B.ptr(vel[2]), B.ptr(f[0]),
+                                                  B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species), B.ptr(MASSES),
+                                                  float(dt), float(t_target), float(tau), B.ptr(thermo)))
+
+    def nvt_second_half(self, vel, f, dt, t_target, tau, thermo):
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_nvt_second_half(self.handle, B.ptr(vel[0]), B.ptr(vel[1]), B.ptr(vel[2]),
+                                                   B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species),
+                                                   B.ptr(MASSES), float(dt), float(t_target), float(tau),
+                                                   B.ptr(thermo)))
+
+    def coordination(self, prev=None):
+        """H coordination numbers (device int32 [N], caller order) of the staged positions and,
+        given an earlier snapshot, the (dissociation, recombination) counts per cell."""
+        coord = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        events = torch.zeros((self.n_struct, 2), dtype=torch.int64, device=self.device) if prev is not None else None
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_coordination(self.handle, B.ptr(coord), B.ptr(prev), B.ptr(events)))
+        return coord, events
+
 
 def to_device(pos, species, device="cuda"):
     """numpy [N,3] FP64 + [N] int -> device SoA [3,N] FP64 and int32 [N]."""
@@ -234,3 +269,53 @@ class MD:
         ev.energy_forces(self.out, self.want_var)
         ev.md_second_half(self.vel, self.out["f"], self.dt)
         return self.out
+
+
+class NVT(MD):
+    """Nose-Hoover NVT (one thermostat per cell, flare_nvt_*_half) with the same list cadence.
+    `thermo` holds (zeta, eta, K) per cell on the device."""
+
+    def __init__(self, ev: Evaluator, pos, vel, species, offsets, boxes, t_target, tau, dt=0.1, skin=0.2,
+                 rebuild=10, want_var=True):
+        super().__init__(ev, pos, vel, species, offsets, boxes, dt, skin, rebuild, want_var)
+        self.t_target, self.tau = t_target, tau
+        self.thermo = ev.new_thermostat(vel)
+
+    def step(self):
+        ev = self.ev
+        ev.nvt_first_half(self.pos, self.vel, self.out["f"], self.dt, self.t_target, self.tau, self.thermo)
+        self.nstep += 1
+        if self.nstep % self.rebuild == 0:
+            ev.neighbors(self.pos, self.species, self.offsets, self.boxes, self.skin)
+        ev.descriptors(self.pos)
+        ev.energy_forces(self.out, self.want_var)
+        ev.nvt_second_half(self.vel, self.out["f"], self.dt, self.t_target, self.tau, self.thermo)
+        return self.out
+
+
+class Production:
+    """The in-situ work of the paper's production runs (Section VI.A) around an NVT run:
+    every `every` steps, hydrogen coordination numbers, the reaction events since the last
+    snapshot (dissociations 1 -> 0, recombinations 0 -> 1) and the largest uncertainty per
+    cell against the active-learning threshold (sigma > threshold flags the cell)."""
+
+    def __init__(self, nvt: NVT, every=1000, threshold=0.005):
+        self.nvt, self.every, self.threshold = nvt, every, threshold
+        self.coord, _ = nvt.ev.coordination()
+        self.events = torch.zeros((nvt.ev.n_struct, 2), dtype=torch.int64, device=nvt.ev.device)
+        self.sigma_max = torch.zeros(nvt.ev.n_struct, dtype=torch.float32, device=nvt.ev.device)
+        self.flagged = []
+
+    def step(self):
+        out = self.nvt.step()
+        if self.nvt.nstep % self.every == 0:
+            ev = self.nvt.ev
+            coord, ev_counts = ev.coordination(self.coord)
+            self.events += ev_counts
+            self.coord = coord
+            smax = ev.variance()["sigma_max"]
+            self.sigma_max = torch.maximum(self.sigma_max, smax)
+            hot = torch.nonzero(smax > self.threshold).flatten().cpu().tolist()
+            if hot:
+                self.flagged.append((self.nvt.nstep, hot))
+        return out
