@@ -15,9 +15,9 @@
 //      tile;
 //   4. either g is copied out coalesced as G[tile][k][row] (the layout the standalone
 //      adjoint kernel reads with one lane pair per row), or, when the forces are wanted
-//      now, the lane pairs take their row's densities back (parked in G by step 1), form
+//      now, the lane pairs keep their row's densities from step 1 in registers, form
 //      u = G^ c from the gradient tile in LDS and write the per-pair terms w (adjoint.h):
-//      g never goes to HBM. The forces variant runs with every wave on its own 32-row
+//      neither g nor c goes to HBM. The forces variant runs with every wave on its own 32-row
 //      sub-tiles (k_fused144_w): each of the steps touches only the wave's own rows.
 // Inside a 16-wide K chunk, k-step t of lane group q uses k = 4q + t for A and B alike.
 #include <type_traits>
@@ -50,8 +50,7 @@ struct FusedArgs {
   const uint4* L6[4];    // three-way BF16 form: L, same layout
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
   int vchol;             // part 1 of Wf holds the Cholesky factor L: V = |L^T d|^2
-  float* G;              // [tiles][144][128]: g (no forces here), or the densities of each
-                         // tile between its descriptor and adjoint phases (forces here)
+  float* G;              // [tiles][144][128]: g, when the forces are not formed here
   float4* w;             // per-slot adjoint terms (written when the forces are formed here)
   float* nrm;            // per atom
   float* e_int;
@@ -516,26 +515,18 @@ __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
   return m;
 }
 
-// 1. descriptors of the tile's rows into the LDS tile (thread t of 256: row t/2, half t&1)
-// cstore (optional): the tile's densities are also written there, c[n][q] of thread t
-// at cstore[(8n + q) * 256 + t] (coalesced), for the adjoint phase of the same tile.
+// 1. descriptors of the tile's rows into the LDS tile (thread t of 256: row t/2, half t&1);
+// the densities are left in c for the adjoint phase of the same rows.
 template <int PREC>
 __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float* nrm_s, float* rsc_s, int row0,
-                                           int t, float* cstore, int cstride = FT) {
+                                           int t, float (&c)[NR][NQ]) {
   const int rl = t >> 1, h = t & 1;
   const int i = a.aor[row0 + rl];
-  float c[NR][NQ];
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
   if (i >= 0) accumulate_half(a.v, row0 + rl, h, c);
-  if (cstore) {
-#pragma unroll
-    for (int n = 0; n < NR; ++n)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) cstore[(n * NQ + q) * cstride + t] = c[n][q];
-  }
   // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
   // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
   // |d~|^2: FP64 in the split forms (their norms stay FP64), FP32 in the FP32 form (144
@@ -649,16 +640,12 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 }
 
 // 4. adjoint in place: u = G^ c from the gradient tile, then the per-pair terms. The
-// densities come from cstore (written by desc_phase) instead of a second pass over the pairs.
+// densities c come from the descriptor phase of the same rows, kept in registers through
+// the forms phase (no second pass over the pairs, no round trip through memory).
 __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t,
-                                              const float* cstore, int cstride = FT) {
+                                              float (&c)[NR][NQ]) {
   const int rl = t >> 1, h = t & 1;
   if (a.aor[row0 + rl] < 0) return;
-  float c[NR][NQ];
-#pragma unroll
-  for (int n = 0; n < NR; ++n)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) c[n][q] = cstore[(n * NQ + q) * cstride + t];
   u_transform_half(As + rl * AS, 1, h, c);
   adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
 }
@@ -673,7 +660,10 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const int t = threadIdx.x;
-  desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, nullptr);
+  {
+    float c[NR][NQ];
+    desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, c);
+  }
   __syncthreads();
   if (a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
@@ -699,8 +689,7 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
 // 32-row sub-tiles (its index, then + the number of waves in the grid) and runs
 // descriptors, forms and adjoint on them back to back, with no work-group barrier. The two
 // waves that share a SIMD drift apart, so their vector and matrix work interleave on the
-// shared datapath. Densities are parked in the sub-tile's slice of G (64 lanes x 64 floats
-// fit in its 32 x 144).
+// shared datapath.
 constexpr int WR = 32;          // rows per wave sub-tile
 constexpr int WW = 8;           // waves per work-group
 
@@ -727,12 +716,12 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
   float* rs = rsc_s[wv];
   for (int st = blockIdx.x * WW + wv; st < nsub; st += nw) {
     const int row0 = st * WR;
-    float* cs = a.G + (size_t)st * WR * ND1;
-    desc_phase<PREC>(a, A, ns, rs, row0, lane, cs, 64);
+    float c[NR][NQ];
+    desc_phase<PREC>(a, A, ns, rs, row0, lane, c);
     wave_phase_fence();
     forms_phase<PREC, false>(a, A, ns, rs, row0, lane, tile_model(a, row0));
     wave_phase_fence();
-    adjoint_phase(a, A, row0, lane, cs, 64);
+    adjoint_phase(a, A, row0, lane, c);
     wave_phase_fence();
   }
 }
