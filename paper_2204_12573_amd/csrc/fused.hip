@@ -55,6 +55,8 @@ struct FusedArgs {
   float* nrm;            // per atom
   float* e_int;
   float* v_int;
+  float* e_row;          // the same per row
+  float* v_row;
   float* D_out;          // optional [rows][144] normalised descriptors
 };
 
@@ -595,7 +597,11 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
           const int rl = wave * 32 + i * 16 + 4 * grp + r;
           const int atom = a.aor[row0 + rl];
           const float nv = nrm_s[rl];
-          if (atom >= 0) a.v_int[atom] = nv > 0.f ? dots[i][r] / (nv * nv) : 0.f;
+          if (atom >= 0) {
+            const float v = nv > 0.f ? dots[i][r] / (nv * nv) : 0.f;
+            a.v_int[atom] = v;
+            a.v_row[row0 + rl] = v;
+          }
         }
     }
   }
@@ -629,7 +635,10 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
         const float nv = nrm_s[rl];
         const float inv2 = nv > 0.f ? 1.f / (nv * nv) : 0.f;
         const float e = dots[i][r] * inv2;        // e = Y~ . d~ / |d~|^2
-        if (l16 == 0 && atom >= 0) a.e_int[atom] = e;
+        if (l16 == 0 && atom >= 0) {
+          a.e_int[atom] = e;
+          a.e_row[row0 + rl] = e;
+        }
         const float s2 = 2.f * inv2;              // g = (2/|d~|^2) (Y~ - e d~)
         float* d = As + rl * AS + l16;
         // each lane reads its own d-elements before overwriting them with g
@@ -755,6 +764,8 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   a.nrm = s->nrm;
   a.e_int = s->e_int;
   a.v_int = s->v_int;
+  a.e_row = s->e_row.p;
+  a.v_row = s->v_row.p;
   a.D_out = d_out;
   const int ntiles = s->rows1 / FR;
   a.mode = mode & 3;

@@ -288,6 +288,20 @@ __global__ __launch_bounds__(NT) void k_slice_len(int n, const int* __restrict__
   atomicMax(&slice_len[global_row(b, row_of[i], rows1) >> 5], cnt[i]);
 }
 
+// Per-row copies of the atom's caller index, pair count and cell (padding rows: -1, 0, 0).
+__global__ __launch_bounds__(NT) void k_row_meta(int rows, int rows1, const int* __restrict__ aor1,
+                                                 const int* __restrict__ aorx, const int* __restrict__ perm,
+                                                 const int* __restrict__ cnt, const int* __restrict__ sid,
+                                                 int* __restrict__ perm_row, int* __restrict__ cnt_row,
+                                                 int* __restrict__ sid_row) {
+  const int R = blockIdx.x * NT + threadIdx.x;
+  if (R >= rows) return;
+  const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
+  perm_row[R] = i >= 0 ? perm[i] : -1;
+  cnt_row[R] = i >= 0 ? cnt[i] : 0;
+  sid_row[R] = i >= 0 ? sid[i] : 0;
+}
+
 // One thread per row: the row's own pairs into its slots, the rest of its slice length
 // (and every slot of a padding row) marked empty. Writes of a slice's 32 rows are
 // contiguous for each k.
@@ -494,6 +508,15 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->nl_cnt, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
   }
+  HIPCHK(s->perm_row.reserve((size_t)r1 + rx + 1));
+  HIPCHK(s->cnt_row.reserve((size_t)r1 + rx + 1));
+  HIPCHK(s->sid_row.reserve((size_t)r1 + rx + 1));
+  HIPCHK(s->e_row.reserve((size_t)r1 + rx + 1));
+  HIPCHK(s->v_row.reserve((size_t)r1 + rx + 1));
+  if (r1 + rx > 0)
+    k_row_meta<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p, s->perm,
+                                                      s->nl_cnt, s->sid, s->perm_row.p, s->cnt_row.p,
+                                                      s->sid_row.p);
   // sliced layout: slice lengths, their prefix, then the slots
   s->n_slices = (r1 + rx) / 32;
   HIPCHK(s->slice_len.reserve(s->n_slices + 1));

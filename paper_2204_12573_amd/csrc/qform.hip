@@ -192,7 +192,9 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
                                                       const float* __restrict__ nrm,
                                                       float* __restrict__ G,
                                                       float* __restrict__ e_int,
-                                                      float* __restrict__ v_int) {
+                                                      float* __restrict__ v_int,
+                                                      float* __restrict__ e_row,
+                                                      float* __restrict__ v_row) {
   // one wave per row
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -211,8 +213,8 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
     for (int k = first; k < first + half; ++k) v += p[k];
   }
   if (lane == 0) {
-    if (has_e) e_int[atom] = e;
-    if (has_v) v_int[atom] = v;
+    if (has_e) e_int[atom] = e, e_row[row] = e;
+    if (has_v) v_int[atom] = v, v_row[row] = v;
   }
   if (!has_e) return;
   const float nv = nrm[atom];
@@ -252,7 +254,8 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   const int ntiles = 2 * parts;   // 272 columns per tile
   k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
   k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
-                                                        s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int);
+                                                        s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int,
+                                                        s->e_row.p + s->rows1, s->v_row.p + s->rows1);
 }
 
 }  // namespace flare

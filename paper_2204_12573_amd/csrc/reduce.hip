@@ -10,32 +10,30 @@ namespace {
 
 constexpr int NT = 256;
 
-// Caller-order outputs, one thread per row. Forces by gathering the per-pair adjoint
-// terms over the row's slots: F_i = sum_k (w(slot(i,k)) - w_in(slot(i,k))) for the row's
-// own pairs k < count, in slot order (deterministic); w_in holds each slot's reverse term.
-__global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* __restrict__ aor1,
-                                                const int* __restrict__ aorx,
-                                                const int* __restrict__ slice_base,
+// Caller-order outputs, one thread per row; every per-row input is read in row order
+// (coalesced). Forces by gathering the per-pair adjoint terms over the row's slots:
+// F_i = sum_k (w(slot(i,k)) - w_in(slot(i,k))) for the row's own pairs k < count, in slot
+// order (deterministic); w_in holds each slot's reverse term.
+__global__ __launch_bounds__(NT) void k_outputs(int rows, const int* __restrict__ slice_base,
                                                 const float4* __restrict__ w,
                                                 const float4* __restrict__ w_in,
-                                                const int* __restrict__ perm,
-                                                const int* __restrict__ cnt,
-                                                const int* __restrict__ sid,
+                                                const int* __restrict__ perm_row,
+                                                const int* __restrict__ cnt_row,
+                                                const int* __restrict__ sid_row,
                                                 const double* __restrict__ cell_scale,
-                                                const float* __restrict__ e_int,
-                                                const float* __restrict__ v_int,
+                                                const float* __restrict__ e_row,
+                                                const float* __restrict__ v_row,
                                                 float* __restrict__ e_atom, float* __restrict__ fx,
                                                 float* __restrict__ fy, float* __restrict__ fz,
                                                 float* __restrict__ var_atom,
                                                 float* __restrict__ sigma_atom) {
   const int R = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   if (R >= rows) return;
-  const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
-  if (i < 0) return;
-  const int a = perm[i];
-  if (e_atom) e_atom[a] = e_int[i];
+  const int a = perm_row[R];
+  if (a < 0) return;
+  if (e_atom) e_atom[a] = e_row[R];
   if (fx) {
-    const int base = slice_base[R >> 5], len = cnt[i];   // the row's own pairs (no padding)
+    const int base = slice_base[R >> 5], len = cnt_row[R];   // the row's own pairs (no padding)
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int k = 0; k < len; ++k) {
       const int slot = (base + k) * 32 + (R & 31);
@@ -46,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* 
       sz += wo.z - wr.z;
     }
     if (cell_scale) {
-      const float k = (float)cell_scale[sid[i]];
+      const float k = (float)cell_scale[sid_row[R]];
       sx *= k;
       sy *= k;
       sz *= k;
@@ -55,9 +53,11 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, int rows1, const int* 
     fy[a] = sy;
     fz[a] = sz;
   }
-  const float v = v_int[i];
-  if (var_atom) var_atom[a] = v;
-  if (sigma_atom) sigma_atom[a] = sqrtf(fmaxf(v, 0.f));
+  if (var_atom || sigma_atom) {
+    const float v = v_row[R];
+    if (var_atom) var_atom[a] = v;
+    if (sigma_atom) sigma_atom[a] = sqrtf(fmaxf(v, 0.f));
+  }
 }
 
 // Atoms without any neighbour in the list radius: zero energy, force and variance.
@@ -297,9 +297,9 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
   if (n == 0) return;
   const int rows = s->rows1 + s->rowsx;
   if (rows > 0)
-    k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
-                                                         s->slice_base.p, s->w_slot.p, s->w_in.p, s->perm,
-                                                         s->nl_cnt, s->sid, cell_scale, s->e_int, s->v_int, e_atom, fx, fy, fz, var_atom,
+    k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->slice_base.p, s->w_slot.p, s->w_in.p,
+                                                         s->perm_row.p, s->cnt_row.p, s->sid_row.p, cell_scale,
+                                                         s->e_row.p, s->v_row.p, e_atom, fx, fy, fz, var_atom,
                                                          sigma_atom);
   k_outputs_empty<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->bucket, s->perm, e_atom, fx, fy, fz, var_atom,
                                                            sigma_atom);

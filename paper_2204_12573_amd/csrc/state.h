@@ -190,6 +190,9 @@ struct flare_state {
   flare::DevBuf<float4> w_slot;                      // per slot: de_i/dDelta (x, y, z, 0)
   flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
   flare::DevBuf<int2> pair_cache;                    // list build: first pairs of each atom
+  // per row (144-wide rows, then mixed rows), so that the output pass reads them in row order
+  flare::DevBuf<int> perm_row, cnt_row, sid_row;     // caller index (-1: padding), pairs, cell
+  flare::DevBuf<float> e_row, v_row;                 // per step: e_i, V_i
   // virial (allocated at the first flare_virial call)
   flare::DevBuf<float> vir_int;                      // [9][max_atoms] per internal atom
   flare::DevBuf<double> red_w;                       // [tasks][9]
