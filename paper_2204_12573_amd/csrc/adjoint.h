@@ -113,11 +113,12 @@ __device__ __forceinline__ void u_transform_half(const float* g, int gstride, in
 }
 
 // Exchange the two halves of u so that both lanes of the row hold all of it, then split
-// the row's slots between the lanes (k = h, h + 2, ...): each pair term is evaluated once,
-// written to its slot (zero for padding and pairs outside the cutoff) and scattered to
-// the reverse pair's slot of w_in, where the force gather of the neighbour reads it.
+// the row's slots between the lanes (k = h, h + 2, ...): each pair term is evaluated once
+// and scattered to the reverse pair's slot of w_in, where the force gather of the
+// neighbour reads it; the row's own terms are summed (each lane over its slots in order,
+// then the two lanes) into f_own[R].
 __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int h, const float (&c)[NR][NQ],
-                                                   float4* __restrict__ w) {
+                                                   float4* __restrict__ f_own) {
   float u[NR][NLM];
 #pragma unroll
   for (int n = 0; n < NR; ++n)
@@ -141,6 +142,7 @@ __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int
     gb[e] = k < len ? v.geom[s0 + (size_t)k * 32] : zero;
     rb[e] = k < len ? v.rev[s0 + (size_t)k * 32] : 0;
   }
+  float sx = 0.f, sy = 0.f, sz = 0.f;
   for (int k0 = h; k0 < len; k0 += 4) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -157,12 +159,17 @@ __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int
         int sp;
         float wx = 0.f, wy = 0.f, wz = 0.f;
         if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
-        const float4 wk = make_float4(wx, wy, wz, 0.f);
-        w[s0 + (size_t)k * 32] = wk;
-        v.w_in[rk] = wk;
+        v.w_in[rk] = make_float4(wx, wy, wz, 0.f);
+        sx += wx;
+        sy += wy;
+        sz += wz;
       }
     }
   }
+  sx += xor1(sx);
+  sy += xor1(sy);
+  sz += xor1(sz);
+  if (h == 0) f_own[R] = make_float4(sx, sy, sz, 0.f);
 }
 
 }  // namespace flare

@@ -17,7 +17,7 @@ constexpr int TA = 256;   // threads of the 144-row adjoint kernel (128 rows, 2 
 // One row per lane pair (see half.h and adjoint.h), reading g from the tile-transposed
 // G[tile][k][128] written by the quadratic-form kernel.
 __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __restrict__ atom_of_row,
-                                                   const float* __restrict__ G, float4* __restrict__ w) {
+                                                   const float* __restrict__ G, float4* __restrict__ f_own) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int t = threadIdx.x, rl = t >> 1, h = t & 1;
   const int i = atom_of_row[tile * 128 + rl];
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __rest
   const int R = tile * 128 + rl;
   accumulate_half(v, R, h, c);
   u_transform_half(G + (size_t)tile * ND1 * 128 + rl, 128, h, c);
-  adjoint_pairs_half(v, R, h, c, w);
+  adjoint_pairs_half(v, R, h, c, f_own);
 }
 
 // Mixed rows, 16 lanes per row (mixed.h): lane a = s*8 + n forms its density channel,
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __rest
 // over the lanes (k = L, L + 16, ...), each pair reading u of its neighbour species from LDS.
 __global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows1,
                                                             const int* __restrict__ atom_of_row,
-                                                            const float* __restrict__ G, float4* __restrict__ w) {
+                                                            const float* __restrict__ G, float4* __restrict__ f_own) {
   __shared__ __attribute__((aligned(16))) float cs[MROWS * MSTRIDE];
   const int rl = threadIdx.x >> 4, L = threadIdx.x & 15;
   const int row = blockIdx.x * MROWS + rl;
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows
   if (i < 0) return;
   const int base = v.slice_base[R >> 5];
   const int len = v.slice_base[(R >> 5) + 1] - base;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
   for (int k = L; k < len; k += 16) {
     const size_t slot = (size_t)(base + k) * 32 + (R & 31);
     PairGeom pg;
@@ -98,10 +99,16 @@ __global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows
     float wx = 0.f, wy = 0.f, wz = 0.f;
     if (unpack_geom(v.geom[slot], pg, sp))
       pair_force(pg, v.rc, [&](int n, int lm) { return crow[cidx(sp * NR + n, lm)]; }, wx, wy, wz);
-    const float4 wk = make_float4(wx, wy, wz, 0.f);
-    w[slot] = wk;
-    v.w_in[v.rev[slot]] = wk;
+    v.w_in[v.rev[slot]] = make_float4(wx, wy, wz, 0.f);
+    sx += wx;
+    sy += wy;
+    sz += wz;
   }
+  // the row's own terms: each lane's slots in order, then the 16 lanes
+  sx = sum16(sx);
+  sy = sum16(sy);
+  sz = sum16(sz);
+  if (L == 0) f_own[R] = make_float4(sx, sy, sz, 0.f);
 }
 
 }  // namespace
@@ -111,13 +118,13 @@ void compute_forces(flare_state* s, bool rows144) {
   if (rows144) {
     StageTimer tm(s, FLARE_T_FORCE1);
     if (s->rows1 > 0)
-      k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->w_slot.p);
+      k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->f_own.p);
   }
   {
     StageTimer tm(s, FLARE_T_FORCEX);
     if (s->rowsx > 0)
       k_adjoint_mixed<<<s->rowsx / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, s->atom_of_rowx.p, s->Gx.p,
-                                                                    s->w_slot.p);
+                                                                    s->f_own.p);
   }
 }
 

@@ -51,7 +51,7 @@ struct FusedArgs {
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
   int vchol;             // part 1 of Wf holds the Cholesky factor L: V = |L^T d|^2
   float* G;              // [tiles][144][128]: g, when the forces are not formed here
-  float4* w;             // per-slot adjoint terms (written when the forces are formed here)
+  float4* f_own;         // per row: sum of its own pair terms (written when the forces are formed here)
   float* nrm;            // per atom
   float* e_int;
   float* v_int;
@@ -656,7 +656,7 @@ __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* A
   const int rl = t >> 1, h = t & 1;
   if (a.aor[row0 + rl] < 0) return;
   u_transform_half(As + rl * AS, 1, h, c);
-  adjoint_pairs_half(a.v, row0 + rl, h, c, a.w);
+  adjoint_pairs_half(a.v, row0 + rl, h, c, a.f_own);
 }
 
 // One tile per work-group, phases in sequence (descriptor export, energies or variances
@@ -760,7 +760,7 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
   }
   a.vchol = s->model->vchol ? 1 : 0;
   a.G = s->G1.p;
-  a.w = s->w_slot.p;
+  a.f_own = s->f_own.p;
   a.nrm = s->nrm;
   a.e_int = s->e_int;
   a.v_int = s->v_int;

@@ -545,7 +545,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->slot_pair.reserve(nslots + 1));
   HIPCHK(s->slot_rev.reserve(nslots + 1));
   HIPCHK(s->geom.reserve(nslots + 1));
-  HIPCHK(s->w_slot.reserve(nslots + 1));
+  HIPCHK(s->f_own.reserve((size_t)r1 + rx + 1));
   HIPCHK(s->w_in.reserve(nslots + 1));
   if (r1 + rx > 0)
     k_fill_slots<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p,

@@ -11,11 +11,11 @@ namespace {
 constexpr int NT = 256;
 
 // Caller-order outputs, one thread per row; every per-row input is read in row order
-// (coalesced). Forces by gathering the per-pair adjoint terms over the row's slots:
-// F_i = sum_k (w(slot(i,k)) - w_in(slot(i,k))) for the row's own pairs k < count, in slot
-// order (deterministic); w_in holds each slot's reverse term.
+// (coalesced). Forces: F_i = sum_k w(i,k) - sum_k w_in(slot(i,k)), the first sum (the row's
+// own pair terms) formed by the adjoint as f_own, the second over the row's own pairs
+// k < count in slot order (deterministic); w_in holds each slot's reverse term.
 __global__ __launch_bounds__(NT) void k_outputs(int rows, const int* __restrict__ slice_base,
-                                                const float4* __restrict__ w,
+                                                const float4* __restrict__ f_own,
                                                 const float4* __restrict__ w_in,
                                                 const int* __restrict__ perm_row,
                                                 const int* __restrict__ cnt_row,
@@ -34,15 +34,15 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, const int* __restrict_
   if (e_atom) e_atom[a] = e_row[R];
   if (fx) {
     const int base = slice_base[R >> 5], len = cnt_row[R];   // the row's own pairs (no padding)
-    float sx = 0.f, sy = 0.f, sz = 0.f;
+    float rx = 0.f, ry = 0.f, rz = 0.f;
     for (int k = 0; k < len; ++k) {
-      const int slot = (base + k) * 32 + (R & 31);
-      const float4 wo = w[slot];
-      const float4 wr = w_in[slot];
-      sx += wo.x - wr.x;
-      sy += wo.y - wr.y;
-      sz += wo.z - wr.z;
+      const float4 wr = w_in[(base + k) * 32 + (R & 31)];
+      rx += wr.x;
+      ry += wr.y;
+      rz += wr.z;
     }
+    const float4 fo = f_own[R];
+    float sx = fo.x - rx, sy = fo.y - ry, sz = fo.z - rz;
     if (cell_scale) {
       const float k = (float)cell_scale[sid_row[R]];
       sx *= k;
@@ -165,13 +165,15 @@ __global__ __launch_bounds__(NC) void k_reduce_cells(const double* __restrict__ 
   }
 }
 
-// Per-row virial W_i = -sum_k Delta_k (x) w_k over the row's own pairs (Delta = r u from
-// the slot geometry, w = de_i/dDelta from the adjoint), in slot order; [9][n] internal.
+// Per-row virial terms over the row's own pairs in slot order, [9][n] internal. The cell's
+// W = -sum_p Delta_p (x) w_p runs over all its pairs; the reverse q of p has Delta_q =
+// -Delta_p and w_in(slot p) = w_q, so relabelling the sum gives W = sum_p Delta_p (x)
+// w_in(slot p), which each row forms from its own slots (Delta = r u from the geometry).
 __global__ __launch_bounds__(NT) void k_virial_rows(int rows, int rows1, const int* __restrict__ aor1,
                                                     const int* __restrict__ aorx,
                                                     const int* __restrict__ slice_base,
                                                     const float4* __restrict__ geom,
-                                                    const float4* __restrict__ w,
+                                                    const float4* __restrict__ w_in,
                                                     const int* __restrict__ cnt, int n,
                                                     float* __restrict__ vir) {
   const int R = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
@@ -185,14 +187,14 @@ __global__ __launch_bounds__(NT) void k_virial_rows(int rows, int rows1, const i
   for (int k = 0; k < len; ++k) {
     const int slot = (base + k) * 32 + (R & 31);
     const float4 g = geom[slot];
-    const float4 wk = w[slot];
+    const float4 wk = w_in[slot];
     const float r = fabsf(g.w);      // 0 outside the cutoff: no contribution
     const float d[3] = {r * g.x, r * g.y, r * g.z};
     const float ww[3] = {wk.x, wk.y, wk.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) acc[3 * a + b] -= d[a] * ww[b];
+      for (int b = 0; b < 3; ++b) acc[3 * a + b] += d[a] * ww[b];
   }
 #pragma unroll
   for (int c = 0; c < 9; ++c) vir[(size_t)c * n + i] = acc[c];
@@ -297,7 +299,7 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
   if (n == 0) return;
   const int rows = s->rows1 + s->rowsx;
   if (rows > 0)
-    k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->slice_base.p, s->w_slot.p, s->w_in.p,
+    k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->slice_base.p, s->f_own.p, s->w_in.p,
                                                          s->perm_row.p, s->cnt_row.p, s->sid_row.p, cell_scale,
                                                          s->e_row.p, s->v_row.p, e_atom, fx, fy, fz, var_atom,
                                                          sigma_atom);
@@ -322,7 +324,7 @@ void virial_cells(flare_state* s, double* virial_struct) {
   const int nt = (int)s->tasks.size();
   if (rows > 0)
     k_virial_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
-                                                             s->slice_base.p, s->geom.p, s->w_slot.p, s->nl_cnt, n,
+                                                             s->slice_base.p, s->geom.p, s->w_in.p, s->nl_cnt, n,
                                                              s->vir_int.p);
   if (nt > 0)
     k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->vir_int.p, n, s->red_w.p);

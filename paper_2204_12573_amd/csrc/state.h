@@ -62,7 +62,7 @@ struct SlotView {
                             // cutoff or padding; r < 0 marks an H neighbour, r > 0 Pt
   const int* slice_base;    // [slices + 1] in groups of 32 slots
   const int* rev;           // per slot: slot of the reverse pair (padding: itself)
-  float4* w_in;             // per slot: the adjoint term of the reverse pair, scattered there
+  float4* w_in;             // per slot: the adjoint term de_j/dDelta of the reverse pair
   float rc;
 };
 
@@ -187,7 +187,7 @@ struct flare_state {
   flare::DevBuf<int> slice_len, slice_base;          // [slices (+1)]
   flare::DevBuf<int> slot_atom, slot_j, slot_s, slot_pair, slot_rev;
   flare::DevBuf<float4> geom;                        // per slot, per step
-  flare::DevBuf<float4> w_slot;                      // per slot: de_i/dDelta (x, y, z, 0)
+  flare::DevBuf<float4> f_own;                       // per row: sum of de_i/dDelta over its own pairs
   flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
   flare::DevBuf<int2> pair_cache;                    // list build: first pairs of each atom
   // per row (144-wide rows, then mixed rows), so that the output pass reads them in row order
