@@ -277,15 +277,14 @@ __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ n
 // Row R of atom i: 144-wide rows R = row_of[i], mixed rows R = rows1 + row_of[i].
 __device__ inline int global_row(int b, int r, int rows1) { return b < 4 ? r : rows1 + r; }
 
-__global__ __launch_bounds__(NT) void k_slice_len(int n, const int* __restrict__ bucket,
-                                                  const int* __restrict__ row_of,
-                                                  const int* __restrict__ cnt, int rows1,
+// Length of each 32-row slice: the largest pair count of its rows (padding rows count 0).
+__global__ __launch_bounds__(NT) void k_slice_len(int nslices, const int* __restrict__ cnt_row,
                                                   int* __restrict__ slice_len) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  const int b = bucket[i];
-  if (b < 0) return;
-  atomicMax(&slice_len[global_row(b, row_of[i], rows1) >> 5], cnt[i]);
+  const int S = blockIdx.x * NT + threadIdx.x;
+  if (S >= nslices) return;
+  int m = 0;
+  for (int r = 0; r < 32; ++r) m = max(m, cnt_row[S * 32 + r]);
+  slice_len[S] = m;
 }
 
 // Per-row copies of the atom's caller index, pair count and cell (padding rows: -1, 0, 0).
@@ -312,8 +311,7 @@ __global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const in
                                                    const int32_t* __restrict__ nl_s,
                                                    const int* __restrict__ slice_base,
                                                    int* __restrict__ slot_atom, int* __restrict__ slot_j,
-                                                   int* __restrict__ slot_s, int* __restrict__ slot_pair,
-                                                   int* __restrict__ slot_of_pair) {
+                                                   int* __restrict__ slot_s, int* __restrict__ slot_pair) {
   const int R = blockIdx.x * NT + threadIdx.x;
   if (R >= rows) return;
   const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
@@ -327,7 +325,6 @@ __global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const in
       slot_j[slot] = nl_j[p];
       slot_s[slot] = nl_s[p];
       slot_pair[slot] = p;
-      slot_of_pair[p] = slot;
     } else {
       slot_atom[slot] = -1;
       slot_j[slot] = 0;
@@ -335,6 +332,22 @@ __global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const in
       slot_pair[slot] = 0;
     }
   }
+}
+
+// slot of every pair, one thread per atom in internal order (each writes its own contiguous
+// range of the pair array)
+__global__ __launch_bounds__(NT) void k_slot_of_pair(int n, const int* __restrict__ bucket,
+                                                     const int* __restrict__ row_of, int rows1,
+                                                     const int* __restrict__ nl_off,
+                                                     const int* __restrict__ slice_base,
+                                                     int* __restrict__ slot_of_pair) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int b = bucket[i];
+  if (b < 0) return;                  // no listed pairs
+  const int R = global_row(b, row_of[i], rows1);
+  const int base = slice_base[R >> 5], p0 = nl_off[i], own = nl_off[i + 1] - p0;
+  for (int k = 0; k < own; ++k) slot_of_pair[p0 + k] = (base + k) * 32 + (R & 31);
 }
 
 // slot of the reverse pair; padding slots point at themselves
@@ -521,9 +534,8 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   s->n_slices = (r1 + rx) / 32;
   HIPCHK(s->slice_len.reserve(s->n_slices + 1));
   HIPCHK(s->slice_base.reserve(s->n_slices + 1));
-  HIPCHK(hipMemsetAsync(s->slice_len.p, 0, (s->n_slices + 1) * sizeof(int), st));
-  if (n > 0)
-    k_slice_len<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, s->nl_cnt, r1, s->slice_len.p);
+  if (s->n_slices > 0)
+    k_slice_len<<<(s->n_slices + NT - 1) / NT, NT, 0, st>>>(s->n_slices, s->cnt_row.p, s->slice_len.p);
   HIPCHK(s->scan_scratch.reserve(scan_scratch_ints(std::max<long long>(scan_n, s->n_slices))));
   scan_exclusive(s->slice_len.p, s->slice_base.p, s->n_slices, s->scan_scratch.p, st);
   HIPCHK(hipMemcpyAsync(s->h_info + 9, s->slice_base.p + s->n_slices, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -550,7 +562,9 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   if (r1 + rx > 0)
     k_fill_slots<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p,
                                                         s->nl_off, s->nl_j, s->nl_s, s->slice_base.p, s->slot_atom.p,
-                                                        s->slot_j.p, s->slot_s.p, s->slot_pair.p, s->slot_of_pair);
+                                                        s->slot_j.p, s->slot_s.p, s->slot_pair.p);
+  if (n > 0)
+    k_slot_of_pair<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, r1, s->nl_off, s->slice_base.p, s->slot_of_pair);
   if (nslots > 0)
     k_rev_slots<<<(int)((nslots + NT - 1) / NT), NT, 0, st>>>(nslots, s->slot_atom.p, s->slot_pair.p, s->nl_rev,
                                                               s->slot_of_pair, s->slot_rev.p);
