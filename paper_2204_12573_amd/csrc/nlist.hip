@@ -262,11 +262,18 @@ __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ n
     const int32_t want = pack_shift(-sx, -sy, -sz);
     int found = -1;
     const int q1 = nl_off[j + 1];
-    for (int q = nl_off[j]; q < q1; ++q) {
-      if (nl_j[q] == i && nl_s[q] == want) {
-        found = q;
-        break;
+    // four entries per step, their loads issued together
+    for (int q = nl_off[j]; q < q1 && found < 0; q += 4) {
+      int jj[4];
+      int32_t ss[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        jj[u] = q + u < q1 ? nl_j[q + u] : -1;
+        ss[u] = q + u < q1 ? nl_s[q + u] : 0;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (found < 0 && jj[u] == i && ss[u] == want) found = q + u;
     }
     if (found < 0) atomicOr(status, 256);
     rev[p] = found < 0 ? p : found;
