@@ -728,7 +728,11 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
     float c[NR][NQ];
     desc_phase<PREC>(a, A, ns, rs, row0, lane, c);
     wave_phase_fence();
+    // the matrix-core phase issues first when both waves of a SIMD are ready: its MFMAs
+    // keep the shared datapath busy for 32 cycles each, the other wave fills the gaps
+    __builtin_amdgcn_s_setprio(1);
     forms_phase<PREC, false>(a, A, ns, rs, row0, lane, tile_model(a, row0));
+    __builtin_amdgcn_s_setprio(0);
     wave_phase_fence();
     adjoint_phase(a, A, row0, lane, c);
     wave_phase_fence();
