@@ -202,21 +202,29 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
           const int bb = g.bin_base + (cz * g.nb[1] + cy) * g.nb[0] + cx;
           const int j0 = bstart[bb], j1 = bstart[bb + 1];
           const bool zero_shift = (sx == 0) && (sy == 0) && (sz == 0);
-          for (int j = j0; j < j1; ++j) {
-            const double4 wj = w[j];
-            const double dx = (wj.x - wx) + tx;
-            const double dy = (wj.y - wy) + ty;
-            const double dz = (wj.z - wz) + tz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < rl2 && !(zero_shift && j == i)) {
-              if (FILL) {
-                nl_j[o + cnt] = j;
-                nl_s[o + cnt] = pack_shift(sx, sy, sz);
-              } else if (cnt < PAIR_CACHE) {
-                cache[(size_t)cnt * n + i] = make_int2(j, pack_shift(sx, sy, sz));
+          // the bin's atoms in order, four positions loaded per step
+          for (int j4 = j0; j4 < j1; j4 += 4) {
+            double4 wq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wq[u] = j4 + u < j1 ? w[j4 + u] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int j = j4 + u;
+              if (j >= j1) break;
+              const double dx = (wq[u].x - wx) + tx;
+              const double dy = (wq[u].y - wy) + ty;
+              const double dz = (wq[u].z - wz) + tz;
+              const double r2 = dx * dx + dy * dy + dz * dz;
+              if (r2 < rl2 && !(zero_shift && j == i)) {
+                if (FILL) {
+                  nl_j[o + cnt] = j;
+                  nl_s[o + cnt] = pack_shift(sx, sy, sz);
+                } else if (cnt < PAIR_CACHE) {
+                  cache[(size_t)cnt * n + i] = make_int2(j, pack_shift(sx, sy, sz));
+                }
+                mask |= 1 << sp[j];
+                ++cnt;
               }
-              mask |= 1 << sp[j];
-              ++cnt;
             }
           }
         }
