@@ -208,31 +208,49 @@ __device__ __forceinline__ void mfma_pass_bf16(const float* As, const uint4* __r
 #pragma unroll
     for (int j = 0; j < NCB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const uint4* Wp = W + lane;
+  // column blocks in groups of three with one register buffer of B (hi, lo) fragments:
+  // the lo parts for the next group load after the d_hi x beta_lo products, the hi parts
+  // after the last use
+  bf8 bh[3], bl[3];
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) {
+    bh[jj] = __builtin_bit_cast(bf8, Wp[(jj * 2 + 0) * 64]);
+    bl[jj] = __builtin_bit_cast(bf8, Wp[(jj * 2 + 1) * 64]);
+  }
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
     bf8 ahi[2], alo[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
       split8(&As[(wave * 32 + i * 16 + l16) * AS + ks * 32 + 8 * grp], ks == NKS - 1 && grp >= 2, ahi[i], alo[i]);
-    bf8 bhv[NCB], blv[NCB];
 #pragma unroll
-    for (int j = 0; j < NCB; ++j) {
-      bhv[j] = __builtin_bit_cast(bf8, Wp[((ks * NCB + j) * 2 + 0) * 64]);
-      blv[j] = __builtin_bit_cast(bf8, Wp[((ks * NCB + j) * 2 + 1) * 64]);
+    for (int jg = 0; jg < NCB / 3; ++jg) {
+      const int nks = jg + 1 < NCB / 3 ? ks : ks + 1, njg = jg + 1 < NCB / 3 ? jg + 1 : 0;
+      const bool more = nks < NKS;
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          acc[i][3 * jg + jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bl[jj], acc[i][3 * jg + jj], 0, 0, 0);
+      if (more) {
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) bl[jj] = __builtin_bit_cast(bf8, Wp[((nks * NCB + 3 * njg + jj) * 2 + 1) * 64]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          acc[i][3 * jg + jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bh[jj], acc[i][3 * jg + jj], 0, 0, 0);
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          acc[i][3 * jg + jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bh[jj], acc[i][3 * jg + jj], 0, 0, 0);
+      if (more) {
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) bh[jj] = __builtin_bit_cast(bf8, Wp[((nks * NCB + 3 * njg + jj) * 2 + 0) * 64]);
+      }
     }
-    // product outermost: consecutive MFMAs write different accumulators
-#pragma unroll
-    for (int j = 0; j < NCB; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int j = 0; j < NCB; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int j = 0; j < NCB; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhv[j], acc[i][j], 0, 0, 0);
   }
 }
 
