@@ -111,52 +111,6 @@ __device__ __forceinline__ void mfma_pass(const float* As, const float4* __restr
   }
 }
 
-// The same passes with one register buffer of B fragments: the fragment of column block j
-// for the next chunk is loaded as soon as the last k-step of the current chunk has used it
-// (36 VGPRs fewer; the remaining MFMAs of the chunk cover the load).
-template <int PART, bool TRI = false>
-__device__ __forceinline__ void mfma_pass_sb(const float* As, const float4* __restrict__ W, int wave, int lane,
-                                             f4 (&acc)[2][NCB]) {
-  const int l16 = lane & 15, grp = lane >> 4;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < NCB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  const float4* Wp = W + (size_t)PART * NKC * NCB * 64 + lane;
-  float4 b[NCB];
-  constexpr int K0 = TRI ? NKC - 1 : 0;
-#pragma unroll
-  for (int j = 0; j < NCB; ++j)
-    if (!TRI || j <= K0) b[j] = Wp[(K0 * NCB + j) * 64];
-#pragma unroll
-  for (int it = 0; it < NKC; ++it) {
-    const int kc = TRI ? NKC - 1 - it : it;
-    const int kn = TRI ? kc - 1 : kc + 1;
-    float4 a[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      a[i] = *reinterpret_cast<const float4*>(&As[(wave * 32 + i * 16 + l16) * AS + kc * 16 + 4 * grp]);
-#define FQ_STEP(C)                                                                           \
-  _Pragma("unroll") for (int j = 0; j < NCB; ++j) {                                         \
-    if (TRI && j > kc) continue;                                                            \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i)                                           \
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].C, b[j].C, acc[i][j], 0, 0, 0); \
-  }
-    FQ_STEP(x)
-    FQ_STEP(y)
-    FQ_STEP(z)
-#undef FQ_STEP
-#pragma unroll
-    for (int j = 0; j < NCB; ++j) {
-      if (TRI && j > kc) continue;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, b[j].w, acc[i][j], 0, 0, 0);
-      if (it + 1 < NKC && (!TRI || j <= kn)) b[j] = Wp[(kn * NCB + j) * 64];
-    }
-  }
-}
-
 // Split form of the energy pass on v_mfma_f32_16x16x32_bf16: D = D_hi + D_lo and
 // beta = beta_hi + beta_lo in BF16, Y = D_hi beta_hi + D_hi beta_lo + D_lo beta_hi with FP32
 // accumulation (the dropped D_lo beta_lo is ~2^-16 relative). K = 144 runs as five 32-wide
@@ -584,8 +538,7 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
 
 // 2/3. quadratic forms and epilogue on a complete descriptor tile; leaves g in the tile
 // when the energy pass runs. Wave w of the 4 owns rows 32w .. 32w + 31.
-// SB: B fragments single-buffered (mfma_pass_sb), for register-limited callers
-template <int PREC, bool SB = false>
+template <int PREC>
 __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const float* nrm_s,
                                             const float* rsc_s, int row0, int t, const TileModel& tm) {
   const int lane = t & 63, wave = t >> 6;
@@ -599,12 +552,10 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
       row_sumsq<true>(acc, dots);
     } else if (PREC != FLARE_FP32 || a.vchol) {
       // Z = D L on FP32 cores, L lower-triangular
-      if (SB) mfma_pass_sb<1, true>(As, tm.Wf, wave, lane, acc);
-      else mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);
+      mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);
       row_sumsq<PREC != FLARE_FP32>(acc, dots);
     } else {
-      if (SB) mfma_pass_sb<1>(As, tm.Wf, wave, lane, acc);
-      else mfma_pass<1>(As, tm.Wf, wave, lane, acc);
+      mfma_pass<1>(As, tm.Wf, wave, lane, acc);
       row_dots(As, acc, wave, lane, dots);
     }
     if (l16 == 0) {
@@ -640,8 +591,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
           for (int j = 0; j < NCB; ++j) acc[i][j][r] *= inv;
         }
     } else {
-      if (SB) mfma_pass_sb<0>(As, tm.Wf, wave, lane, acc);
-      else mfma_pass<0>(As, tm.Wf, wave, lane, acc);
+      mfma_pass<0>(As, tm.Wf, wave, lane, acc);
     }
     row_dots(As, acc, wave, lane, dots);
 #pragma unroll
@@ -749,7 +699,7 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
     // the matrix-core phase issues first when both waves of a SIMD are ready: its MFMAs
     // keep the shared datapath busy for 32 cycles each, the other wave fills the gaps
     __builtin_amdgcn_s_setprio(1);
-    forms_phase<PREC, false>(a, A, ns, rs, row0, lane, tile_model(a, row0));
+    forms_phase<PREC>(a, A, ns, rs, row0, lane, tile_model(a, row0));
     __builtin_amdgcn_s_setprio(0);
     wave_phase_fence();
     adjoint_phase(a, A, row0, lane, c);

@@ -11,18 +11,6 @@ struct PairGeom {
   float r, ux, uy, uz;
 };
 
-// geometry of slot k of row R; false for padding or a pair outside the cutoff.
-// sp receives the neighbour species (0 H, 1 Pt).
-__device__ __forceinline__ bool slot_geom(const SlotView& v, int R, int k, PairGeom& pg, int& sp) {
-  const float4 g = v.geom[slot_of(v.slice_base, R, k)];
-  pg.ux = g.x;
-  pg.uy = g.y;
-  pg.uz = g.z;
-  pg.r = fabsf(g.w);
-  sp = g.w > 0.f ? 1 : 0;
-  return g.w != 0.f;
-}
-
 // Visit the geometry of row R's slots in order, f(g, k), with the loads PD slots ahead of
 // their use: the loop body is unrolled PD times over a ring of PD registers, so no value
 // moves between registers. All rows of a wave share one slice (and its length), so the
