@@ -69,7 +69,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(st, beta, sigma, half_width=6.0):
+def cpu_baseline(st, beta, sigma, half_width=11.0):
     """The FP64 oracle on a bounded sample: every atom of a 2*half_width A square column
     through slab and gas (E+F+sigma for those atoms)."""
     import numpy as np
