@@ -252,9 +252,12 @@ int flare_kinetic(flare_state* state, double* vx, double* vy, double* vz, const 
 
 /*
  * Hydrogen coordination numbers (Section VI.A): coord[a] = 1 when atom a is H and another
- * H atom is within 1 A (squared FP64 distance of the positions staged by the last
- * flare_descriptors, below 1), else 0 (always 0 for other species). A change 1 -> 0
+ * H atom is within 1 A (squared FP64 distance of the given positions, moved to the images
+ * of the list build, below 1), else 0 (always 0 for other species). A change 1 -> 0
  * between two snapshots is a dissociation, 0 -> 1 a recombination.
+ *   x, y, z     DEVICE FP64 [n_atoms] each, caller order: the positions last passed to
+ *               flare_descriptors (the list covers them only within half the skin of the
+ *               build, which that call checked); read only
  *   coord       DEVICE int32 [n_atoms], caller order (written)
  *   coord_prev  DEVICE int32 [n_atoms] of an earlier snapshot, or NULL
  *   events      DEVICE int64 [n_struct][2] (dissociations, recombinations) per cell
@@ -262,8 +265,8 @@ int flare_kinetic(flare_state* state, double* vx, double* vy, double* vz, const 
  * Needs the list to cover 1 A (it does: r_list > r_cut > 1 A) and descriptors staged
  * for the current positions (FLARE_E_STALE otherwise).
  */
-int flare_coordination(flare_state* state, int32_t* coord, const int32_t* coord_prev,
-                       int64_t* events);
+int flare_coordination(flare_state* state, const double* x, const double* y, const double* z,
+                       int32_t* coord, const int32_t* coord_prev, int64_t* events);
 
 /*
  * Stage timers. When enabled, the library records a pair of HIP events on the state's

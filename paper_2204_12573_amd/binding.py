@@ -55,7 +55,7 @@ SIGNATURES = {
     "flare_nvt_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d, _d, _p]),
     "flare_nvt_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d, _d, _p]),
     "flare_kinetic": (_i, [_p, _p, _p, _p, _p, _p, _p]),
-    "flare_coordination": (_i, [_p, _p, _p, _p]),
+    "flare_coordination": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "flare_timers_enable": (_i, [_p, _i]),
     "flare_timers_read": (_i, [_p, _p, _p, _i]),
     "flare_status": (_i, [_p, _p]),

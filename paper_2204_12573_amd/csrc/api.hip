@@ -17,7 +17,6 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 PairView pair_view(const flare_state* s) {
   PairView v;
   v.n = s->n_atoms;
-  v.pos = s->pos;
   v.sp = s->sp;
   v.sid = s->sid;
   v.grids = s->d_grids.p;
@@ -414,7 +413,7 @@ int flare_descriptor_dim(const flare_model* m, int* n_d) {
 
 static void free_state(flare_state* s) {
   void* ptrs[] = {s->perm, s->sp,  s->sid, s->bin,   s->envmask, s->bucket, s->row_of, s->nl_cnt,
-                  s->nl_off, s->w, s->off, s->pos,   s->nrm,     s->e_int,  s->v_int,
+                  s->nl_off, s->w, s->off, s->dlt,   s->nrm,     s->e_int,  s->v_int,
                   s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->nl_rev, s->slot_of_pair, s->d_status,
                   s->d_info};
   for (void* p : ptrs)
@@ -446,7 +445,7 @@ static void free_state(flare_state* s) {
   s->slice_base.release();
   s->slot_atom.release();
   s->slot_j.release();
-  s->slot_s.release();
+  s->slot_d0.release();
   s->slot_pair.release();
   s->slot_rev.release();
   s->geom.release();
@@ -489,7 +488,7 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   al((void**)&s->nl_off, (n + 1) * 4);
   al((void**)&s->w, n * 32);
   al((void**)&s->off, 3 * n * 8);
-  al((void**)&s->pos, n * 32);
+  al((void**)&s->dlt, n * 16);
   al((void**)&s->nrm, n * 4);
   al((void**)&s->e_int, n * 4);
   al((void**)&s->v_int, n * 4);
@@ -868,14 +867,16 @@ int flare_kinetic(flare_state* s, double* vx, double* vy, double* vz, const int3
   return FLARE_OK;
 }
 
-int flare_coordination(flare_state* s, int32_t* coord, const int32_t* coord_prev, int64_t* events) {
+int flare_coordination(flare_state* s, const double* x, const double* y, const double* z, int32_t* coord,
+                       const int32_t* coord_prev, int64_t* events) {
   ARG(s && coord, "null pointer");
+  ARG(s->n_atoms == 0 || (x && y && z), "null positions");
   ARG((coord_prev == nullptr) == (events == nullptr), "pass coord_prev and events together");
   if (!s->have_desc) {
     set_error("flare_coordination needs positions staged by flare_descriptors");
     return FLARE_E_STALE;
   }
-  coordination(s, coord, coord_prev, events);
+  coordination(s, x, y, z, coord, coord_prev, events);
   CHK(hipGetLastError());
   return FLARE_OK;
 }
@@ -898,7 +899,7 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
          s->atom_of_row1.bytes() + s->atom_of_rowx.bytes() + s->D1.bytes() + s->G1.bytes() + s->Dx.bytes() +
          s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
          s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
-         s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_s.bytes() + s->slot_pair.bytes() +
+         s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_d0.bytes() + s->slot_pair.bytes() +
          s->slot_rev.bytes() + s->geom.bytes() + s->f_own.bytes() + s->w_in.bytes() + s->pair_cache.bytes() + s->vir_int.bytes() + s->red_w.bytes() +
          s->perm_row.bytes() + s->cnt_row.bytes() + s->sid_row.bytes() + s->e_row.bytes() + s->v_row.bytes();
   }

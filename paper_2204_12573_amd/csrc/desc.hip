@@ -71,23 +71,26 @@ __global__ __launch_bounds__(MTHREADS) void k_desc_mixed(SlotView v, int rows1, 
 
 constexpr int NTG = 256;
 
+// Internal position of each atom for this step, x + off in FP64, checked against its
+// reference position w (the wrapped position at the list build): the displacement since the
+// build must stay within half the skin. The displacement itself is kept in FP32: it is
+// smaller than half the skin, so its rounding is far below that of the pair vectors.
 __global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict__ perm,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ y,
                                                     const double* __restrict__ z,
                                                     const double* __restrict__ off,
                                                     const double4* __restrict__ w,
-                                                    double4* __restrict__ pos, double lim2,
+                                                    float4* __restrict__ dlt, double lim2,
                                                     int* __restrict__ status) {
   const int i = blockIdx.x * NTG + threadIdx.x;
   if (i >= n) return;
   const int a = perm[i];
-  const double p0 = x[a] + off[i];
-  const double p1 = y[a] + off[(size_t)n + i];
-  const double p2 = z[a] + off[2 * (size_t)n + i];
-  pos[i] = make_double4(p0, p1, p2, 0.0);
   const double4 wi = w[i];
-  const double d0 = p0 - wi.x, d1 = p1 - wi.y, d2 = p2 - wi.z;
+  const double d0 = (x[a] + off[i]) - wi.x;
+  const double d1 = (y[a] + off[(size_t)n + i]) - wi.y;
+  const double d2 = (z[a] + off[2 * (size_t)n + i]) - wi.z;
+  dlt[i] = make_float4((float)d0, (float)d1, (float)d2, 0.f);
   const double d2s = d0 * d0 + d1 * d1 + d2 * d2;
   if (!(d2s <= lim2)) {
     if (!isfinite(d2s)) atomicOr(status, FLARE_FLAG_NONFINITE);
@@ -95,34 +98,29 @@ __global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict
   }
 }
 
-// Per-step geometry of every slot: Delta = (x_j - x_i) + s*L in FP64, kept when
-// |Delta|^2 < r_c^2, then (u^, r) in FP32 with the sign of r carrying the neighbour species.
+// Per-step geometry of every slot. The pair vector is split as
+//   Delta = [(w_j - w_i) + s*L] + (delta_j - delta_i),
+// the bracket fixed at the list build (FP64, stored rounded to FP32 with the neighbour's
+// species in .w) and the displacements since the build added in FP32; kept when
+// |Delta|^2 < r_c^2, written as (u^, r) with the sign of r carrying the neighbour species.
 __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __restrict__ slot_atom,
                                               const int* __restrict__ slot_j,
-                                              const int32_t* __restrict__ slot_s,
-                                              const int* __restrict__ sp, const int* __restrict__ sid,
-                                              const CellGrid* __restrict__ grids,
-                                              const double4* __restrict__ pos, int n, double rc2,
+                                              const float4* __restrict__ slot_d0,
+                                              const float4* __restrict__ dlt, float rc2,
                                               float4* __restrict__ geom) {
   const long long slot = (long long)blockIdx.x * NTG + threadIdx.x;
   if (slot >= nslots) return;
   const int i = slot_atom[slot];
   float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
   if (i >= 0) {
-    const int j = slot_j[slot];
-    int sx, sy, sz;
-    unpack_shift(slot_s[slot], sx, sy, sz);
-    const CellGrid* g = grids + sid[i];
-    const double4 pj = pos[j], pi = pos[i];
-    const double dx = (pj.x - pi.x) + (double)sx * g->L[0];
-    const double dy = (pj.y - pi.y) + (double)sy * g->L[1];
-    const double dz = (pj.z - pi.z) + (double)sz * g->L[2];
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const float4 d0 = slot_d0[slot];
+    const float4 dj = dlt[slot_j[slot]], di = dlt[i];
+    const float fx = d0.x + (dj.x - di.x), fy = d0.y + (dj.y - di.y), fz = d0.z + (dj.z - di.z);
+    const float r2 = fx * fx + fy * fy + fz * fz;
     if (r2 < rc2) {
-      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      const float r = sqrtf(r2);
       const float inv = 1.f / r;
-      out = make_float4(fx * inv, fy * inv, fz * inv, sp[j] ? r : -r);
+      out = make_float4(fx * inv, fy * inv, fz * inv, d0.w * r);
     }
   }
   geom[slot] = out;
@@ -160,7 +158,7 @@ void gather_positions(flare_state* s, const double* x, const double* y, const do
   const int n = s->n_atoms;
   if (n == 0) return;
   const double lim = 0.5 * s->skin;
-  k_gather_pos<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, x, y, z, s->off, s->w, s->pos,
+  k_gather_pos<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, x, y, z, s->off, s->w, s->dlt,
                                                            lim * lim, s->d_status);
 }
 
@@ -168,9 +166,8 @@ void pair_geometry(flare_state* s) {
   const long long ns = s->n_slots;
   if (ns == 0) return;
   const double rc = s->model->r_cut;
-  k_geom<<<(int)((ns + NTG - 1) / NTG), NTG, 0, s->stream>>>(ns, s->slot_atom.p, s->slot_j.p, s->slot_s.p, s->sp,
-                                                             s->sid, s->d_grids.p, s->pos, s->n_atoms, rc * rc,
-                                                             s->geom.p);
+  k_geom<<<(int)((ns + NTG - 1) / NTG), NTG, 0, s->stream>>>(ns, s->slot_atom.p, s->slot_j.p, s->slot_d0.p,
+                                                             s->dlt, (float)(rc * rc), s->geom.p);
 }
 
 void compute_descriptors_mixed(flare_state* s) {

@@ -325,32 +325,50 @@ __global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const in
                                                    const int* __restrict__ nl_j,
                                                    const int32_t* __restrict__ nl_s,
                                                    const int* __restrict__ slice_base,
+                                                   const double4* __restrict__ w, const int* __restrict__ sp,
+                                                   const int* __restrict__ sid,
+                                                   const CellGrid* __restrict__ grids,
                                                    int* __restrict__ slot_atom, int* __restrict__ slot_j,
-                                                   int* __restrict__ slot_s, int* __restrict__ slot_pair) {
+                                                   float4* __restrict__ slot_d0, int* __restrict__ slot_pair) {
   const int R = blockIdx.x * NT + threadIdx.x;
   if (R >= rows) return;
   const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
   const int base = slice_base[R >> 5], len = slice_base[(R >> 5) + 1] - base;
   const int p0 = i >= 0 ? nl_off[i] : 0, own = i >= 0 ? nl_off[i + 1] - p0 : 0;
+  double4 wi = make_double4(0.0, 0.0, 0.0, 0.0);
+  double L0 = 0.0, L1 = 0.0, L2 = 0.0;
+  if (i >= 0) {
+    wi = w[i];
+    const CellGrid* g = grids + sid[i];
+    L0 = g->L[0];
+    L1 = g->L[1];
+    L2 = g->L[2];
+  }
   for (int k = 0; k < len; ++k) {
     const int slot = (base + k) * 32 + (R & 31);
     if (k < own) {
       const int p = p0 + k;
+      const int j = nl_j[p];
+      int sx, sy, sz;
+      unpack_shift(nl_s[p], sx, sy, sz);
+      const double4 wj = w[j];
+      // the fixed part of the pair vector (reference positions and the periodic shift)
+      const double dx = (wj.x - wi.x) + (double)sx * L0;
+      const double dy = (wj.y - wi.y) + (double)sy * L1;
+      const double dz = (wj.z - wi.z) + (double)sz * L2;
       slot_atom[slot] = i;
-      slot_j[slot] = nl_j[p];
-      slot_s[slot] = nl_s[p];
+      slot_j[slot] = j;
+      slot_d0[slot] = make_float4((float)dx, (float)dy, (float)dz, sp[j] ? 1.f : -1.f);
       slot_pair[slot] = p;
     } else {
       slot_atom[slot] = -1;
       slot_j[slot] = 0;
-      slot_s[slot] = 0;
+      slot_d0[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
       slot_pair[slot] = 0;
     }
   }
 }
 
-// slot of every pair, one thread per atom in internal order (each writes its own contiguous
-// range of the pair array)
 __global__ __launch_bounds__(NT) void k_slot_of_pair(int n, const int* __restrict__ bucket,
                                                      const int* __restrict__ row_of, int rows1,
                                                      const int* __restrict__ nl_off,
@@ -568,7 +586,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   s->n_slots = nslots;
   HIPCHK(s->slot_atom.reserve(nslots + 1));
   HIPCHK(s->slot_j.reserve(nslots + 1));
-  HIPCHK(s->slot_s.reserve(nslots + 1));
+  HIPCHK(s->slot_d0.reserve(nslots + 1));
   HIPCHK(s->slot_pair.reserve(nslots + 1));
   HIPCHK(s->slot_rev.reserve(nslots + 1));
   HIPCHK(s->geom.reserve(nslots + 1));
@@ -576,8 +594,9 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->w_in.reserve(nslots + 1));
   if (r1 + rx > 0)
     k_fill_slots<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p,
-                                                        s->nl_off, s->nl_j, s->nl_s, s->slice_base.p, s->slot_atom.p,
-                                                        s->slot_j.p, s->slot_s.p, s->slot_pair.p);
+                                                        s->nl_off, s->nl_j, s->nl_s, s->slice_base.p, s->w, s->sp,
+                                                        s->sid, s->d_grids.p, s->slot_atom.p, s->slot_j.p,
+                                                        s->slot_d0.p, s->slot_pair.p);
   if (n > 0)
     k_slot_of_pair<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, r1, s->nl_off, s->slice_base.p, s->slot_of_pair);
   if (nslots > 0)

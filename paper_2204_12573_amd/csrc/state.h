@@ -32,7 +32,6 @@ struct DevBuf {
 // Read-only view of the per-step pair data, passed to kernels by value.
 struct PairView {
   int n;                              // atoms
-  const double4* pos;                 // [n] internal positions
   const int* sp;                      // species
   const int* sid;                     // cell of each atom
   const CellGrid* grids;              // per cell
@@ -152,7 +151,7 @@ struct flare_state {
   int* nl_off = nullptr;     // [max_atoms + 1]
   double4* w = nullptr;      // [N] wrapped positions at the list build (x, y, z, 0)
   double* off = nullptr;     // [3][N] image offset: internal position = x + off
-  double4* pos = nullptr;    // [N] internal positions of the current step (x, y, z, 0)
+  float4* dlt = nullptr;     // [N] displacement of the current step from w, FP32 (x, y, z, 0)
   float* nrm = nullptr;      // |d~| per internal atom
   float* e_int = nullptr;
   float* v_int = nullptr;
@@ -185,7 +184,8 @@ struct flare_state {
   int n_slices = 0;
   long long n_slots = 0;
   flare::DevBuf<int> slice_len, slice_base;          // [slices (+1)]
-  flare::DevBuf<int> slot_atom, slot_j, slot_s, slot_pair, slot_rev;
+  flare::DevBuf<int> slot_atom, slot_j, slot_pair, slot_rev;
+  flare::DevBuf<float4> slot_d0;                     // per slot: (w_j - w_i) + s*L in FP32, neighbour species sign
   flare::DevBuf<float4> geom;                        // per slot, per step
   flare::DevBuf<float4> f_own;                       // per row: sum of de_i/dDelta over its own pairs
   flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
@@ -245,7 +245,8 @@ void nvt_first(flare_state* s, double* x, double* y, double* z, double* vx, doub
 void nvt_second(flare_state* s, double* vx, double* vy, double* vz, const float* fx, const float* fy,
                 const float* fz, const int32_t* species, const double* masses, double dt, double t0, double tau,
                 double* thermo, bool update);
-void coordination(flare_state* s, int32_t* coord, const int32_t* prev, int64_t* events);
+void coordination(flare_state* s, const double* x, const double* y, const double* z, int32_t* coord,
+                  const int32_t* prev, int64_t* events);
 void set_error(const std::string& msg);
 // FP8 fragments from FP32 values in fragment order [groups][lane 64][8] (fused.hip)
 void make_fp8_fragments(const float* vals, int groups, uint64_t* out);

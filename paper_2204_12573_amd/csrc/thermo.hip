@@ -157,28 +157,32 @@ __global__ __launch_bounds__(NC) void k_nh_close(const double* __restrict__ red,
   }
 }
 
-// coordination of every atom (internal index i, written in caller order)
+// coordination of every atom (internal index i, written in caller order); positions are
+// the caller's FP64 ones moved to the atom's image, x + off, exactly as staged for the step
 __global__ __launch_bounds__(NT) void k_coord(int n, const int* __restrict__ perm, const int* __restrict__ sp,
                                               const int* __restrict__ sid, const CellGrid* __restrict__ grids,
-                                              const double4* __restrict__ pos, const int* __restrict__ nl_off,
-                                              const int* __restrict__ nl_j, const int32_t* __restrict__ nl_s,
-                                              int32_t* __restrict__ coord) {
+                                              const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ z, const double* __restrict__ off,
+                                              const int* __restrict__ nl_off, const int* __restrict__ nl_j,
+                                              const int32_t* __restrict__ nl_s, int32_t* __restrict__ coord) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   int c = 0;
   if (sp[i] == 0) {
     const CellGrid* g = grids + sid[i];
-    const double4 pi = pos[i];
+    const int a = perm[i];
+    const double pix = x[a] + off[i], piy = y[a] + off[(size_t)n + i], piz = z[a] + off[2 * (size_t)n + i];
     for (int p = nl_off[i]; p < nl_off[i + 1] && c == 0; ++p) {
       const int j = nl_j[p];
       if (sp[j] != 0) continue;
       int sx, sy, sz;
       unpack_shift(nl_s[p], sx, sy, sz);
-      const double4 pj = pos[j];
-      const double dx = (pj.x - pi.x) + (double)sx * g->L[0];
-      const double dy = (pj.y - pi.y) + (double)sy * g->L[1];
-      const double dz = (pj.z - pi.z) + (double)sz * g->L[2];
+      const int b = perm[j];
+      const double pjx = x[b] + off[j], pjy = y[b] + off[(size_t)n + j], pjz = z[b] + off[2 * (size_t)n + j];
+      const double dx = (pjx - pix) + (double)sx * g->L[0];
+      const double dy = (pjy - piy) + (double)sy * g->L[1];
+      const double dz = (pjz - piz) + (double)sz * g->L[2];
       if (dx * dx + dy * dy + dz * dz < 1.0) c = 1;
     }
   }
@@ -251,11 +255,12 @@ void nvt_second(flare_state* s, double* vx, double* vy, double* vz, const float*
                                          update ? 1 : 0);
 }
 
-void coordination(flare_state* s, int32_t* coord, const int32_t* prev, int64_t* events) {
+void coordination(flare_state* s, const double* x, const double* y, const double* z, int32_t* coord,
+                  const int32_t* prev, int64_t* events) {
   const int n = s->n_atoms, nc = s->n_struct, nt = (int)s->tasks.size();
   if (n > 0)
-    k_coord<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->sp, s->sid, s->d_grids.p, s->pos, s->nl_off,
-                                                     s->nl_j, s->nl_s, coord);
+    k_coord<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->sp, s->sid, s->d_grids.p, x, y, z, s->off,
+                                                     s->nl_off, s->nl_j, s->nl_s, coord);
   if (prev && events) {
     if (nt > 0) k_events_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, prev, coord, s->red_e.p);
     if (nc > 0) k_events_cells<<<(nc + NC - 1) / NC, NC, 0, s->stream>>>(nc, s->red_e.p, s->d_first_task.p, events);

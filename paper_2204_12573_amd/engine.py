@@ -226,13 +226,15 @@ class Evaluator:
                                                    B.ptr(MASSES), float(dt), float(t_target), float(tau),
                                                    B.ptr(thermo)))
 
-    def coordination(self, prev=None):
-        """H coordination numbers (device int32 [N], caller order) of the staged positions and,
-        given an earlier snapshot, the (dissociation, recombination) counts per cell."""
+    def coordination(self, pos, prev=None):
+        """H coordination numbers (device int32 [N], caller order) of `pos`, the positions last
+        passed to `descriptors`, and, given an earlier snapshot, the (dissociation,
+        recombination) counts per cell."""
         coord = torch.empty(self.n, dtype=torch.int32, device=self.device)
         events = torch.zeros((self.n_struct, 2), dtype=torch.int64, device=self.device) if prev is not None else None
         with torch.cuda.stream(self.stream):
-            B.check(self.lib.flare_coordination(self.handle, B.ptr(coord), B.ptr(prev), B.ptr(events)))
+            B.check(self.lib.flare_coordination(self.handle, B.ptr(pos[0]), B.ptr(pos[1]), B.ptr(pos[2]),
+                                                B.ptr(coord), B.ptr(prev), B.ptr(events)))
         return coord, events
 
 
@@ -301,7 +303,7 @@ class Production:
 
     def __init__(self, nvt: NVT, every=1000, threshold=0.005):
         self.nvt, self.every, self.threshold = nvt, every, threshold
-        self.coord, _ = nvt.ev.coordination()
+        self.coord, _ = nvt.ev.coordination(nvt.pos)
         self.events = torch.zeros((nvt.ev.n_struct, 2), dtype=torch.int64, device=nvt.ev.device)
         self.sigma_max = torch.zeros(nvt.ev.n_struct, dtype=torch.float32, device=nvt.ev.device)
         self.flagged = []
@@ -310,7 +312,7 @@ class Production:
         out = self.nvt.step()
         if self.nvt.nstep % self.every == 0:
             ev = self.nvt.ev
-            coord, ev_counts = ev.coordination(self.coord)
+            coord, ev_counts = ev.coordination(self.nvt.pos, self.coord)
             self.events += ev_counts
             self.coord = coord
             smax = ev.variance()["sigma_max"]

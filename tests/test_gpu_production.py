@@ -84,14 +84,14 @@ def test_coordination_and_events(model):
     p, s = engine.to_device(b.pos, b.species)
     ev.neighbors(p, s, b.offsets, b.boxes, 4.0)     # skin 4 A: the list covers moves below 2 A
     ev.descriptors(p)
-    c1, _ = ev.coordination()
+    c1, _ = ev.coordination(p)
     p2, _ = engine.to_device(pos2, b.species)
     ev.descriptors(p2)
     assert np.abs(pos2 - b.pos).max() < 2.0 / np.sqrt(3.0)
     assert ev.status() == 0            # the moves stay within half the skin
-    c2, events = ev.coordination(c1)
+    c2, events = ev.coordination(p2, c1)
     ev.descriptors(p)                  # back: the broken bonds recombine
-    c3, back = ev.coordination(c2)
+    c3, back = ev.coordination(p, c2)
     torch.cuda.synchronize()
     c1, c2, events = c1.cpu().numpy(), c2.cpu().numpy(), events.cpu().numpy()
     np.testing.assert_array_equal(c3.cpu().numpy(), c1)
