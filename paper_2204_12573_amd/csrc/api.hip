@@ -446,13 +446,13 @@ static void free_state(flare_state* s) {
   s->slot_atom.release();
   s->slot_j.release();
   s->slot_d0.release();
-  s->slot_pair.release();
   s->slot_rev.release();
   s->geom.release();
   s->f_own.release();
   s->w_in.release();
   s->pair_cache.release();
-  s->perm_row.release();
+  s->row_out.release();
+  s->row_caller.release();
   s->cnt_row.release();
   s->sid_row.release();
   s->e_row.release();
@@ -899,9 +899,10 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
          s->atom_of_row1.bytes() + s->atom_of_rowx.bytes() + s->D1.bytes() + s->G1.bytes() + s->Dx.bytes() +
          s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
          s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
-         s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_d0.bytes() + s->slot_pair.bytes() +
+         s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_d0.bytes() +
          s->slot_rev.bytes() + s->geom.bytes() + s->f_own.bytes() + s->w_in.bytes() + s->pair_cache.bytes() + s->vir_int.bytes() + s->red_w.bytes() +
-         s->perm_row.bytes() + s->cnt_row.bytes() + s->sid_row.bytes() + s->e_row.bytes() + s->v_row.bytes();
+         s->cnt_row.bytes() + s->sid_row.bytes() + s->e_row.bytes() + s->v_row.bytes() +
+         s->row_out.bytes() + s->row_caller.bytes();
   }
   *bytes = b;
   return FLARE_OK;

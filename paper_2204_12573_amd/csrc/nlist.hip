@@ -302,18 +302,26 @@ __global__ __launch_bounds__(NT) void k_slice_len(int nslices, const int* __rest
   slice_len[S] = m;
 }
 
-// Per-row copies of the atom's caller index, pair count and cell (padding rows: -1, 0, 0).
+// Per-row copies of the atom's pair count and cell (padding rows: 0, 0).
 __global__ __launch_bounds__(NT) void k_row_meta(int rows, int rows1, const int* __restrict__ aor1,
-                                                 const int* __restrict__ aorx, const int* __restrict__ perm,
-                                                 const int* __restrict__ cnt, const int* __restrict__ sid,
-                                                 int* __restrict__ perm_row, int* __restrict__ cnt_row,
+                                                 const int* __restrict__ aorx, const int* __restrict__ cnt,
+                                                 const int* __restrict__ sid, int* __restrict__ cnt_row,
                                                  int* __restrict__ sid_row) {
   const int R = blockIdx.x * NT + threadIdx.x;
   if (R >= rows) return;
   const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
-  perm_row[R] = i >= 0 ? perm[i] : -1;
   cnt_row[R] = i >= 0 ? cnt[i] : 0;
   sid_row[R] = i >= 0 ? sid[i] : 0;
+}
+
+// Row of every atom in caller order (-1: no listed pair, no row).
+__global__ __launch_bounds__(NT) void k_caller_rows(int n, const int* __restrict__ bucket,
+                                                    const int* __restrict__ row_of, int rows1,
+                                                    const int* __restrict__ perm, int* __restrict__ row_caller) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int b = bucket[i];
+  row_caller[perm[i]] = b < 0 ? -1 : global_row(b, row_of[i], rows1);
 }
 
 // One thread per row: the row's own pairs into its slots, the rest of its slice length
@@ -323,48 +331,24 @@ __global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const in
                                                    const int* __restrict__ aorx,
                                                    const int* __restrict__ nl_off,
                                                    const int* __restrict__ nl_j,
-                                                   const int32_t* __restrict__ nl_s,
                                                    const int* __restrict__ slice_base,
-                                                   const double4* __restrict__ w, const int* __restrict__ sp,
-                                                   const int* __restrict__ sid,
-                                                   const CellGrid* __restrict__ grids,
                                                    int* __restrict__ slot_atom, int* __restrict__ slot_j,
-                                                   float4* __restrict__ slot_d0, int* __restrict__ slot_pair) {
+                                                   int* __restrict__ slot_rev, float4* __restrict__ slot_d0) {
   const int R = blockIdx.x * NT + threadIdx.x;
   if (R >= rows) return;
   const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
   const int base = slice_base[R >> 5], len = slice_base[(R >> 5) + 1] - base;
   const int p0 = i >= 0 ? nl_off[i] : 0, own = i >= 0 ? nl_off[i + 1] - p0 : 0;
-  double4 wi = make_double4(0.0, 0.0, 0.0, 0.0);
-  double L0 = 0.0, L1 = 0.0, L2 = 0.0;
-  if (i >= 0) {
-    wi = w[i];
-    const CellGrid* g = grids + sid[i];
-    L0 = g->L[0];
-    L1 = g->L[1];
-    L2 = g->L[2];
-  }
   for (int k = 0; k < len; ++k) {
     const int slot = (base + k) * 32 + (R & 31);
     if (k < own) {
-      const int p = p0 + k;
-      const int j = nl_j[p];
-      int sx, sy, sz;
-      unpack_shift(nl_s[p], sx, sy, sz);
-      const double4 wj = w[j];
-      // the fixed part of the pair vector (reference positions and the periodic shift)
-      const double dx = (wj.x - wi.x) + (double)sx * L0;
-      const double dy = (wj.y - wi.y) + (double)sy * L1;
-      const double dz = (wj.z - wi.z) + (double)sz * L2;
       slot_atom[slot] = i;
-      slot_j[slot] = j;
-      slot_d0[slot] = make_float4((float)dx, (float)dy, (float)dz, sp[j] ? 1.f : -1.f);
-      slot_pair[slot] = p;
+      slot_j[slot] = nl_j[p0 + k];
     } else {
       slot_atom[slot] = -1;
       slot_j[slot] = 0;
+      slot_rev[slot] = slot;            // padding slots point at themselves
       slot_d0[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
-      slot_pair[slot] = 0;
     }
   }
 }
@@ -383,15 +367,46 @@ __global__ __launch_bounds__(NT) void k_slot_of_pair(int n, const int* __restric
   for (int k = 0; k < own; ++k) slot_of_pair[p0 + k] = (base + k) * 32 + (R & 31);
 }
 
-// slot of the reverse pair; padding slots point at themselves
-__global__ __launch_bounds__(NT) void k_rev_slots(long long nslots, const int* __restrict__ slot_atom,
-                                                  const int* __restrict__ slot_pair,
-                                                  const int* __restrict__ nl_rev,
-                                                  const int* __restrict__ slot_of_pair,
-                                                  int* __restrict__ slot_rev) {
-  const long long slot = (long long)blockIdx.x * NT + threadIdx.x;
-  if (slot >= nslots) return;
-  slot_rev[slot] = slot_atom[slot] < 0 ? (int)slot : slot_of_pair[nl_rev[slot_pair[slot]]];
+// Per listed pair p = (i, j, s), in list order: the slot of its reverse pair and the fixed
+// part of its pair vector, (w_j - w_i) + s*L from the reference positions in FP64, kept in
+// FP32 with the neighbour species as +-1. A work-group takes the pairs of NT consecutive
+// atoms (i by bisection in the group's offsets, in LDS); the atoms are in spatial order, so
+// the neighbour positions it reads are close together.
+__global__ __launch_bounds__(NT) void k_pair_slots(int n, const int* __restrict__ nl_off,
+                                                   const int* __restrict__ nl_j,
+                                                   const int32_t* __restrict__ nl_s,
+                                                   const int* __restrict__ nl_rev,
+                                                   const int* __restrict__ slot_of_pair,
+                                                   const double4* __restrict__ w, const int* __restrict__ sp,
+                                                   const int* __restrict__ sid,
+                                                   const CellGrid* __restrict__ grids,
+                                                   int* __restrict__ slot_rev, float4* __restrict__ slot_d0) {
+  __shared__ int offs[NT + 1];
+  const int a0 = blockIdx.x * NT;
+  const int na = min(NT, n - a0);
+  for (int k = threadIdx.x; k <= na; k += NT) offs[k] = nl_off[a0 + k];
+  __syncthreads();
+  const int p0 = offs[0], p1 = offs[na];
+  for (int p = p0 + threadIdx.x; p < p1; p += NT) {
+    int lo = 0, hi = na;            // largest k with offs[k] <= p
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (offs[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int i = a0 + lo;
+    const int j = nl_j[p];
+    int sx, sy, sz;
+    unpack_shift(nl_s[p], sx, sy, sz);
+    const CellGrid* g = grids + sid[i];
+    const double4 wj = w[j], wi = w[i];
+    const double dx = (wj.x - wi.x) + (double)sx * g->L[0];
+    const double dy = (wj.y - wi.y) + (double)sy * g->L[1];
+    const double dz = (wj.z - wi.z) + (double)sz * g->L[2];
+    const int slot = slot_of_pair[p];
+    slot_rev[slot] = slot_of_pair[nl_rev[p]];
+    slot_d0[slot] = make_float4((float)dx, (float)dy, (float)dz, sp[j] ? 1.f : -1.f);
+  }
 }
 
 struct Row0 {
@@ -554,15 +569,16 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->nl_cnt, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
   }
-  HIPCHK(s->perm_row.reserve((size_t)r1 + rx + 1));
   HIPCHK(s->cnt_row.reserve((size_t)r1 + rx + 1));
   HIPCHK(s->sid_row.reserve((size_t)r1 + rx + 1));
   HIPCHK(s->e_row.reserve((size_t)r1 + rx + 1));
   HIPCHK(s->v_row.reserve((size_t)r1 + rx + 1));
+  HIPCHK(s->row_out.reserve((size_t)r1 + rx + 1));
+  HIPCHK(s->row_caller.reserve((size_t)n + 1));
+  if (n > 0) k_caller_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, r1, s->perm, s->row_caller.p);
   if (r1 + rx > 0)
-    k_row_meta<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p, s->perm,
-                                                      s->nl_cnt, s->sid, s->perm_row.p, s->cnt_row.p,
-                                                      s->sid_row.p);
+    k_row_meta<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p,
+                                                      s->nl_cnt, s->sid, s->cnt_row.p, s->sid_row.p);
   // sliced layout: slice lengths, their prefix, then the slots
   s->n_slices = (r1 + rx) / 32;
   HIPCHK(s->slice_len.reserve(s->n_slices + 1));
@@ -587,21 +603,19 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->slot_atom.reserve(nslots + 1));
   HIPCHK(s->slot_j.reserve(nslots + 1));
   HIPCHK(s->slot_d0.reserve(nslots + 1));
-  HIPCHK(s->slot_pair.reserve(nslots + 1));
   HIPCHK(s->slot_rev.reserve(nslots + 1));
   HIPCHK(s->geom.reserve(nslots + 1));
   HIPCHK(s->f_own.reserve((size_t)r1 + rx + 1));
   HIPCHK(s->w_in.reserve(nslots + 1));
   if (r1 + rx > 0)
     k_fill_slots<<<(r1 + rx + NT - 1) / NT, NT, 0, st>>>(r1 + rx, r1, s->atom_of_row1.p, s->atom_of_rowx.p,
-                                                        s->nl_off, s->nl_j, s->nl_s, s->slice_base.p, s->w, s->sp,
-                                                        s->sid, s->d_grids.p, s->slot_atom.p, s->slot_j.p,
-                                                        s->slot_d0.p, s->slot_pair.p);
-  if (n > 0)
+                                                        s->nl_off, s->nl_j, s->slice_base.p, s->slot_atom.p,
+                                                        s->slot_j.p, s->slot_rev.p, s->slot_d0.p);
+  if (n > 0) {
     k_slot_of_pair<<<nblk, NT, 0, st>>>(n, s->bucket, s->row_of, r1, s->nl_off, s->slice_base.p, s->slot_of_pair);
-  if (nslots > 0)
-    k_rev_slots<<<(int)((nslots + NT - 1) / NT), NT, 0, st>>>(nslots, s->slot_atom.p, s->slot_pair.p, s->nl_rev,
-                                                              s->slot_of_pair, s->slot_rev.p);
+    k_pair_slots<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev, s->slot_of_pair, s->w, s->sp,
+                                       s->sid, s->d_grids.p, s->slot_rev.p, s->slot_d0.p);
+  }
   // reduction tasks: contiguous internal ranges of one cell, at most 2048 atoms each (one
   // work-group per task); cell c owns tasks [first_task[c], first_task[c + 1])
   s->tasks.clear();

@@ -10,29 +10,23 @@ namespace {
 
 constexpr int NT = 256;
 
-// Caller-order outputs, one thread per row; every per-row input is read in row order
-// (coalesced). Forces: F_i = sum_k w(i,k) - sum_k w_in(slot(i,k)), the first sum (the row's
-// own pair terms) formed by the adjoint as f_own, the second over the row's own pairs
-// k < count in slot order (deterministic); w_in holds each slot's reverse term.
-__global__ __launch_bounds__(NT) void k_outputs(int rows, const int* __restrict__ slice_base,
-                                                const float4* __restrict__ f_own,
-                                                const float4* __restrict__ w_in,
-                                                const int* __restrict__ perm_row,
-                                                const int* __restrict__ cnt_row,
-                                                const int* __restrict__ sid_row,
-                                                const double* __restrict__ cell_scale,
-                                                const float* __restrict__ e_row,
-                                                const float* __restrict__ v_row,
-                                                float* __restrict__ e_atom, float* __restrict__ fx,
-                                                float* __restrict__ fy, float* __restrict__ fz,
-                                                float* __restrict__ var_atom,
-                                                float* __restrict__ sigma_atom) {
+// Outputs in two coalesced passes. Rows (row order): F_i = sum_k w(i,k) - sum_k
+// w_in(slot(i,k)), the first sum (the row's own pair terms) formed by the adjoint as f_own,
+// the second over the row's own pairs k < count in slot order (deterministic), written with
+// e_i as one 16-byte record per row. Atoms (caller order): each atom reads its row's record
+// and variance and writes every requested output; atoms without a row get zeros.
+__global__ __launch_bounds__(NT) void k_outputs_rows(int rows, int want_f, const int* __restrict__ slice_base,
+                                                     const float4* __restrict__ f_own,
+                                                     const float4* __restrict__ w_in,
+                                                     const int* __restrict__ cnt_row,
+                                                     const int* __restrict__ sid_row,
+                                                     const double* __restrict__ cell_scale,
+                                                     const float* __restrict__ e_row,
+                                                     float4* __restrict__ row_out) {
   const int R = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   if (R >= rows) return;
-  const int a = perm_row[R];
-  if (a < 0) return;
-  if (e_atom) e_atom[a] = e_row[R];
-  if (fx) {
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  if (want_f) {
     const int base = slice_base[R >> 5], len = cnt_row[R];   // the row's own pairs (no padding)
     float rx = 0.f, ry = 0.f, rz = 0.f;
     for (int k = 0; k < len; ++k) {
@@ -42,42 +36,43 @@ __global__ __launch_bounds__(NT) void k_outputs(int rows, const int* __restrict_
       rz += wr.z;
     }
     const float4 fo = f_own[R];
-    float sx = fo.x - rx, sy = fo.y - ry, sz = fo.z - rz;
+    sx = fo.x - rx;
+    sy = fo.y - ry;
+    sz = fo.z - rz;
     if (cell_scale) {
       const float k = (float)cell_scale[sid_row[R]];
       sx *= k;
       sy *= k;
       sz *= k;
     }
-    fx[a] = sx;
-    fy[a] = sy;
-    fz[a] = sz;
   }
-  if (var_atom || sigma_atom) {
-    const float v = v_row[R];
-    if (var_atom) var_atom[a] = v;
-    if (sigma_atom) sigma_atom[a] = sqrtf(fmaxf(v, 0.f));
-  }
+  row_out[R] = make_float4(sx, sy, sz, e_row[R]);
 }
 
-// Atoms without any neighbour in the list radius: zero energy, force and variance.
-__global__ __launch_bounds__(NT) void k_outputs_empty(int n, const int* __restrict__ bucket,
-                                                      const int* __restrict__ perm,
+__global__ __launch_bounds__(NT) void k_outputs_atoms(int n, const int* __restrict__ row_caller,
+                                                      const float4* __restrict__ row_out,
+                                                      const float* __restrict__ v_row,
                                                       float* __restrict__ e_atom, float* __restrict__ fx,
                                                       float* __restrict__ fy, float* __restrict__ fz,
                                                       float* __restrict__ var_atom,
                                                       float* __restrict__ sigma_atom) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= n || bucket[i] >= 0) return;
-  const int a = perm[i];
-  if (e_atom) e_atom[a] = 0.f;
-  if (fx) {
-    fx[a] = 0.f;
-    fy[a] = 0.f;
-    fz[a] = 0.f;
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n) return;
+  const int R = row_caller[a];
+  float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+  float v = 0.f;
+  if (R >= 0) {
+    o = row_out[R];
+    if (var_atom || sigma_atom) v = v_row[R];
   }
-  if (var_atom) var_atom[a] = 0.f;
-  if (sigma_atom) sigma_atom[a] = 0.f;
+  if (e_atom) e_atom[a] = o.w;
+  if (fx) {
+    fx[a] = o.x;
+    fy[a] = o.y;
+    fz[a] = o.z;
+  }
+  if (var_atom) var_atom[a] = v;
+  if (sigma_atom) sigma_atom[a] = sqrtf(fmaxf(v, 0.f));
 }
 
 __device__ inline void two_sum_add(double& s, double& c, double x) {
@@ -299,12 +294,11 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
   if (n == 0) return;
   const int rows = s->rows1 + s->rowsx;
   if (rows > 0)
-    k_outputs<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->slice_base.p, s->f_own.p, s->w_in.p,
-                                                         s->perm_row.p, s->cnt_row.p, s->sid_row.p, cell_scale,
-                                                         s->e_row.p, s->v_row.p, e_atom, fx, fy, fz, var_atom,
-                                                         sigma_atom);
-  k_outputs_empty<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->bucket, s->perm, e_atom, fx, fy, fz, var_atom,
-                                                           sigma_atom);
+    k_outputs_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, fx != nullptr, s->slice_base.p, s->f_own.p,
+                                                              s->w_in.p, s->cnt_row.p, s->sid_row.p, cell_scale,
+                                                              s->e_row.p, s->row_out.p);
+  k_outputs_atoms<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->row_caller.p, s->row_out.p, s->v_row.p, e_atom, fx,
+                                                           fy, fz, var_atom, sigma_atom);
 }
 
 void reduce_cells(flare_state* s, double* e_struct, float* sigma_max) {

@@ -184,15 +184,17 @@ struct flare_state {
   int n_slices = 0;
   long long n_slots = 0;
   flare::DevBuf<int> slice_len, slice_base;          // [slices (+1)]
-  flare::DevBuf<int> slot_atom, slot_j, slot_pair, slot_rev;
+  flare::DevBuf<int> slot_atom, slot_j, slot_rev;
   flare::DevBuf<float4> slot_d0;                     // per slot: (w_j - w_i) + s*L in FP32, neighbour species sign
   flare::DevBuf<float4> geom;                        // per slot, per step
   flare::DevBuf<float4> f_own;                       // per row: sum of de_i/dDelta over its own pairs
   flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
   flare::DevBuf<int2> pair_cache;                    // list build: first pairs of each atom
   // per row (144-wide rows, then mixed rows), so that the output pass reads them in row order
-  flare::DevBuf<int> perm_row, cnt_row, sid_row;     // caller index (-1: padding), pairs, cell
+  flare::DevBuf<int> cnt_row, sid_row;               // pairs, cell
   flare::DevBuf<float> e_row, v_row;                 // per step: e_i, V_i
+  flare::DevBuf<float4> row_out;                     // per step: (F_i, e_i) in row order
+  flare::DevBuf<int> row_caller;                     // [N] row of each atom, caller order (-1: none)
   // virial (allocated at the first flare_virial call)
   flare::DevBuf<float> vir_int;                      // [9][max_atoms] per internal atom
   flare::DevBuf<double> red_w;                       // [tasks][9]
