@@ -243,13 +243,15 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
 
 // For every pair p = (i, j, s) find q = (j, i, -s) in j's list. The list is symmetric
 // because the FP64 distance test gives the same value for both orders (negating a
-// rounded difference is exact). A missing partner sets the species flag bit 8.
+// rounded difference is exact). Only pairs with i < j search (and write both rev[p] and
+// rev[q]); pairs of an atom with its own image (i == j) search for themselves; rev was
+// filled with -1 before, so a pair left without a partner shows in k_rev_check.
 // One thread per pair: a work-group takes the pairs of NT consecutive atoms, finds each
 // pair's atom by bisection in the group's offsets (in LDS), then scans j's list.
 __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ nl_off,
                                                 const int* __restrict__ nl_j,
                                                 const int32_t* __restrict__ nl_s,
-                                                int* __restrict__ rev, int* __restrict__ status) {
+                                                int* __restrict__ rev) {
   __shared__ int offs[NT + 1];
   const int a0 = blockIdx.x * NT;
   const int na = min(NT, n - a0);
@@ -257,6 +259,7 @@ __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ n
   __syncthreads();
   const int p0 = offs[0], p1 = offs[na];
   for (int p = p0 + threadIdx.x; p < p1; p += NT) {
+    const int j = nl_j[p];
     int lo = 0, hi = na;            // largest k with offs[k] <= p
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ n
       else hi = mid;
     }
     const int i = a0 + lo;
-    const int j = nl_j[p];
+    if (j < i) continue;            // found by the partner's thread
     int sx, sy, sz;
     unpack_shift(nl_s[p], sx, sy, sz);
     const int32_t want = pack_shift(-sx, -sy, -sz);
@@ -283,9 +286,18 @@ __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ n
       for (int u = 0; u < 4; ++u)
         if (found < 0 && jj[u] == i && ss[u] == want) found = q + u;
     }
-    if (found < 0) atomicOr(status, 256);
-    rev[p] = found < 0 ? p : found;
+    if (found >= 0) {
+      rev[p] = found;
+      rev[found] = p;
+    }
   }
+}
+
+// Every pair must have its reverse (species flag bit 8 otherwise).
+__global__ __launch_bounds__(NT) void k_rev_check(int npairs, const int* __restrict__ rev,
+                                                  int* __restrict__ status) {
+  const int p = blockIdx.x * NT + threadIdx.x;
+  if (p < npairs && rev[p] < 0) atomicOr(status, 256);
 }
 
 // ---- sliced pair layout ----
@@ -565,7 +577,11 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     k_pairs<true><<<nblk, NT, 0, st>>>(n, s->d_grids.p, s->sid, s->bin, s->w, s->sp, s->bin_start.p,
                                         rl2, nullptr, nullptr, nullptr, nullptr, nblk, s->nl_off,
                                         s->nl_j, s->nl_s, s->pair_cache.p);
-    k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev, s->d_status);
+    if (pairs > 0) {
+      HIPCHK(hipMemsetAsync(s->nl_rev, 0xff, (size_t)pairs * sizeof(int), st));
+      k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev);
+      k_rev_check<<<(int)((pairs + NT - 1) / NT), NT, 0, st>>>((int)pairs, s->nl_rev, s->d_status);
+    }
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->nl_cnt, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
   }
