@@ -7,12 +7,16 @@
 // tile writes its partial row sums, the beta tiles also Y.
 //
 // Tiling: a work-group of 4 waves owns 64 RB rows; each wave owns RB 16-row blocks x CB
-// 16-column blocks, accumulated by v_mfma_f32_16x16x4_f32. K advances in
+// 16-column blocks, accumulated by v_mfma_f32_16x16x4_f32. Three work-groups share a CU
+// (LDS allows three; the B fragments are read in groups of four column blocks so that the
+// registers allow three waves per SIMD as well). K advances in
 // chunks of 16 staged in LDS (double-buffered). Inside a chunk the four k-steps are
 // interleaved so that each lane reads its four k-values of A and of B with one
 // 128-bit LDS load: k-step t, lane group g uses k = 4g + t (the same map for A and B,
 // which is all a sum over k requires). LDS rows are padded to 20 floats, which spreads
 // the eight 16-byte reads of each lane octet over distinct banks.
+#include <type_traits>
+
 #include "state.h"
 
 namespace flare {
@@ -40,7 +44,7 @@ struct QArgs {
 };
 
 template <int KD, int CB, int RB>
-__global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
+__global__ __launch_bounds__(NTQ, 3) void k_qform(QArgs q) {
   constexpr int TM = 4 * RB * 16;              // rows per work-group
   constexpr int NC = CB * 16;                  // columns per work-group
   constexpr int NCHUNK = KD / KC;
@@ -115,6 +119,10 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
   QF_GLOAD(c0);
   QF_LSTORE(c0 & 1);
   __syncthreads();
+  // the main loop once without the triangular skip (beta tiles) and once with it (L tiles),
+  // so that the beta tiles' MFMAs carry no per-block test
+  auto main_loop = [&](auto lp) {
+  constexpr bool LP = decltype(lp)::value;
   for (int c = c0; c < NCHUNK; ++c) {
     const int buf = c & 1;
     if (c + 1 < NCHUNK) QF_GLOAD(c + 1);
@@ -122,25 +130,33 @@ __global__ __launch_bounds__(NTQ) void k_qform(QArgs q) {
 #pragma unroll
     for (int i = 0; i < RB; ++i)
       a[i] = *reinterpret_cast<const float4*>(&As[buf][(wave * RB * 16 + i * 16 + l16) * LDSW + 4 * grp]);
-    float4 bv[CB];
+    // B fragments in groups of four column blocks, each group used for all four k-steps
+    // (consecutive MFMAs still write different accumulators), so only a group is live
 #pragma unroll
-    for (int j = 0; j < CB; ++j) bv[j] = *reinterpret_cast<const float4*>(&Bs[buf][(j * 16 + l16) * LDSW + 4 * grp]);
-    // k-step outermost (consecutive MFMAs write different accumulators); with W = L the
-    // column block ct*CB + j has no entries in chunks c below it
+    for (int j0 = 0; j0 < CB; j0 += 4) {
+      float4 bg[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u < CB) bg[u] = *reinterpret_cast<const float4*>(&Bs[buf][((j0 + u) * 16 + l16) * LDSW + 4 * grp]);
 #define QF_STEP(C)                                                                              \
-  _Pragma("unroll") for (int j = 0; j < CB; ++j) {                                             \
-    if (lpart && c < ct * CB + j) continue;                                                    \
+  _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                              \
+    const int j = j0 + u;                                                                      \
+    if (j >= CB || (LP && c < ct * CB + j)) continue;                                          \
     _Pragma("unroll") for (int i = 0; i < RB; ++i)                                             \
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].C, bv[j].C, acc[i][j], 0, 0, 0);   \
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].C, bg[u].C, acc[i][j], 0, 0, 0);   \
   }
-    QF_STEP(x)
-    QF_STEP(y)
-    QF_STEP(z)
-    QF_STEP(w)
+      QF_STEP(x)
+      QF_STEP(y)
+      QF_STEP(z)
+      QF_STEP(w)
 #undef QF_STEP
+    }
     if (c + 1 < NCHUNK) QF_LSTORE(buf ^ 1);
     __syncthreads();
   }
+  };
+  if (lpart) main_loop(std::true_type{});
+  else main_loop(std::false_type{});
 
   // ---- epilogue: lane holds Y[row = 4*grp + r][col = 16*j + l16] of each block ----
   const bool has_e = q.mode & 1;
