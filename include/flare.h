@@ -157,6 +157,9 @@ int flare_neighbors_export(flare_state* state, long long* offsets, int32_t* j, i
  *   d_out     optional DEVICE FP32 [n_atoms][n_d] normalised descriptors in the packed
  *             order, zeros outside an atom's block (NULL = not written)
  *   norm_out  optional DEVICE FP32 [n_atoms] |d~_i| (NULL = not written)
+ * Pair vectors are formed as the FP64 difference of the positions at the list build (plus
+ * the image shift), rounded to FP32, plus the FP32 displacements of both atoms since the
+ * build; pairs with |Delta|^2 < r_cut^2 (FP32) enter the descriptors.
  * The descriptors stay resident in the state for flare_energy_forces / flare_variance.
  */
 int flare_descriptors(flare_state* state, const double* x, const double* y, const double* z,
