@@ -32,6 +32,24 @@ def test_library_exports_every_declared_symbol():
     assert set(declared()) == set(binding.SIGNATURES)
 
 
+def declared_arities():
+    """Number of parameters of every declared entry point (no function-pointer arguments)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:int|const char\s*\*)\s*(flare_\w+)\s*\(([^)]*)\)\s*;", text, flags=re.M):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_the_header():
+    from paper_2204_12573_amd import binding
+    ar = declared_arities()
+    assert set(ar) == set(declared())
+    for name, (_, args) in binding.SIGNATURES.items():
+        assert len(args) == ar[name], (name, len(args), ar[name])
+
+
 def test_host_only_calls():
     from paper_2204_12573_amd import binding
     if not os.path.exists(binding.LIB_PATH):
