@@ -59,7 +59,7 @@ class Footprint:
 
     def bytes(self, n_atoms):
         n, p = self.atoms_pairs(n_atoms)
-        per_atom = 4 * 16 + 8 * 12 + 4 * 6 + 8 * 24   # int arrays, FP64 SoA, FP32 outputs, pair cache
+        per_atom = 4 * 16 + 8 * 12 + 4 * 6 + 8 * 32   # int arrays, FP64 SoA, FP32 outputs, pair cache
         per_pair = 4 * 4                                # j, shift, reverse, slot of pair
         per_slot = 4 * 3 + 16 * 3                       # slot ints, fixed pair vector, geometry, reverse term
         rows = 2 * 144 * 4 + 16 + 5 * 4                 # descriptor + gradient, own force, row copies
