@@ -379,18 +379,35 @@ __global__ __launch_bounds__(NT) void k_fill_slots(int rows, int rows1, const in
   }
 }
 
+// Slot of every listed pair, in list order: a work-group takes the pairs of NT consecutive
+// atoms (one contiguous range of the list), keeps each atom's row and slice base in LDS and
+// finds each position's atom by bisection, so that the writes are coalesced.
 __global__ __launch_bounds__(NT) void k_slot_of_pair(int n, const int* __restrict__ bucket,
                                                      const int* __restrict__ row_of, int rows1,
                                                      const int* __restrict__ nl_off,
                                                      const int* __restrict__ slice_base,
                                                      int* __restrict__ slot_of_pair) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  const int b = bucket[i];
-  if (b < 0) return;                  // no listed pairs
-  const int R = global_row(b, row_of[i], rows1);
-  const int base = slice_base[R >> 5], p0 = nl_off[i], own = nl_off[i + 1] - p0;
-  for (int k = 0; k < own; ++k) slot_of_pair[p0 + k] = (base + k) * 32 + (R & 31);
+  __shared__ int offs[NT + 1], lane_row[NT], sbase[NT];
+  const int a0 = blockIdx.x * NT;
+  const int na = min(NT, n - a0);
+  for (int k = threadIdx.x; k <= na; k += NT) offs[k] = nl_off[a0 + k];
+  if (threadIdx.x < na) {
+    const int b = bucket[a0 + threadIdx.x];
+    // an atom without pairs owns no position of the list; its entries are never read
+    const int R = b < 0 ? 0 : global_row(b, row_of[a0 + threadIdx.x], rows1);
+    lane_row[threadIdx.x] = R & 31;
+    sbase[threadIdx.x] = b < 0 ? 0 : slice_base[R >> 5];
+  }
+  __syncthreads();
+  for (int p = offs[0] + threadIdx.x; p < offs[na]; p += NT) {
+    int lo = 0, hi = na;            // largest k with offs[k] <= p
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (offs[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    slot_of_pair[p] = (sbase[lo] + (p - offs[lo])) * 32 + lane_row[lo];
+  }
 }
 
 // Per listed pair p = (i, j, s), in list order: the slot of its reverse pair and the fixed
