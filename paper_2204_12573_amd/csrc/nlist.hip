@@ -208,15 +208,10 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
         const int sy = floor_div(uy, g.nb[1]);
         const int cy = uy - sy * g.nb[1];
         const double ty = (double)sy * g.L[1];
-        for (int ox = -g.K[0]; ox <= g.K[0]; ++ox) {
-          const int ux = bx + ox;
-          const int sx = floor_div(ux, g.nb[0]);
-          const int cx = ux - sx * g.nb[0];
+        // the atoms of bin bb (image shift sx along x) in order, four positions per step
+        auto scan_bin = [&](int j0, int j1, int sx) {
           const double tx = (double)sx * g.L[0];
-          const int bb = g.bin_base + (cz * g.nb[1] + cy) * g.nb[0] + cx;
-          const int j0 = bstart[bb], j1 = bstart[bb + 1];
           const bool zero_shift = (sx == 0) && (sy == 0) && (sz == 0);
-          // the bin's atoms in order, four positions loaded per step
           for (int j4 = j0; j4 < j1; j4 += 4) {
             double4 wq[4];
 #pragma unroll
@@ -240,6 +235,28 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
                 ++cnt;
               }
             }
+          }
+        };
+        const int rb = g.bin_base + (cz * g.nb[1] + cy) * g.nb[0];
+        if (g.K[0] == 1) {
+          // one-bin stencil in x: the row's three bin ranges are loaded together
+          int sxs[3], j0s[3], j1s[3];
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            const int ux = bx + u - 1;
+            sxs[u] = floor_div(ux, g.nb[0]);
+            const int bb = rb + (ux - sxs[u] * g.nb[0]);
+            j0s[u] = bstart[bb];
+            j1s[u] = bstart[bb + 1];
+          }
+#pragma unroll
+          for (int u = 0; u < 3; ++u) scan_bin(j0s[u], j1s[u], sxs[u]);
+        } else {
+          for (int ox = -g.K[0]; ox <= g.K[0]; ++ox) {
+            const int ux = bx + ox;
+            const int sx = floor_div(ux, g.nb[0]);
+            const int bb = rb + (ux - sx * g.nb[0]);
+            scan_bin(bstart[bb], bstart[bb + 1], sx);
           }
         }
       }
