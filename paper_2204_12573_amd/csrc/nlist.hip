@@ -275,8 +275,9 @@ __global__ __launch_bounds__(NT) void k_pairs(int n, const CellGrid* __restrict_
 // For every pair p = (i, j, s) find q = (j, i, -s) in j's list. The list is symmetric
 // because the FP64 distance test gives the same value for both orders (negating a
 // rounded difference is exact). Only pairs with i < j search (and write both rev[p] and
-// rev[q]); pairs of an atom with its own image (i == j) search for themselves; rev was
-// filled with -1 before, so a pair left without a partner shows in k_rev_check.
+// rev[q]); a pair of an atom with its own image (i == j) searches too, so both threads of
+// such a pair write the same two values; rev was filled with -1 before, so a pair left
+// without a partner shows in k_rev_check.
 // One thread per pair: a work-group takes the pairs of NT consecutive atoms, finds each
 // pair's atom by bisection in the group's offsets (in LDS), then scans j's list.
 __global__ __launch_bounds__(NT) void k_reverse(int n, const int* __restrict__ nl_off,
