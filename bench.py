@@ -186,6 +186,67 @@ def sample_errors(engine, torch, st, beta, sigma, precision, tg, ref):
             "sigma": float(np.abs(sg - ref.sigma[rows]).max() / np.abs(ref.sigma[rows]).max())}
 
 
+def precision_16m(engine, torch, small, beta, sigma, half_width=13.1, evals=5):
+    """The ~16 M-atom precision workload: the 1 M-atom cell tiled 4 x 4 laterally
+    (400 x 400 x 24 Pt(111) under the same gas column), one list build and `evals` timed
+    E + F + sigma evaluations per arithmetic form (inputs resident), errors against the FP64
+    oracle on a seeded subsample of ~10,000 atoms: every atom of a 2*half_width A square
+    column through slab, surface and gas at a seeded position (neighbouring sampled atoms
+    share the oracle's work), each taken from a random copy. The oracle evaluates them in the
+    1 M-atom cell, whose environments all copies share."""
+    import numpy as np
+
+    from oracle import evaluate as oev
+    from paper_2204_12573_amd import binding, structures as S
+    big = S.tiled(small, 4, 4)
+    n, n1 = big.n, small.n
+    rng = np.random.default_rng(2204)
+    cx, cy = rng.uniform(0.0, 1.0, 2) * small.box[:2]
+    dx = np.abs((small.pos[:, 0] - cx + 0.5 * small.box[0]) % small.box[0] - 0.5 * small.box[0])
+    dy = np.abs((small.pos[:, 1] - cy + 0.5 * small.box[1]) % small.box[1] - 0.5 * small.box[1])
+    tg = np.nonzero((dx < half_width) & (dy < half_width))[0]
+    n_sample = len(tg)
+    log(f"  oracle on {n_sample} sampled atoms ...")
+    t0 = time.perf_counter()
+    ref = oev.evaluate(small.pos, small.species, small.box, beta, sigma, targets=tg)
+    t_oracle = time.perf_counter() - t0
+    rows = ref.row_of(tg)
+    atoms = rng.integers(0, 16, len(tg)) * n1 + tg
+    p, s = engine.to_device(big.pos, big.species)
+    forms = {}
+    for name, prec in (("plain_fp32", 0), ("mixed_bf16_split", binding.BF16_SPLIT),
+                       ("mixed_fp8_split", binding.FP8_SPLIT), ("mixed_bf16x6_split", binding.BF16X6_SPLIT)):
+        log(f"  {name} on {n} atoms ...")
+        model = engine.Model(beta, sigma, precision=prec)
+        ev = engine.Evaluator(model, max_atoms=n, max_pairs=12 * n)
+        ev.neighbors(p, s, [0, n], big.box, 0.2)
+        out = ev.compute(p, want_var=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(evals):
+            out = ev.compute(p, want_var=True, out=out)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / evals
+        status = ev.status()
+        e = out["e"].cpu().numpy()[atoms]
+        f = out["f"].cpu().numpy().T[atoms]
+        sg = out["sigma"].cpu().numpy()[atoms]
+        forms[name] = {
+            "M_atom_evals_per_s": round(n / el / 1e6, 1), "ms_per_eval": round(el * 1e3, 3),
+            "status_flags": status,
+            "err_vs_fp64_oracle": {
+                "e": float(np.abs(e - ref.e[rows]).max() / np.abs(ref.e[rows]).max()),
+                "f": float(np.linalg.norm(f - ref.f, axis=1).max() / np.linalg.norm(ref.f, axis=1).max()),
+                "sigma": float(np.abs(sg - ref.sigma[rows]).max() / np.abs(ref.sigma[rows]).max())}}
+        del out, ev, model
+        torch.cuda.synchronize()
+    return {"atoms": n, "cell": "1 M-atom cell tiled 4 x 4 (400 x 400 x 24 Pt(111) + H2 gas)",
+            "evals_timed": evals,
+            "sample": f"{n_sample} atoms of a {2*half_width:.1f} A square column at a seeded position, each "
+                      f"from a random copy; FP64 oracle {t_oracle:.1f} s",
+            "forms": forms}
+
+
 def serving(engine, torch, beta, sigma, n_req, rate):
     from paper_2204_12573_amd import binding, serve
     out = {}
@@ -242,6 +303,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the split-precision, serving and autograd legs")
     ap.add_argument("--serve-requests", type=int, default=1200)
+    ap.add_argument("--no-huge", action="store_true", help="skip the ~16 M-atom precision leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy, a kernel of known traffic for counter scaling")
     args = ap.parse_args()
@@ -372,6 +434,9 @@ def main():
             "note": "both passes on BF16 matrix cores with d, beta and L split into three BF16 parts "
                     "(x0 + x1 + x2 = the FP32 value), six of the nine part products, FP32 accumulation "
                     "(FP32-level error); FP64 norms and sums; mixed-environment rows FP32"}
+        if not args.no_huge:
+            log("precision forms at ~16 M atoms ...")
+            out["precision_16m"] = precision_16m(engine, torch, st, beta, sigma)
         log("production NVT ...")
         out["production_nvt"] = production_nvt(engine, torch, st, beta, sigma, args.steps, args.warmup)
         log("serving ...")

@@ -178,6 +178,16 @@ def config_huge(seed=0) -> Structure:
     return h2_over_pt111(400, 400, 24, gas_height=1142.2, jitter=0.05, seed=seed)
 
 
+def tiled(st: Structure, nx: int, ny: int) -> Structure:
+    """The cell repeated nx x ny times laterally (a larger periodic cell). Every atom's
+    environment is its original's translated by whole box lengths, so a quantity of the
+    small cell holds for each of its copies; copy c = a + nx*b holds atoms [c*n, (c+1)*n)."""
+    shifts = [(a, b) for b in range(ny) for a in range(nx)]
+    pos = np.concatenate([st.pos + np.array([a * st.box[0], b * st.box[1], 0.0]) for a, b in shifts])
+    return Structure(pos=pos, species=np.tile(st.species, len(shifts)),
+                     box=np.array([nx * st.box[0], ny * st.box[1], st.box[2]]))
+
+
 def concat(structs) -> Batch:
     pos = np.concatenate([s.pos for s in structs])
     species = np.concatenate([s.species for s in structs]).astype(np.int32)

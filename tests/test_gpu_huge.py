@@ -22,19 +22,11 @@ TOLS = {Bd.FP32: TOL, Bd.BF16_SPLIT: 1e-4, Bd.FP8_SPLIT: 1e-2, Bd.BF16X6_SPLIT: 
 SIGMA_TOL = 1e-5
 
 
-def _tile(st, nx, ny):
-    n = st.n
-    shifts = [(a, b) for b in range(ny) for a in range(nx)]
-    pos = np.concatenate([st.pos + np.array([a * st.box[0], b * st.box[1], 0.0]) for a, b in shifts])
-    species = np.tile(st.species, len(shifts))
-    box = np.array([nx * st.box[0], ny * st.box[1], st.box[2]])
-    return pos, species, box, n
-
-
 def test_huge_tiled_all_forms():
     small = S.config_large()
     beta, sigma = S.random_model(DEFAULT.n_desc)
-    pos, species, box, n1 = _tile(small, 4, 4)
+    big_st = S.tiled(small, 4, 4)
+    pos, species, box, n1 = big_st.pos, big_st.species, big_st.box, small.n
     n = len(species)
     print(f"case: tiled cell, {n} atoms", flush=True)
     rng = np.random.default_rng(31)
