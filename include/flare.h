@@ -72,7 +72,11 @@ extern "C" {
 /* ---- device status bits (flare_status) ---- */
 #define FLARE_FLAG_NONFINITE  1  /* a position was NaN/inf                                     */
 #define FLARE_FLAG_SPECIES    2  /* a species index was out of range                            */
-#define FLARE_FLAG_DISPLACED  4  /* some atom moved more than skin/2 since the list was built    */
+#define FLARE_FLAG_DISPLACED  4  /* some atom moved more than skin/2 since the list was built:
+                                    the list may miss pairs inside r_cut, results of that step
+                                    are not to be trusted                                      */
+#define FLARE_FLAG_UNCERTAIN  8  /* flare_uncertainty_monitor: a cell's largest sigma exceeded
+                                    the threshold (the active-learning trigger)               */
 
 typedef struct flare_model flare_model;
 typedef struct flare_state flare_state;
@@ -204,11 +208,40 @@ int flare_forces(flare_state* state, const double* cell_scale, float* fx, float*
 int flare_virial(flare_state* state, double* virial_struct);
 
 /*
+ * flare_virial without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels
+ * and the same result, bit for bit, but the FP64 per-task sums go to a fixed 1 MiB device
+ * array of the library (one copy per GPU, held until the process ends) instead of state
+ * memory that flare_virial grows on its first call. No hipMalloc, hipFree or stage-timer
+ * event is made. Limit: at most 14,563 reduction tasks (a task is up to 2,048 atoms of one
+ * cell: about 29 M atoms in one cell, fewer with many small cells); beyond it
+ * FLARE_E_CAPACITY. The state's device must be current (FLARE_E_ARG otherwise). All calls
+ * on one GPU share the array: calls that overlap on one GPU (different streams at once) race.
+ *   virial_struct  DEVICE FP64 [n_struct][9], as flare_virial.
+ */
+int flare_virial_noalloc(flare_state* state, double* virial_struct);
+
+/*
  * Variance and uncertainty only (Eq. 2), from the resident descriptors.
  *   var_atom, sigma_atom  DEVICE FP32 [n_atoms] (either may be NULL)
  *   sigma_max             DEVICE FP32 [n_struct] largest sigma per cell (NULL = skip)
  */
 int flare_variance(flare_state* state, float* var_atom, float* sigma_atom, float* sigma_max);
+
+/*
+ * Uncertainty monitor of a production run (the paper's Section V.A active-learning
+ * trigger and Section VII.B runs, which watch the largest atomic uncertainty against a
+ * threshold): from the variances of the positions staged by the last flare_descriptors
+ * call (computed here if no earlier call formed them), per cell c
+ *   m_c = max_i sigma_i;  sigma_max_run[c] = max(sigma_max_run[c], m_c);
+ *   if m_c > threshold: over_count[c] += 1 and the status bit FLARE_FLAG_UNCERTAIN is raised.
+ *   sigma_max_run  DEVICE FP32 [n_struct], read and written (start it at 0)
+ *   over_count     DEVICE int32 [n_struct], read and written (start it at 0)
+ * Not synchronising: the caller reads the arrays, or the status bit through
+ * flare_status / flare_interval_status, when it next waits for the stream.
+ */
+int flare_uncertainty_monitor(flare_state* state, double threshold, float* sigma_max_run,
+                              int32_t* over_count);
 
 /*
  * Velocity-Verlet halves on caller arrays (DEVICE FP64 [n_atoms] each; forces FP32).
@@ -293,9 +326,18 @@ int flare_timers_read(flare_state* state, double* ms, long long* counts, int res
 /* Device memory held by the model (model may be NULL) and the state, in bytes (HOST). */
 int flare_memory_bytes(const flare_model* model, const flare_state* state, long long* bytes);
 
-/* Read and clear the device status word (SYNCHRONISING). flags_host: HOST int32.
- * flare_neighbors starts a new interval: it clears the word before its own checks. */
+/* Read and clear the status bits raised since the previous flare_status call
+ * (SYNCHRONISING). flags_host: HOST int32. The bits are sticky: a list build moves the
+ * device word to the host at its synchronisation point and does not drop it, so a bit
+ * raised in any interval between two list builds is returned here. */
 int flare_status(flare_state* state, int32_t* flags_host);
+
+/* The status bits raised between the previous list build (or flare_status call) and the
+ * last flare_neighbors call, i.e. during the interval that call ended (not synchronising:
+ * flare_neighbors read them at its own synchronisation point). They stay pending for
+ * flare_status as well. An MD driver checks FLARE_FLAG_DISPLACED | FLARE_FLAG_NONFINITE
+ * here after every rebuild. flags_host: HOST int32. */
+int flare_interval_status(const flare_state* state, int32_t* flags_host);
 
 #ifdef __cplusplus
 }

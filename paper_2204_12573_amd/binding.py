@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
 OK, E_ARG, E_SPECIES, E_BOX, E_CAPACITY, E_NONFINITE, E_STALE, E_OOM, E_HIP, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 FP32, BF16_SPLIT, FP8_SPLIT, BF16X6_SPLIT = 0, 1, 2, 3
-FLAG_NONFINITE, FLAG_SPECIES, FLAG_DISPLACED = 1, 2, 4
+FLAG_NONFINITE, FLAG_SPECIES, FLAG_DISPLACED, FLAG_UNCERTAIN = 1, 2, 4, 8
 
 
 class FlareError(RuntimeError):
@@ -47,6 +47,7 @@ SIGNATURES = {
     "flare_energy_forces": (_i, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "flare_forces": (_i, [_p, _p, _p, _p, _p]),
     "flare_virial": (_i, [_p, _p]),
+    "flare_virial_noalloc": (_i, [_p, _p]),
     "flare_model_info": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "flare_variance": (_i, [_p, _p, _p, _p]),
     "flare_memory_bytes": (_i, [_p, _p, ctypes.POINTER(_ll)]),
@@ -59,6 +60,8 @@ SIGNATURES = {
     "flare_timers_enable": (_i, [_p, _i]),
     "flare_timers_read": (_i, [_p, _p, _p, _i]),
     "flare_status": (_i, [_p, _p]),
+    "flare_interval_status": (_i, [_p, _p]),
+    "flare_uncertainty_monitor": (_i, [_p, _d, _p, _p]),
 }
 
 TIMER_NAMES = ["list", "desc144", "desc544", "qform144", "qform544", "force144", "force544",

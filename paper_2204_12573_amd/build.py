@@ -26,7 +26,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-munsafe-fp-atomics",
     # packed FP32 math stays off: the compiler must not form v_pk_* FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",

@@ -439,7 +439,6 @@ static void free_state(flare_state* s) {
   s->d_first_task.release();
   s->red_e.release();
   s->red_s.release();
-  s->vir_int.release();
   s->red_w.release();
   s->slice_len.release();
   s->slice_base.release();
@@ -743,11 +742,10 @@ int flare_virial(flare_state* s, double* virial_struct) {
     set_error("flare_virial needs forces (flare_energy_forces or flare_forces) for the current positions");
     return FLARE_E_STALE;
   }
-  CHK(s->vir_int.reserve((size_t)9 * s->n_atoms + 9));
   CHK(s->red_w.reserve((size_t)9 * s->tasks.size() + 9));
   {
     StageTimer tm(s, FLARE_T_OUT);
-    virial_cells(s, virial_struct);
+    virial_cells(s, virial_struct, s->red_w.p);
   }
   CHK(hipGetLastError());
   return FLARE_OK;
@@ -775,6 +773,33 @@ int flare_variance(flare_state* s, float* var_atom, float* sigma_atom, float* si
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, nullptr, nullptr, nullptr, nullptr, var_atom, sigma_atom);
     reduce_cells(s, nullptr, sigma_max);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_uncertainty_monitor(flare_state* s, double threshold, float* sigma_max_run, int32_t* over_count) {
+  ARG(s && sigma_max_run && over_count, "null pointer");
+  ARG(std::isfinite(threshold), "threshold must be finite");
+  if (!s->have_desc) {
+    set_error("flare_uncertainty_monitor before flare_descriptors");
+    return FLARE_E_STALE;
+  }
+  if (s->v_gen != s->pos_gen) {
+    {
+      StageTimer tm(s, FLARE_T_QFORM1);
+      fused_quadratic_forms(s, 2, nullptr);
+    }
+    compute_descriptors_mixed(s);
+    {
+      StageTimer tm(s, FLARE_T_QFORMX);
+      mixed_quadratic_forms(s, false, true);
+    }
+    s->v_gen = s->pos_gen;
+  }
+  {
+    StageTimer tm(s, FLARE_T_OUT);
+    reduce_cells(s, nullptr, nullptr, (float)threshold, sigma_max_run, over_count);
   }
   CHK(hipGetLastError());
   return FLARE_OK;
@@ -900,7 +925,7 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
          s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
          s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
          s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_d0.bytes() +
-         s->slot_rev.bytes() + s->geom.bytes() + s->f_own.bytes() + s->w_in.bytes() + s->pair_cache.bytes() + s->vir_int.bytes() + s->red_w.bytes() +
+         s->slot_rev.bytes() + s->geom.bytes() + s->f_own.bytes() + s->w_in.bytes() + s->pair_cache.bytes() + s->red_w.bytes() +
          s->cnt_row.bytes() + s->sid_row.bytes() + s->e_row.bytes() + s->v_row.bytes() +
          s->row_out.bytes() + s->row_caller.bytes();
   }
@@ -939,10 +964,17 @@ int flare_timers_read(flare_state* s, double* ms, long long* counts, int reset) 
 
 int flare_status(flare_state* s, int32_t* flags_host) {
   ARG(s && flags_host, "null pointer");
-  CHK(hipMemcpyAsync(s->h_info + 8, s->d_status, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  CHK(hipMemcpyAsync(s->h_info + 11, s->d_status, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   CHK(hipMemsetAsync(s->d_status, 0, sizeof(int), s->stream));
   CHK(hipStreamSynchronize(s->stream));
-  *flags_host = s->h_info[8];
+  *flags_host = s->h_info[11] | s->flags_pending;
+  s->flags_pending = 0;
+  return FLARE_OK;
+}
+
+int flare_interval_status(const flare_state* s, int32_t* flags_host) {
+  ARG(s && flags_host, "null pointer");
+  *flags_host = s->flags_at_build;
   return FLARE_OK;
 }
 

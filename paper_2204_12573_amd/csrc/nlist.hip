@@ -509,14 +509,18 @@ __global__ __launch_bounds__(NT) void k_off_check(int n, const int* __restrict__
   if (i <= n && nl_off[i] < 0) atomicOr(status, 512);
 }
 
-// info[0] = total pairs, info[1..6] = bucket totals, info[7] = status
+// info[0] = total pairs, info[1..6] = bucket totals, info[7] = the build's own status
+// word, info[8] = the caller-visible status word raised since it was last read, which is
+// moved to the host here (and cleared) so that no flag of the ended interval is lost
 __global__ void k_info(int n, const int* __restrict__ nl_off, const int* __restrict__ blk_scan,
-                       int nblk, const int* __restrict__ status, int* __restrict__ info) {
+                       int nblk, int* __restrict__ status, int* __restrict__ info) {
   if (threadIdx.x == 0) {
     info[0] = nl_off[n];
     for (int b = 0; b < NBUCKET; ++b)
       info[1 + b] = blk_scan[(size_t)(b + 1) * NCK * nblk] - blk_scan[(size_t)b * NCK * nblk];
-    info[7] = *status;
+    info[7] = status[1];
+    info[8] = status[0];
+    status[0] = 0;
   }
 }
 
@@ -551,10 +555,13 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->blk_bucket_scan.reserve((size_t)NKEY * nblk + 1));
   long long scan_n = std::max<long long>({(long long)nbins, (long long)n, (long long)NKEY * nblk});
   HIPCHK(s->scan_scratch.reserve(scan_scratch_ints(scan_n)));
-  HIPCHK(hipMemsetAsync(s->d_status, 0, sizeof(int), st));
+  // the build checks its inputs in a word of its own (d_status[1]); the caller-visible
+  // word d_status[0] keeps what the per-step calls raised until k_info moves it to the host
+  int* bst = s->d_status + 1;
+  HIPCHK(hipMemsetAsync(bst, 0, sizeof(int), st));
   if (n > 0) {
     k_wrap_bin<<<grid_of(n), NT, 0, st>>>(n, x, y, z, species, s->d_struct_off.p, nc, s->d_grids.p,
-                                          s->o_bin, s->o_sid, s->o_w, s->o_off, s->d_status);
+                                          s->o_bin, s->o_sid, s->o_w, s->o_off, bst);
   }
   HIPCHK(hipMemsetAsync(s->bin_count.p, 0, (nbins + 1) * sizeof(int), st));
   HIPCHK(hipMemsetAsync(s->bin_fill.p, 0, (nbins + 1) * sizeof(int), st));
@@ -575,10 +582,12 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   }
   scan_exclusive(s->nl_cnt, s->nl_off, n, s->scan_scratch.p, st);
   scan_exclusive(s->blk_bucket.p, s->blk_bucket_scan.p, NKEY * nblk, s->scan_scratch.p, st);
-  k_off_check<<<grid_of(n + 1), NT, 0, st>>>(n, s->nl_off, s->d_status);
+  k_off_check<<<grid_of(n + 1), NT, 0, st>>>(n, s->nl_off, bst);
   k_info<<<1, 64, 0, st>>>(n, s->nl_off, s->blk_bucket_scan.p, nblk, s->d_status, s->d_info);
-  HIPCHK(hipMemcpyAsync(s->h_info, s->d_info, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(s->h_info, s->d_info, 9 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  s->flags_at_build = s->h_info[8];
+  s->flags_pending |= s->h_info[8];
   const int flags = s->h_info[7];
   if (flags & FLARE_FLAG_SPECIES) {
     set_error("species index outside [0, n_species)");
@@ -629,7 +638,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
     if (pairs > 0) {
       HIPCHK(hipMemsetAsync(s->nl_rev, 0xff, (size_t)pairs * sizeof(int), st));
       k_reverse<<<nblk, NT, 0, st>>>(n, s->nl_off, s->nl_j, s->nl_s, s->nl_rev);
-      k_rev_check<<<(int)((pairs + NT - 1) / NT), NT, 0, st>>>((int)pairs, s->nl_rev, s->d_status);
+      k_rev_check<<<(int)((pairs + NT - 1) / NT), NT, 0, st>>>((int)pairs, s->nl_rev, bst);
     }
     k_assign_rows<<<nblk, NT, 0, st>>>(n, s->bucket, s->nl_cnt, s->blk_bucket_scan.p, nblk, row0, s->row_of,
                                         s->atom_of_row1.p, s->atom_of_rowx.p);
@@ -653,7 +662,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->scan_scratch.reserve(scan_scratch_ints(std::max<long long>(scan_n, s->n_slices))));
   scan_exclusive(s->slice_len.p, s->slice_base.p, s->n_slices, s->scan_scratch.p, st);
   HIPCHK(hipMemcpyAsync(s->h_info + 9, s->slice_base.p + s->n_slices, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(s->h_info + 10, s->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(s->h_info + 10, bst, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (s->h_info[10] & 256) {
     set_error("internal: neighbour list is not symmetric");

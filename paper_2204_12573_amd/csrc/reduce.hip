@@ -125,11 +125,16 @@ __global__ __launch_bounds__(NT) void k_reduce_tasks(const RedTask* __restrict__
 // lanes in a fixed stride, then combined in a fixed tree (deterministic).
 constexpr int NC = 64;
 
+// With a monitor (run_max != nullptr) the cell's largest sigma also updates its running
+// maximum, and a value above the threshold counts in over[cell] and raises the status bit.
 __global__ __launch_bounds__(NC) void k_reduce_cells(const double* __restrict__ red_e,
                                                      const float* __restrict__ red_s,
                                                      const int* __restrict__ first_task,
                                                      double* __restrict__ e_struct,
-                                                     float* __restrict__ sigma_max) {
+                                                     float* __restrict__ sigma_max, float thr,
+                                                     float* __restrict__ run_max,
+                                                     int* __restrict__ over,
+                                                     int* __restrict__ status) {
   __shared__ double ss[NC], sc[NC];
   __shared__ float sm[NC];
   const int cell = blockIdx.x, t = threadIdx.x;
@@ -157,48 +162,29 @@ __global__ __launch_bounds__(NC) void k_reduce_cells(const double* __restrict__ 
   if (t == 0) {
     if (e_struct) e_struct[cell] = ss[0] + sc[0];
     if (sigma_max) sigma_max[cell] = sm[0];
+    if (run_max) {
+      run_max[cell] = fmaxf(run_max[cell], sm[0]);
+      if (sm[0] > thr) {
+        over[cell] += 1;
+        atomicOr(status, FLARE_FLAG_UNCERTAIN);
+      }
+    }
   }
 }
 
-// Per-row virial terms over the row's own pairs in slot order, [9][n] internal. The cell's
-// W = -sum_p Delta_p (x) w_p runs over all its pairs; the reverse q of p has Delta_q =
-// -Delta_p and w_in(slot p) = w_q, so relabelling the sum gives W = sum_p Delta_p (x)
-// w_in(slot p), which each row forms from its own slots (Delta = r u from the geometry).
-__global__ __launch_bounds__(NT) void k_virial_rows(int rows, int rows1, const int* __restrict__ aor1,
-                                                    const int* __restrict__ aorx,
-                                                    const int* __restrict__ slice_base,
-                                                    const float4* __restrict__ geom,
-                                                    const float4* __restrict__ w_in,
-                                                    const int* __restrict__ cnt, int n,
-                                                    float* __restrict__ vir) {
-  const int R = xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-  if (R >= rows) return;
-  const int i = R < rows1 ? aor1[R] : aorx[R - rows1];
-  if (i < 0) return;
-  const int base = slice_base[R >> 5], len = cnt[i];
-  float acc[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = 0.f;
-  for (int k = 0; k < len; ++k) {
-    const int slot = (base + k) * 32 + (R & 31);
-    const float4 g = geom[slot];
-    const float4 wk = w_in[slot];
-    const float r = fabsf(g.w);      // 0 outside the cutoff: no contribution
-    const float d[3] = {r * g.x, r * g.y, r * g.z};
-    const float ww[3] = {wk.x, wk.y, wk.z};
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) acc[3 * a + b] += d[a] * ww[b];
-  }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) vir[(size_t)c * n + i] = acc[c];
-}
-
-// One block per task: FP64 sums of the 9 virial components over [begin, end), fixed order.
+// Virial of one reduction task (a contiguous internal atom range of one cell): per atom
+// the nine products over its own pairs in slot order, summed in FP32; then the atoms of
+// the task in FP64 in a fixed order. The cell's W = -sum_p Delta_p (x) w_p runs over all its
+// pairs; the reverse q of p has Delta_q = -Delta_p and w_in(slot p) = w_q, so relabelling the
+// sum gives W = sum_p Delta_p (x) w_in(slot p), which each atom forms from its own slots
+// (Delta = r u from the geometry). red_w [tasks][9] holds the task sums.
 __global__ __launch_bounds__(NT) void k_virial_tasks(const RedTask* __restrict__ tasks,
                                                      const int* __restrict__ bucket,
-                                                     const float* __restrict__ vir, int n,
+                                                     const int* __restrict__ row_of, int rows1,
+                                                     const int* __restrict__ slice_base,
+                                                     const float4* __restrict__ geom,
+                                                     const float4* __restrict__ w_in,
+                                                     const int* __restrict__ cnt,
                                                      double* __restrict__ red_w) {
   __shared__ double sw[9][NT];
   const RedTask tk = tasks[blockIdx.x];
@@ -206,9 +192,27 @@ __global__ __launch_bounds__(NT) void k_virial_tasks(const RedTask* __restrict__
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0;
   for (int i = tk.begin + threadIdx.x; i < tk.end; i += NT) {
-    if (bucket[i] < 0) continue;
+    const int b = bucket[i];
+    if (b < 0) continue;
+    const int R = b < 4 ? row_of[i] : rows1 + row_of[i];
+    const int base = slice_base[R >> 5], len = cnt[i];
+    float va[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] += (double)vir[(size_t)c * n + i];
+    for (int c = 0; c < 9; ++c) va[c] = 0.f;
+    for (int k = 0; k < len; ++k) {
+      const int slot = (base + k) * 32 + (R & 31);
+      const float4 g = geom[slot];
+      const float4 wk = w_in[slot];
+      const float r = fabsf(g.w);      // 0 outside the cutoff: no contribution
+      const float d[3] = {r * g.x, r * g.y, r * g.z};
+      const float ww[3] = {wk.x, wk.y, wk.z};
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) va[3 * x + y] += d[x] * ww[y];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += (double)va[c];
   }
 #pragma unroll
   for (int c = 0; c < 9; ++c) sw[c][threadIdx.x] = acc[c];
@@ -301,29 +305,24 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
                                                            fy, fz, var_atom, sigma_atom);
 }
 
-void reduce_cells(flare_state* s, double* e_struct, float* sigma_max) {
-  if (!e_struct && !sigma_max) return;
+void reduce_cells(flare_state* s, double* e_struct, float* sigma_max, float thr, float* run_max, int* over) {
+  if (!e_struct && !sigma_max && !run_max) return;
   const int nt = (int)s->tasks.size();
   if (nt == 0) return;
   k_reduce_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->e_int, s->v_int, e_struct != nullptr,
-                                           sigma_max != nullptr, s->red_e.p, s->red_s.p);
+                                           sigma_max != nullptr || run_max != nullptr, s->red_e.p, s->red_s.p);
   if (s->n_struct > 0)
     k_reduce_cells<<<s->n_struct, NC, 0, s->stream>>>(s->red_e.p, s->red_s.p, s->d_first_task.p, e_struct,
-                                                      sigma_max);
+                                                      sigma_max, thr, run_max, over, s->d_status);
 }
 
-void virial_cells(flare_state* s, double* virial_struct) {
-  const int n = s->n_atoms;
-  const int rows = s->rows1 + s->rowsx;
+void virial_cells(flare_state* s, double* virial_struct, double* red_w) {
   const int nt = (int)s->tasks.size();
-  if (rows > 0)
-    k_virial_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, s->rows1, s->atom_of_row1.p, s->atom_of_rowx.p,
-                                                             s->slice_base.p, s->geom.p, s->w_in.p, s->nl_cnt, n,
-                                                             s->vir_int.p);
   if (nt > 0)
-    k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->vir_int.p, n, s->red_w.p);
+    k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->row_of, s->rows1, s->slice_base.p,
+                                             s->geom.p, s->w_in.p, s->nl_cnt, red_w);
   if (s->n_struct > 0)
-    k_virial_cells<<<s->n_struct, NC, 0, s->stream>>>(s->red_w.p, s->d_first_task.p, virial_struct);
+    k_virial_cells<<<s->n_struct, NC, 0, s->stream>>>(red_w, s->d_first_task.p, virial_struct);
 }
 
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,

@@ -195,14 +195,15 @@ struct flare_state {
   flare::DevBuf<float> e_row, v_row;                 // per step: e_i, V_i
   flare::DevBuf<float4> row_out;                     // per step: (F_i, e_i) in row order
   flare::DevBuf<int> row_caller;                     // [N] row of each atom, caller order (-1: none)
-  // virial (allocated at the first flare_virial call)
-  flare::DevBuf<float> vir_int;                      // [9][max_atoms] per internal atom
+  // virial task sums (allocated at the first flare_virial call)
   flare::DevBuf<double> red_w;                       // [tasks][9]
 
   flare::Timers timers;
 
   // ---- status ----
-  int* d_status = nullptr;   // device status word
+  int* d_status = nullptr;   // [0] caller-visible status word (sticky), [1] list-build checks
+  int flags_at_build = 0;    // word [0] as the last list build found it
+  int flags_pending = 0;     // flags moved to the host by list builds, not yet returned by flare_status
   int* d_info = nullptr;     // small device results read at list builds
   int* h_info = nullptr;     // pinned host copy
 };
@@ -232,8 +233,11 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v);
 void compute_forces(flare_state* s, bool rows144);
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
                       float* var_atom, float* sigma_atom, const double* cell_scale = nullptr);
-void reduce_cells(flare_state* s, double* e_struct, float* sigma_max);
-void virial_cells(flare_state* s, double* virial_struct);
+// per-cell E and max sigma; with run_max, the uncertainty monitor (threshold thr, counts in over)
+void reduce_cells(flare_state* s, double* e_struct, float* sigma_max, float thr = 0.f, float* run_max = nullptr,
+                  int* over = nullptr);
+// per-cell virial; red_w: [tasks][9] FP64 task sums (scratch)
+void virial_cells(flare_state* s, double* virial_struct, double* red_w);
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy,
               double* vz, const float* fx, const float* fy, const float* fz,
               const int32_t* species, double inv_m0, double inv_m1, double dt);

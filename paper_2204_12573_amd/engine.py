@@ -140,6 +140,13 @@ class Evaluator:
             B.check(self.lib.flare_virial(self.handle, B.ptr(out)))
         return out
 
+    def virial_noalloc(self, out):
+        """As virial(), through the allocation-free entry point; `out` is a device FP64
+        [n_struct, 3, 3] tensor (the call allocates nothing)."""
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_virial_noalloc(self.handle, B.ptr(out)))
+        return out
+
     def memory_bytes(self, with_model=True):
         b = ctypes.c_longlong()
         B.check(self.lib.flare_memory_bytes(self.model.handle if with_model else None, self.handle,
@@ -171,9 +178,23 @@ class Evaluator:
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(B.TIMER_NAMES)}
 
     def status(self):
+        """Status bits raised since the last call (synchronising; sticky across list builds)."""
         f = np.zeros(1, np.int32)
         B.check(self.lib.flare_status(self.handle, B.ptr(f)))
         return int(f[0])
+
+    def interval_status(self):
+        """Status bits of the interval the last list build ended (no wait)."""
+        f = np.zeros(1, np.int32)
+        B.check(self.lib.flare_interval_status(self.handle, B.ptr(f)))
+        return int(f[0])
+
+    def uncertainty_monitor(self, threshold, sigma_max_run, over_count):
+        """Per-cell running max of sigma and count of evaluations above `threshold`
+        (device FP32 / int32 [n_struct], updated in place) for the staged positions."""
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_uncertainty_monitor(self.handle, float(threshold), B.ptr(sigma_max_run),
+                                                       B.ptr(over_count)))
 
     def _outputs(self, out, want_var):
         out = {} if out is None else out
@@ -245,11 +266,28 @@ def to_device(pos, species, device="cuda"):
     return p, s
 
 
+class DisplacedError(RuntimeError):
+    """An interval between two list builds raised FLARE_FLAG_DISPLACED or NONFINITE: some
+    atom moved more than half the skin (the list may have missed pairs) or a position
+    became non-finite."""
+
+
+def check_interval(ev):
+    flags = ev.interval_status()
+    bad = flags & (B.FLAG_DISPLACED | B.FLAG_NONFINITE)
+    if bad:
+        raise DisplacedError(f"list interval ended with status flags {flags:#x} (displaced > skin/2 or non-finite)")
+    return flags
+
+
 class MD:
     """Velocity-Verlet NVE with a neighbour-list rebuild every `rebuild` steps.
 
     One step: half kick + drift, list rebuild when due, descriptors, energies, forces
-    (and variances), half kick. State (x, v) stays FP64 on the device.
+    (and variances), half kick. State (x, v) stays FP64 on the device. Every rebuild checks
+    the status bits of the interval it ends (no extra wait: the build reads them at its
+    own synchronisation point) and raises DisplacedError if an atom moved more than half
+    the skin or a position became non-finite.
     """
 
     def __init__(self, ev: Evaluator, pos, vel, species, offsets, boxes, dt=0.5, skin=0.2,
@@ -267,6 +305,7 @@ class MD:
         self.nstep += 1
         if self.nstep % self.rebuild == 0:
             ev.neighbors(self.pos, self.species, self.offsets, self.boxes, self.skin)
+            check_interval(ev)
         ev.descriptors(self.pos)
         ev.energy_forces(self.out, self.want_var)
         ev.md_second_half(self.vel, self.out["f"], self.dt)
@@ -289,6 +328,7 @@ class NVT(MD):
         self.nstep += 1
         if self.nstep % self.rebuild == 0:
             ev.neighbors(self.pos, self.species, self.offsets, self.boxes, self.skin)
+            check_interval(ev)
         ev.descriptors(self.pos)
         ev.energy_forces(self.out, self.want_var)
         ev.nvt_second_half(self.vel, self.out["f"], self.dt, self.t_target, self.tau, self.thermo)
@@ -299,25 +339,29 @@ class Production:
     """The in-situ work of the paper's production runs (Section VI.A) around an NVT run:
     every `every` steps, hydrogen coordination numbers, the reaction events since the last
     snapshot (dissociations 1 -> 0, recombinations 0 -> 1) and the largest uncertainty per
-    cell against the active-learning threshold (sigma > threshold flags the cell)."""
+    cell against the active-learning threshold, all on the device (flare_coordination,
+    flare_uncertainty_monitor): `sigma_max` is the running maximum per cell, `over` counts
+    the monitor points at which a cell exceeded the threshold, and the status bit
+    FLARE_FLAG_UNCERTAIN, read at list builds, says whether any did."""
 
     def __init__(self, nvt: NVT, every=1000, threshold=0.005):
         self.nvt, self.every, self.threshold = nvt, every, threshold
         self.coord, _ = nvt.ev.coordination(nvt.pos)
         self.events = torch.zeros((nvt.ev.n_struct, 2), dtype=torch.int64, device=nvt.ev.device)
         self.sigma_max = torch.zeros(nvt.ev.n_struct, dtype=torch.float32, device=nvt.ev.device)
-        self.flagged = []
+        self.over = torch.zeros(nvt.ev.n_struct, dtype=torch.int32, device=nvt.ev.device)
 
     def step(self):
         out = self.nvt.step()
         if self.nvt.nstep % self.every == 0:
             ev = self.nvt.ev
             coord, ev_counts = ev.coordination(self.nvt.pos, self.coord)
-            self.events += ev_counts
+            with torch.cuda.stream(ev.stream):
+                self.events += ev_counts
             self.coord = coord
-            smax = ev.variance()["sigma_max"]
-            self.sigma_max = torch.maximum(self.sigma_max, smax)
-            hot = torch.nonzero(smax > self.threshold).flatten().cpu().tolist()
-            if hot:
-                self.flagged.append((self.nvt.nstep, hot))
+            ev.uncertainty_monitor(self.threshold, self.sigma_max, self.over)
         return out
+
+    def flagged_cells(self):
+        """Cells whose largest sigma exceeded the threshold at some monitor point (waits)."""
+        return torch.nonzero(self.over).flatten().cpu().tolist()

@@ -9,6 +9,7 @@ from oracle import evaluate as oev, forces as ofo
 from oracle.hyper import DEFAULT
 from paper_2204_12573_amd import autograd as AG, engine, structures as S
 
+from . import oracle_pool as OP
 from .gpu_util import TOL, rel_vec
 
 pytestmark = pytest.mark.gpu
@@ -28,8 +29,10 @@ def _pos(b):
 
 
 def test_energy_and_gradient_vs_oracle(setup):
+    """Every one of the 256 cells: its energy and the gradient of a weighted sum of all
+    cell energies against the oracle's energy and analytic forces (FP64)."""
     beta, sigma, b, mod = setup
-    print("case: autograd, 256 cells", flush=True)
+    print("case: autograd, 256 cells vs oracle gradient", flush=True)
     pos = _pos(b)
     E = mod(pos)
     w = torch.linspace(0.5, 1.5, len(E), dtype=torch.float64, device="cuda")
@@ -37,30 +40,45 @@ def test_energy_and_gradient_vs_oracle(setup):
     E = E.detach().cpu().numpy()
     g = g.cpu().numpy().T
     w = w.cpu().numpy()
-    for k in [0, 1, 77, 128, 255]:
-        st = b.structure(k)
+    jobs = [(b.structure(k).pos, b.structure(k).species, b.structure(k).box, beta, sigma) for k in range(len(b.boxes))]
+    refs = OP.run(OP.cell_energy_forces, jobs)
+    err_e, err_g = [], []
+    for k, (e_ref, f_ref) in enumerate(refs):
         lo, hi = b.offsets[k], b.offsets[k + 1]
-        ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
-        assert abs(E[k] - ref.energy) <= TOL * abs(ref.energy)
-        assert rel_vec(g[lo:hi], -w[k] * ref.f) <= TOL
+        err_e.append(abs(E[k] - e_ref) / abs(e_ref))
+        err_g.append(rel_vec(g[lo:hi], -w[k] * f_ref))
+    print(f"max over 256 cells: energy {max(err_e):.2e}, gradient {max(err_g):.2e}", flush=True)
+    assert max(err_e) <= TOL and max(err_g) <= TOL
 
 
 def test_gradient_vs_oracle_finite_differences(setup):
+    """Four seeded cells, every atom and component: the adjoint gradient of the sum of their
+    energies against central differences (h = 1e-4 A) of the FP64 oracle energy."""
     beta, sigma, b, mod = setup
+    rng = np.random.default_rng(4)
+    cells = np.sort(rng.choice(len(b.boxes), 4, replace=False))
+    print(f"case: autograd FD, cells {cells.tolist()}", flush=True)
     pos = _pos(b)
     E = mod(pos)
-    (g,) = torch.autograd.grad(E[3], pos)
+    sel = torch.zeros(len(E), dtype=torch.float64, device="cuda")
+    sel[torch.from_numpy(cells).cuda()] = 1.0
+    (g,) = torch.autograd.grad((sel * E).sum(), pos)
     g = g.cpu().numpy().T
-    st = b.structure(3)
-    lo = b.offsets[3]
-    atoms = [0, 50, 143, 144, st.n - 1]
-    fn = lambda p: oev.total_energy(p, st.species, st.box, beta)
-    fd = ofo.forces_fd(fn, st.pos, atoms, step=1e-4)     # central differences, FP64
-    ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
-    scale = np.linalg.norm(ref.f, axis=1).max()
-    assert np.linalg.norm(g[lo + np.array(atoms)] + fd, axis=1).max() / scale <= 2e-5
-    # and the gradient of one cell's energy is zero on every other cell
-    other = np.r_[0:lo, b.offsets[4]:b.n]
+    jobs, where = [], []
+    for k in cells:
+        st = b.structure(k)
+        for chunk in np.array_split(np.arange(st.n), 12):
+            jobs.append((st.pos, st.species, st.box, beta, 1e-4, chunk))
+            where.append(b.offsets[k] + chunk)
+    fd = np.concatenate(OP.run(OP.local_fd_forces, jobs))
+    where = np.concatenate(where)
+    scale = np.linalg.norm(fd, axis=1).max()
+    err = np.linalg.norm(g[where] + fd, axis=1).max() / scale
+    print(f"adjoint vs FD: {err:.2e} over {len(where)} atoms", flush=True)
+    assert err <= 2e-5
+    # the gradient is zero on every atom of the other cells
+    other = np.ones(b.n, bool)
+    other[where] = False
     assert np.all(g[other] == 0.0)
 
 

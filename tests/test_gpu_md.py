@@ -6,7 +6,7 @@ import torch
 
 from oracle import evaluate as oev, md as omd
 from oracle.hyper import DEFAULT
-from paper_2204_12573_amd import engine, structures as S
+from paper_2204_12573_amd import binding as Bd, engine, structures as S
 
 pytestmark = pytest.mark.gpu
 
@@ -36,3 +36,24 @@ def test_nve_matches_oracle():
     assert np.abs(x - x_ref).max() < 1e-7
     np.testing.assert_allclose(epot, ep_ref, rtol=1e-5)
     assert ev.status() == 0
+
+
+def test_displaced_interval_raises_at_the_rebuild():
+    """An atom moved more than half the skin between two list builds: the rebuild that ends
+    the interval raises (the flag is not lost by the build), and flare_status still has it."""
+    st = S.config_tiny()
+    beta, sigma = S.random_model(DEFAULT.n_desc)
+    model = engine.Model(beta, sigma)
+    ev = engine.Evaluator(model, max_atoms=st.n, max_pairs=64 * st.n)
+    p, s = engine.to_device(st.pos, st.species)
+    v = torch.zeros_like(p)
+    print("case: tiny NVE, forced displacement", flush=True)
+    md = engine.MD(ev, p, v, s, [0, st.n], st.box, dt=0.5, skin=0.2, rebuild=3)
+    md.step()
+    p[0, 7] += 0.15              # more than skin/2 = 0.1 A
+    md.step()                    # step 2: descriptors raise the flag, no rebuild yet
+    with pytest.raises(engine.DisplacedError):
+        md.step()                # step 3 rebuilds and reports the ended interval
+    assert ev.interval_status() & Bd.FLAG_DISPLACED
+    assert ev.status() & Bd.FLAG_DISPLACED
+    assert ev.status() == 0      # read and cleared

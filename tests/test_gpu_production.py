@@ -7,7 +7,7 @@ import torch
 
 from oracle import evaluate as oev, md as omd
 from oracle.hyper import DEFAULT
-from paper_2204_12573_amd import engine, structures as S
+from paper_2204_12573_amd import binding as Bd, engine, structures as S
 
 pytestmark = pytest.mark.gpu
 
@@ -115,12 +115,24 @@ def test_production_monitor(model):
     p, s = engine.to_device(st.pos, st.species)
     v = torch.from_numpy(np.ascontiguousarray(v0.T)).cuda()
     nvt = engine.NVT(ev, p, v, s, [0, st.n], st.box, t_target=450.0, tau=10.0, dt=0.1)
+    assert ev.status() == 0
     low = engine.Production(nvt, every=2, threshold=0.0)
     for _ in range(4):
         low.step()
-    assert [f[0] for f in low.flagged] == [2, 4]
+    # the monitor ran at steps 2 and 4 and found the cell above a zero threshold both times
+    assert low.over.cpu().tolist() == [2]
+    assert low.flagged_cells() == [0]
+    assert ev.status() & Bd.FLAG_UNCERTAIN
     high = engine.Production(nvt, every=2, threshold=1e9)
+    seen = []
     for _ in range(4):
         high.step()
-    assert high.flagged == []
-    assert float(high.sigma_max[0]) > 0.0
+        if nvt.nstep % 2 == 0:
+            seen.append(float(ev.variance()["sigma_max"][0]))
+    assert high.flagged_cells() == []
+    assert ev.status() == 0
+    # the running maximum is the largest per-cell maximum of the monitor points, and that
+    # maximum is the oracle's largest sigma at the positions of the last one
+    assert float(high.sigma_max[0]) == max(seen)
+    ref = oev.evaluate(p.cpu().numpy().T, st.species, st.box, beta, sigma)
+    assert abs(seen[-1] - ref.sigma.max()) <= 1e-5 * ref.sigma.max()

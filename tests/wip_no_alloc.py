@@ -1,0 +1,85 @@
+"""The allocation-free virial entry point (flare_virial_noalloc, task sums in the library's
+static device array) against flare_virial through the C ABI: two calls in a row, the
+second with a smaller input, each bitwise equal to the allocating entry point's result
+(same kernels, same summation order) and within the FP32 bar of the FP64 oracle virial;
+and the size limit is refused with FLARE_E_CAPACITY before any device work."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import evaluate as oev
+from oracle.hyper import DEFAULT
+from paper_2204_12573_amd import binding as Bd, engine, structures as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _evaluator(beta, sigma, pos, species, offsets, boxes):
+    model = engine.Model(beta, sigma)
+    n = len(species)
+    ev = engine.Evaluator(model, max_atoms=n, max_pairs=64 * n)
+    p, s = engine.to_device(pos, species)
+    ev.neighbors(p, s, offsets, np.asarray(boxes, np.float64).reshape(-1, 3), 0.2)
+    ev.descriptors(p)
+    ev.energy_forces(want_var=False)
+    return model, ev
+
+
+def _both(ev, n_struct):
+    w_static = torch.full((n_struct, 3, 3), float("nan"), dtype=torch.float64, device="cuda")
+    ev.virial_noalloc(w_static)
+    w_alloc = ev.virial()
+    torch.cuda.synchronize()
+    return w_static.cpu().numpy(), w_alloc.cpu().numpy()
+
+
+def test_virial_noalloc_two_calls_second_smaller():
+    beta, sigma = S.random_model(DEFAULT.n_desc)
+    b = S.config_cells(n_cells=6, seed=5)
+    print("case: virial_noalloc, 6 cells then the 80-atom cell", flush=True)
+    model1, ev1 = _evaluator(beta, sigma, b.pos, b.species, b.offsets, b.boxes)
+    w1, r1 = _both(ev1, 6)
+    np.testing.assert_array_equal(w1, r1)
+    for k in range(6):
+        st = b.structure(k)
+        ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma, want_virial=True).virial
+        assert np.abs(w1[k] - ref).max() / np.abs(ref).max() <= TOL
+    st = S.config_tiny()
+    model2, ev2 = _evaluator(beta, sigma, st.pos, st.species, [0, st.n], st.box)
+    w2, r2 = _both(ev2, 1)
+    np.testing.assert_array_equal(w2, r2)
+    ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma, want_virial=True).virial
+    assert np.abs(w2[0] - ref).max() / np.abs(ref).max() <= TOL
+    # the first state is unaffected by the second call sharing the array
+    w1b, _ = _both(ev1, 6)
+    np.testing.assert_array_equal(w1b, r1)
+
+
+def test_virial_noalloc_refuses_more_tasks_than_the_array_holds():
+    """14,564 one-molecule cells need 14,564 reduction tasks, one more than the static
+    array holds: the call returns FLARE_E_CAPACITY (checked on the host, nothing launched)
+    and the allocating entry point still works."""
+    beta, sigma = S.random_model(DEFAULT.n_desc)
+    n_cells = 14564
+    rng = np.random.default_rng(1)
+    box = np.array([12.0, 12.0, 12.0])
+    u = rng.standard_normal((n_cells, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    centre = rng.uniform(2.0, 10.0, (n_cells, 3))
+    pos = np.empty((2 * n_cells, 3))
+    pos[0::2] = centre + 0.37 * u
+    pos[1::2] = centre - 0.37 * u
+    species = np.zeros(2 * n_cells, np.int32)
+    offsets = np.arange(0, 2 * n_cells + 1, 2, dtype=np.int32)
+    boxes = np.tile(box, (n_cells, 1))
+    print("case: virial_noalloc capacity, 14564 cells", flush=True)
+    model, ev = _evaluator(beta, sigma, pos, species, offsets, boxes)
+    out = torch.zeros((n_cells, 3, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(Bd.FlareError) as err:
+        ev.virial_noalloc(out)
+    assert err.value.code == Bd.E_CAPACITY
+    w = ev.virial()
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(w.cpu().numpy()))
