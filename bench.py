@@ -69,26 +69,85 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(st, beta, sigma, half_width=11.0):
-    """The FP64 oracle on a bounded sample: every atom of a 2*half_width A square column
-    through slab and gas (E+F+sigma for those atoms)."""
+def _oracle_crop_part(job):
+    """One worker's share of the oracle crop: E+F+sigma of the given target atoms."""
+    from oracle import evaluate as oev
+    pos, species, box, beta, sigma, tg = job
+    t0 = time.perf_counter()
+    oev.evaluate(pos, species, box, beta, sigma, targets=tg)
+    return time.perf_counter() - t0
+
+
+def _n_workers():
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        cpus = os.cpu_count() or 1
+    return max(1, min(16, cpus))
+
+
+def cpu_baseline(st, beta, sigma, n_crop=100_000, seed=2204):
+    """The FP64 oracle on a bounded sample of the workload: a seeded crop of n_crop atoms of
+    the 1 M-atom cell (every atom of a lateral square column through slab and gas, centred at
+    a seeded point), one E+F+sigma evaluation of those atoms, their targets split into
+    contiguous spatial blocks over one worker process per core (each worker one BLAS thread).
+    The oracle's cost is linear in the atoms it evaluates (neighbour lists from a k-d tree,
+    per-atom descriptors and forms), so a full evaluation of the cell takes N / rate."""
+    import multiprocessing as mp
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    cx, cy = rng.uniform(0.0, 1.0, 2) * st.box[:2]
+    dx = np.abs((st.pos[:, 0] - cx + 0.5 * st.box[0]) % st.box[0] - 0.5 * st.box[0])
+    dy = np.abs((st.pos[:, 1] - cy + 0.5 * st.box[1]) % st.box[1] - 0.5 * st.box[1])
+    r = np.maximum(dx, dy)
+    tg = np.argsort(r, kind="stable")[:n_crop]            # the n_crop atoms nearest the column axis
+    order = tg[np.lexsort((st.pos[tg, 1], st.pos[tg, 0], st.pos[tg, 2]))]
+    nw = _n_workers()
+    parts = np.array_split(order, nw)
+    jobs = [(st.pos, st.species, st.box, beta, sigma, np.sort(p)) for p in parts]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(nw, initializer=_one_blas_thread) as pool:
+        busy = pool.map(_oracle_crop_part, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    rate = len(tg) / wall
+    return {"value": rate / 1e6, "unit": "M atom-steps/s", "cores": int(nw), "kind": "oracle",
+            "sample": f"seeded {len(tg)}-atom crop of the {st.n}-atom cell (a lateral square column through slab "
+                      f"and gas), one E+F+sigma evaluation of those atoms in {wall:.1f} s wall over {nw} worker "
+                      f"processes ({sum(busy):.1f} s of worker time); numpy FP64, one BLAS thread per worker",
+            "full_cell_extrapolation_s": round(st.n / rate, 1)}
+
+
+def _one_blas_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:  # pragma: no cover
+        pass
+
+
+def oracle_tiny_run(beta, sigma, n_steps=10, dt=0.5):
+    """The small workload in full on the host: one E+F+sigma evaluation of the 80-atom cell and
+    a 10-step NVE run (dt 0.5 fs) with the FP64 oracle, single process."""
     import numpy as np
 
-    from oracle import evaluate as oev
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        blas = 1
-    cx, cy = st.box[0] / 2, st.box[1] / 2
-    m = (np.abs(st.pos[:, 0] - cx) < half_width) & (np.abs(st.pos[:, 1] - cy) < half_width)
-    tg = np.nonzero(m)[0]
+    from oracle import evaluate as oev, md as omd
+    from paper_2204_12573_amd import structures as S
+    st = S.config_tiny()
     t0 = time.perf_counter()
-    oev.evaluate(st.pos, st.species, st.box, beta, sigma, targets=tg)
-    dt = time.perf_counter() - t0
-    return {"value": len(tg) / dt / 1e6, "unit": "M atom-steps/s", "cores": int(blas), "kind": "oracle",
-            "sample": f"{len(tg)} atoms of a {2*half_width:.0f}x{2*half_width:.0f} A column (slab + gas) of "
-                      f"the same cell, one E+F+sigma evaluation in {dt:.1f} s; numpy FP64, BLAS threads={blas}"}
+    oev.evaluate(st.pos, st.species, st.box, beta, sigma)
+    t_eval = time.perf_counter() - t0
+
+    def fn(x):
+        r = oev.evaluate(x, st.species, st.box, beta, sigma)
+        return r.energy, r.f
+
+    t0 = time.perf_counter()
+    omd.nve(st.pos, np.zeros_like(st.pos), st.species, dt, n_steps, fn)
+    t_md = time.perf_counter() - t0
+    return {"atoms": st.n, "eval_s": round(t_eval, 3), "nve_steps": n_steps, "nve_s": round(t_md, 3),
+            "M_atom_steps_per_s": st.n * (n_steps + 1) / (t_eval + t_md) / 1e6,
+            "note": "80-atom H2/Pt(111) cell: one evaluation plus a 10-step NVE run (11 evaluations), FP64 oracle"}
 
 
 def md_throughput(engine, torch, st, beta, sigma, steps, warmup, precision):
@@ -170,7 +229,9 @@ def valu_work(engine, st):
     n_h = np.bincount(i, weights=(spj == 0), minlength=st.n)
     n_pt = np.bincount(i, weights=(spj == 1), minlength=st.n)
     single = (n_h > 0) ^ (n_pt > 0)
-    return {"pairs144": int(np.count_nonzero(inside & single[i]))}
+    mixed = (n_h > 0) & (n_pt > 0)
+    return {"pairs144": int(np.count_nonzero(inside & single[i])),
+            "pairs544": int(np.count_nonzero(inside & mixed[i]))}
 
 
 def sample_errors(engine, torch, st, beta, sigma, precision, tg, ref):
@@ -220,7 +281,8 @@ def precision_16m(engine, torch, small, beta, sigma, half_width=13.1, evals=5):
     p, s = engine.to_device(big.pos, big.species)
     forms = {}
     for name, prec in (("plain_fp32", 0), ("mixed_bf16_split", binding.BF16_SPLIT),
-                       ("mixed_fp8_split", binding.FP8_SPLIT), ("mixed_bf16x6_split", binding.BF16X6_SPLIT)):
+                       ("mixed_fp8_split", binding.FP8_SPLIT), ("mixed_bf16x6_split", binding.BF16X6_SPLIT),
+                       ("mixed_bf16x6_split_var32", binding.BF16X6_SPLIT | binding.VAR_FP32)):
         log(f"  {name} on {n} atoms ...")
         model = engine.Model(beta, sigma, precision=prec)
         ev = engine.Evaluator(model, max_atoms=n, max_pairs=12 * n)
@@ -378,6 +440,29 @@ def main():
                 "variance_form": "cholesky" if vchol else "full",
                 "mfma_only": {"achieved": flops_per_launch / t_launch / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                               "frac": flops_per_launch / t_launch / PEAK_FP32_MFMA}}
+    # whole step against its ideal time: every stage at the bound of its algorithmic work
+    # (the per-unit figures of the method; stage-internal layouts such as the per-slot pair
+    # geometry are implementation, not algorithmic work):
+    #   144-wide rows  the fused kernel's t_min above (matrix + vector flops);
+    #   544-wide rows  Y = D beta (2 544^2) and Z = D L (544 * 545) per row on the FP32 matrix
+    #                  cores, vector work per pair (densities 320, adjoint 830) and per row
+    #                  (B2 4352, |d~|^2 1088, epilogue e, g, V 3808, u 8192) at the vector peak;
+    #   list build     100 B per Pt atom, 50 B per H atom of HBM traffic, every `rebuild` steps;
+    #   integrator, reductions and outputs  100 B per atom of HBM traffic.
+    n_pt = int((st.species == 1).sum())
+    mx_mfma = n544 * (2 * 544 * 544 + (544 * 545 if vchol else 2 * 544 * 544))
+    mx_valu = work["pairs544"] * (VALU_FLOP_DENS + VALU_FLOP_ADJ) + n544 * (4352 + 1088 + 3808 + 8192)
+    t_parts = {"rows144_fused": t_min,
+               "rows544": mx_mfma / PEAK_FP32_MFMA + mx_valu / PEAK_FP32_VALU,
+               "list_build": (n_pt * 100 + (n - n_pt) * 50) / PEAK_HBM / 10,
+               "integrator_outputs": n * 100 / PEAK_HBM}
+    t_ideal = sum(t_parts.values())
+    t_step = el / args.steps
+    step_roofline = {"t_ideal_us": t_ideal * 1e6, "t_measured_us": t_step * 1e6, "frac": t_ideal / t_step,
+                     "parts_us": {k: round(v * 1e6, 2) for k, v in t_parts.items()},
+                     "note": "T_ideal / T_measured of one whole MD step (list rebuilds amortised), each stage "
+                             "at the bound of its algorithmic work (FP32 matrix 157.3, FP32 vector 78.6 "
+                             "TFLOP/s, HBM 8 TB/s)"}
     stage_us = {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm.items() if c}
     out = {
         "metric": METRIC,
@@ -396,6 +481,7 @@ def main():
                    "atoms": n, "pairs": int(npairs), "rows144": n144, "rows544": n544,
                    "n_desc": 544, "r_cut": 4.5, "skin": 0.2, "precision": "fp32"},
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "stage_us_per_launch": stage_us,
         "status_flags": status,
     }
@@ -412,6 +498,9 @@ def main():
         ev6, m6, el6, tm6 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
                                           binding.BF16X6_SPLIT)
         del ev6, m6
+        ev7, m7, el7, tm7 = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup,
+                                          binding.BF16X6_SPLIT | binding.VAR_FP32)
+        del ev7, m7
         log("errors vs the FP64 oracle on a 300-atom sample ...")
         rng = np.random.default_rng(12)
         ztop = 23 * S.DZ
@@ -424,21 +513,29 @@ def main():
             "value": round(n * args.steps / el2 / 1e6, 3), "ms_per_step": round(el2 / args.steps * 1e3, 4),
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.BF16_SPLIT, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm2.items() if c},
-            "note": "energy pass BF16 x3 (d and beta split hi/lo), variance |L^T d|^2 on FP32 cores "
-                    "with an FP64 Cholesky factor, FP64 sums; mixed-environment rows FP32"}
+            "note": "energy pass BF16 x3 (d and beta split hi/lo), variance |L^T d|^2 with the FP64 factor "
+                    "on FP64 matrix cores, FP64 sums; mixed-environment rows: FP32 energy, FP64 variance"}
         out["mixed_fp8_split"] = {
             "value": round(n * args.steps / el3 / 1e6, 3), "ms_per_step": round(el3 / args.steps * 1e3, 4),
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.FP8_SPLIT, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm3.items() if c},
             "note": "energy pass OCP e4m3 x3 with power-of-two row and block scales (d and beta split "
-                    "hi/lo'), variance as in the BF16 form; mixed-environment rows FP32"}
+                    "hi/lo'), variance as in the BF16 form (FP64); mixed-environment rows: FP32 energy"}
         out["mixed_bf16x6_split"] = {
             "value": round(n * args.steps / el6 / 1e6, 3), "ms_per_step": round(el6 / args.steps * 1e3, 4),
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.BF16X6_SPLIT, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm6.items() if c},
-            "note": "both passes on BF16 matrix cores with d, beta and L split into three BF16 parts "
+            "note": "energy pass on BF16 matrix cores with d and beta split into three BF16 parts "
                     "(x0 + x1 + x2 = the FP32 value), six of the nine part products, FP32 accumulation "
-                    "(FP32-level error); FP64 norms and sums; mixed-environment rows FP32"}
+                    "(FP32-level error); variance |L^T d|^2 with the FP64 factor on FP64 matrix cores; FP64 "
+                    "norms and sums; mixed-environment rows: FP32 energy, FP64 variance"}
+        out["mixed_bf16x6_split_var32"] = {
+            "value": round(n * args.steps / el7 / 1e6, 3), "ms_per_step": round(el7 / args.steps * 1e3, 4),
+            "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma,
+                                                binding.BF16X6_SPLIT | binding.VAR_FP32, tg, ref),
+            "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm7.items() if c},
+            "note": "the three-way BF16 energy pass with the variance through the FP32 factor on FP32 "
+                    "matrix cores (FLARE_VAR_FP32: the plain form's variance error, not FP64)"}
         if not args.no_huge:
             log("precision forms at ~16 M atoms ...")
             out["precision_16m"] = precision_16m(engine, torch, st, beta, sigma)
@@ -451,6 +548,7 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")
         out["cpu_baseline"] = cpu_baseline(st, beta, sigma)
+        out["cpu_oracle_tiny"] = oracle_tiny_run(beta, sigma)
     print(json.dumps(out), flush=True)
 
 

@@ -53,21 +53,28 @@ extern "C" {
 #define FLARE_E_UNSUPPORTED -9  /* model sizes this build has no kernels for                    */
 
 /* ---- arithmetic of the quadratic forms ---- */
-/* The two-part split forms (BF16, FP8) change the energy contraction d.beta.d of the
- * single-species rows (144-wide) only: the operands are split into a high and a low part
- * in a narrow format and recombined in FP32 accumulators. The three-way BF16 form splits
- * d, beta and L into three BF16 parts each (together the 24 significant bits of the FP32
- * value) and keeps six of the nine part products in both passes, so its error is that of
- * FP32 arithmetic. The variance d.Sigma.d is computed as |L^T d|^2
- * with the FP64 Cholesky factor L of each Sigma block (stored FP32), a sum of squares
- * that does not cancel, in every form when all Sigma blocks are positive definite (the
- * split forms require it; the FP32 form falls back to the full matrix otherwise). Norms
- * and per-structure sums stay FP64. Mixed-environment rows (544-wide) keep FP32 products
- * in all forms. */
+/* The split forms change the energy contraction d.beta.d of the single-species rows
+ * (144-wide): the two-part forms (BF16, FP8) split the operands into a high and a low part
+ * in a narrow format and recombine them in FP32 accumulators; the three-way BF16 form
+ * splits d and beta into three BF16 parts each (together the 24 significant bits of the
+ * FP32 value) and keeps six of the nine part products, so its error is that of FP32
+ * arithmetic. Mixed-environment rows (544-wide) keep FP32 energy products in all forms.
+ * The variance d.Sigma.d is computed as |L^T d|^2 with the FP64 Cholesky factor L of each
+ * Sigma block, a sum of squares, whenever all Sigma blocks are positive definite (the split
+ * forms require it; the FP32 form falls back to the full matrix otherwise): in the FP32
+ * form with L rounded to FP32 on FP32 matrix cores, in the split forms (all rows) with L in
+ * FP64 on the FP64 matrix cores, FP64 sums and an FP64 division by |d~|^2, so that a
+ * near-cancelling variance (an environment close to the sparse set of Eq. 2) keeps FP64
+ * accuracy in the form and only the FP32 rounding of the descriptors remains. Norms and
+ * per-structure sums are FP64 in the split forms. */
 #define FLARE_FP32        0  /* FP32 matrix cores, FP32 accumulation                          */
-#define FLARE_BF16_SPLIT  1  /* d and beta as BF16 hi + lo, three products per tile          */
-#define FLARE_FP8_SPLIT   2  /* OCP e4m3 hi + lo with power-of-two row and block scales      */
-#define FLARE_BF16X6_SPLIT 3 /* d, beta and L as three BF16 parts, six products: FP32 error  */
+#define FLARE_BF16_SPLIT  1  /* d and beta as BF16 hi + lo, three products; FP64 variance     */
+#define FLARE_FP8_SPLIT   2  /* OCP e4m3 hi + lo, power-of-two scales; FP64 variance          */
+#define FLARE_BF16X6_SPLIT 3 /* d and beta as three BF16 parts, six products (FP32 error);
+                                FP64 variance                                                  */
+#define FLARE_VAR_FP32   16  /* OR-ed with a split form: the variance through the FP32 factor
+                                on FP32 matrix cores (FP64 sums) as in the FP32 form, instead
+                                of FP64: faster, with the FP32 form's variance error           */
 
 /* ---- device status bits (flare_status) ---- */
 #define FLARE_FLAG_NONFINITE  1  /* a position was NaN/inf                                     */
@@ -94,15 +101,44 @@ const char* flare_strerror(int code);
  *   n_d = n_species*n_rad*(n_species*n_rad+1)/2 * (l_max+1).
  * This build has kernels for n_species = 2, n_rad = 8, l_max = 3 (n_d = 544); other
  * sizes return FLARE_E_UNSUPPORTED. precision: FLARE_FP32, FLARE_BF16_SPLIT,
- * FLARE_FP8_SPLIT or FLARE_BF16X6_SPLIT; the split forms need every 144 x 144
- * single-species block of Sigma positive definite (FLARE_E_ARG otherwise).
+ * FLARE_FP8_SPLIT or FLARE_BF16X6_SPLIT, a split form optionally | FLARE_VAR_FP32; the
+ * split forms need every 144 x 144 single-species block of Sigma positive definite
+ * (FLARE_E_ARG otherwise).
  * The library copies the matrices to device memory it owns. Runs on the current device.
  */
 int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, double r_cut,
                        const double* beta_host, const double* sigma_host, int precision);
+/*
+ * Create a model from a sparse set: the exact mapping of the sparse GP onto the quadratic
+ * forms (Section V.B, Eqs. 1-2). Kernel k_xi(d1, d2) = sigma^2 (d1 . d2)^xi; per central
+ * species s with sparse descriptors D_s [n_s][n_d] and weights alpha_s:
+ *   beta_s  = sigma^2 D_s^T diag(alpha_s) D_s                       (mean, xi = 2)
+ *   gamma_s = sigma^2 I - sigma^4 D_s^T K_s^-1 D_s,                  (variance, xi = 1)
+ *   K_s     = sigma^2 D_s D_s^T + noise I  (the sparse-set kernel matrix),
+ * so that d^T beta_s d and d^T gamma_s d equal the unmapped SGP mean and variance. The
+ * variance model is gamma (Sigma of flare_model_create). All of it is computed in FP64 on
+ * the current device (K_s by Cholesky, gamma_s = sigma^2 I - sigma^4 Y^T Y with
+ * Y = C^-1 D_s; no inverse is formed), then the model is created as by flare_model_create.
+ *   n_sparse_host  HOST int32 [n_species]: sparse environments of each central species
+ *   d_sparse       DEVICE FP64 [sum n_s][n_d]: normalised descriptors in the packed order of
+ *                  flare_model_create, species 0 first, then species 1
+ *   alpha          DEVICE FP64 [sum n_s], same order
+ *   signal_var     sigma^2 > 0;  noise >= 0 (added to the diagonal of K_s)
+ *   beta_out, gamma_out  optional DEVICE FP64 [n_species][n_d][n_d] copies (NULL = skip)
+ * SYNCHRONISING (runs on the default stream). Allocates device temporaries of
+ * (2 n_max^2 + n_max n_d + 4 n_d^2) doubles, n_max = max_s n_s. A species without sparse
+ * environments gets beta = 0 and gamma = sigma^2 I. Errors: FLARE_E_ARG (sizes, a kernel
+ * matrix that is not positive definite, or a gamma block without a Cholesky factor in a
+ * split precision form), FLARE_E_UNSUPPORTED, FLARE_E_OOM, FLARE_E_HIP.
+ */
+int flare_model_from_sparse_set(flare_model** out, int n_species, int n_rad, int l_max, double r_cut,
+                                const int32_t* n_sparse_host, const double* d_sparse, const double* alpha,
+                                double signal_var, double noise, int precision, double* beta_out,
+                                double* gamma_out);
 int flare_model_destroy(flare_model* model);
 /*
- * How the model evaluates: *precision as passed at creation; *variance_cholesky = 1 when
+ * How the model evaluates: *precision as passed at creation (form | FLARE_VAR_FP32);
+ * *variance_cholesky = 1 when
  * the variance is computed as |L^T d|^2 from the FP64 Cholesky factor L of every Sigma
  * block (all blocks positive definite; always so in the split forms), 0 when the FP32
  * form uses d^T Sigma d with the full matrix. Either pointer may be NULL. HOST pointers.
@@ -227,6 +263,25 @@ int flare_virial_noalloc(flare_state* state, double* virial_struct);
  *   sigma_max             DEVICE FP32 [n_struct] largest sigma per cell (NULL = skip)
  */
 int flare_variance(flare_state* state, float* var_atom, float* sigma_atom, float* sigma_max);
+
+/*
+ * The mapped quadratic forms (Eqs. 1-2) of given vectors, by the same kernels as the
+ * descriptor path for the rows of one environment bucket:
+ *   e_r = d_r^T beta_s d_r,   V_r = d_r^T Sigma_s d_r      (no normalisation of d_r)
+ * bucket: 0 (H centre, H-only), 1 (Pt, H-only), 2 (H, Pt-only), 3 (Pt, Pt-only): d_r is
+ * the 144-wide block of that neighbour species (H-H block, or Pt-Pt block) and beta_s,
+ * Sigma_s the matching 144 x 144 blocks; 4 (H, mixed), 5 (Pt, mixed): the full 544 vector.
+ * Arithmetic as in flare_energy_forces for the model's precision: in the split forms V is
+ * |L^T d|^2 with the FP64 Cholesky factor on the FP64 matrix cores, so a near-cancelling
+ * V << sigma_max(Sigma) |d|^2 keeps FP64 accuracy of the form.
+ *   d_rows          DEVICE FP32 [n_rows][144 or 544]
+ *   e_out, var_out  DEVICE FP32 [n_rows]
+ * n_rows <= max_atoms of the state. Grows the state's row buffers when needed and
+ * overwrites its resident descriptors (call flare_descriptors again before
+ * flare_energy_forces). Not synchronising.
+ */
+int flare_quadratic_forms(flare_state* state, int bucket, int n_rows, const float* d_rows, float* e_out,
+                          float* var_out);
 
 /*
  * Uncertainty monitor of a production run (the paper's Section V.A active-learning

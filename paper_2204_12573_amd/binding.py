@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
 OK, E_ARG, E_SPECIES, E_BOX, E_CAPACITY, E_NONFINITE, E_STALE, E_OOM, E_HIP, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 FP32, BF16_SPLIT, FP8_SPLIT, BF16X6_SPLIT = 0, 1, 2, 3
+VAR_FP32 = 16          # with a split form: the variance through the FP32 factor
 FLAG_NONFINITE, FLAG_SPECIES, FLAG_DISPLACED, FLAG_UNCERTAIN = 1, 2, 4, 8
 
 
@@ -36,6 +37,7 @@ SIGNATURES = {
     "flare_last_error": (ctypes.c_char_p, []),
     "flare_strerror": (ctypes.c_char_p, [_i]),
     "flare_model_create": (_i, [ctypes.POINTER(_p), _i, _i, _i, _d, _p, _p, _i]),
+    "flare_model_from_sparse_set": (_i, [ctypes.POINTER(_p), _i, _i, _i, _d, _p, _p, _p, _d, _d, _i, _p, _p]),
     "flare_model_destroy": (_i, [_p]),
     "flare_descriptor_dim": (_i, [_p, ctypes.POINTER(_i)]),
     "flare_state_create": (_i, [ctypes.POINTER(_p), _p, _i, _ll, _p]),
@@ -50,6 +52,7 @@ SIGNATURES = {
     "flare_virial_noalloc": (_i, [_p, _p]),
     "flare_model_info": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "flare_variance": (_i, [_p, _p, _p, _p]),
+    "flare_quadratic_forms": (_i, [_p, _i, _i, _p, _p, _p]),
     "flare_memory_bytes": (_i, [_p, _p, ctypes.POINTER(_ll)]),
     "flare_md_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
     "flare_md_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),

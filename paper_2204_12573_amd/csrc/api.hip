@@ -181,6 +181,21 @@ void bf16x3_fragments(const std::vector<double>& M, uint16_t* out /* [5][9][3][6
         }
 }
 
+// FP64 fragments of an n x n lower-triangular factor L (row-major) for
+// v_mfma_f64_16x16x4_f64 B operands: [cb][kc][t 4][lane 64], element
+// L[16 kc + 4 (lane / 16) + t][16 cb + lane % 16] (blocks with kc < cb are zero).
+std::vector<double> f64_fragments(const std::vector<double>& L, int n) {
+  const int nb = n / 16;
+  std::vector<double> f((size_t)nb * nb * 4 * 64);
+  for (int cb = 0; cb < nb; ++cb)
+    for (int kc = 0; kc < nb; ++kc)
+      for (int t = 0; t < 4; ++t)
+        for (int lane = 0; lane < 64; ++lane)
+          f[(((size_t)cb * nb + kc) * 4 + t) * 64 + lane] =
+              L[(size_t)(kc * 16 + 4 * (lane / 16) + t) * n + cb * 16 + lane % 16];
+  return f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -212,14 +227,19 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
     set_error("this build has kernels for n_species=2, n_rad=8, l_max=3 only");
     return FLARE_E_UNSUPPORTED;
   }
-  if (precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT && precision != FLARE_FP8_SPLIT &&
-      precision != FLARE_BF16X6_SPLIT) {
-    set_error("precision must be FLARE_FP32, FLARE_BF16_SPLIT, FLARE_FP8_SPLIT or FLARE_BF16X6_SPLIT");
+  const int flags = precision;
+  precision &= ~FLARE_VAR_FP32;
+  if ((precision != FLARE_FP32 && precision != FLARE_BF16_SPLIT && precision != FLARE_FP8_SPLIT &&
+       precision != FLARE_BF16X6_SPLIT) || flags == (FLARE_FP32 | FLARE_VAR_FP32)) {
+    set_error("precision must be FLARE_FP32, or FLARE_BF16_SPLIT, FLARE_FP8_SPLIT or FLARE_BF16X6_SPLIT "
+              "(optionally | FLARE_VAR_FP32)");
     return FLARE_E_UNSUPPORTED;
   }
   flare_model* m = new (std::nothrow) flare_model();
   if (!m) return FLARE_E_OOM;
   m->precision = precision;
+  m->flags = flags;
+  m->var64 = precision != FLARE_FP32 && !(flags & FLARE_VAR_FP32);
   m->r_cut = r_cut;
   CHK(hipGetDevice(&m->device));
   // descriptor block of each bucket inside the packed 544 vector
@@ -311,6 +331,25 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
       }
     }
   }
+  if (m->var64) {
+    // FP64 fragments of the factors for the variance of the split forms
+    for (int b = 0; b < 4; ++b) {
+      std::vector<double> f = f64_fragments(L1[b], ND1);
+      const int rc = upload((void**)&m->L64[b], f.data(), f.size() * sizeof(double));
+      if (rc != FLARE_OK) {
+        flare_model_destroy(m);
+        return rc;
+      }
+    }
+    for (int s = 0; s < NS; ++s) {
+      std::vector<double> f = f64_fragments(Lx[s], ND);
+      const int rc = upload((void**)&m->Lx64[s], f.data(), f.size() * sizeof(double));
+      if (rc != FLARE_OK) {
+        flare_model_destroy(m);
+        return rc;
+      }
+    }
+  }
   if (precision == FLARE_BF16X6_SPLIT) {
     for (int b = 0; b < 4; ++b) {
       const int s = b & 1;
@@ -318,11 +357,7 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
       std::vector<double> beta = sub_block(beta_host + (size_t)s * ND * ND, st, ND1);
       std::vector<uint16_t> frag((size_t)5 * ncb * 3 * 64 * 8);
       bf16x3_fragments(beta, frag.data());
-      int rc = upload((void**)&m->W6[b], frag.data(), frag.size() * sizeof(uint16_t));
-      if (rc == FLARE_OK) {
-        bf16x3_fragments(L1[b], frag.data());      // B[k][n] = L[k][n], lower-triangular
-        rc = upload((void**)&m->L6[b], frag.data(), frag.size() * sizeof(uint16_t));
-      }
+      const int rc = upload((void**)&m->W6[b], frag.data(), frag.size() * sizeof(uint16_t));
       if (rc != FLARE_OK) {
         flare_model_destroy(m);
         return rc;
@@ -383,7 +418,7 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
 
 int flare_model_info(const flare_model* m, int* precision, int* variance_cholesky) {
   ARG(m, "null model");
-  if (precision) *precision = m->precision;
+  if (precision) *precision = m->flags;
   if (variance_cholesky) *variance_cholesky = m->vchol ? 1 : 0;
   return FLARE_OK;
 }
@@ -397,10 +432,12 @@ int flare_model_destroy(flare_model* m) {
     if (m->Wb[b]) (void)hipFree(m->Wb[b]);
     if (m->W8[b]) (void)hipFree(m->W8[b]);
     if (m->W6[b]) (void)hipFree(m->W6[b]);
-    if (m->L6[b]) (void)hipFree(m->L6[b]);
+    if (m->L64[b]) (void)hipFree(m->L64[b]);
   }
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 2; ++k) {
     if (m->Lx[k]) (void)hipFree(m->Lx[k]);
+    if (m->Lx64[k]) (void)hipFree(m->Lx64[k]);
+  }
   delete m;
   return FLARE_OK;
 }
@@ -435,6 +472,7 @@ static void free_state(flare_state* s) {
   s->Gx.release();
   s->Yx.release();
   s->Px.release();
+  s->Px64.release();
   s->d_tasks.release();
   s->d_first_task.release();
   s->red_e.release();
@@ -773,6 +811,36 @@ int flare_variance(flare_state* s, float* var_atom, float* sigma_atom, float* si
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, nullptr, nullptr, nullptr, nullptr, var_atom, sigma_atom);
     reduce_cells(s, nullptr, sigma_max);
+  }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_quadratic_forms(flare_state* s, int bucket, int n_rows, const float* d_rows, float* e_out,
+                          float* var_out) {
+  ARG(s, "null state");
+  ARG(bucket >= 0 && bucket < NBUCKET, "bucket must be 0..5");
+  ARG(n_rows >= 0 && n_rows <= s->max_atoms, "n_rows must be in [0, max_atoms]");
+  ARG(n_rows == 0 || (d_rows && e_out && var_out), "null device array");
+  const int w = bucket_width(bucket);
+  const size_t rows = (size_t)(n_rows + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+  // the resident descriptors of the last flare_descriptors call are overwritten
+  s->have_desc = false;
+  s->v_gen = s->g_gen = s->w_gen = -1;
+  if (n_rows == 0) return FLARE_OK;
+  CHK(s->e_row.reserve(rows + 1));
+  CHK(s->v_row.reserve(rows + 1));
+  if (w == ND1) {
+    CHK(s->G1.reserve(rows * ND1 + 64));
+    forms_given_144(s, bucket, n_rows, d_rows, e_out, var_out);
+  } else {
+    CHK(s->Dx.reserve(rows * ND + 64));
+    CHK(s->Yx.reserve(rows * ND + 64));
+    CHK(s->Gx.reserve(rows * ND + 64));
+    CHK(s->Px.reserve(rows * 4 + 64));
+    CHK(s->Px64.reserve(rows * 9 + 64));
+    const int e = forms_given_544(s, bucket, n_rows, d_rows, e_out, var_out);
+    if (e) CHK((hipError_t)e);
   }
   CHK(hipGetLastError());
   return FLARE_OK;

@@ -47,7 +47,10 @@ struct FusedArgs {
   const uint64_t* W8[4]; // FP8 split form: s_b beta as [ks 5][cb 9][hi/lo' 2][lane 64] x 8 e4m3
   float bscale[4];       // FP8 split form: s_b per bucket (a power of two)
   const uint4* W6[4];    // three-way BF16 form: beta as [ks 5][cb 9][part 3][lane 64] x 8 bf16
-  const uint4* L6[4];    // three-way BF16 form: L, same layout
+  const double* L64[4];  // split forms: the Cholesky factor L in FP64, [cb 9][kc 9][t 4][lane 64]
+  const float* D_in;     // optional [rows][144] given vectors (replace the descriptor phase; no
+                         // normalisation: the forms are those of the vectors as given)
+  int n_given;           // with D_in: rows 0 .. n_given - 1 are the given vectors
   int mode;              // bit 0: energy + gradient (beta), bit 1: variance (Sigma)
   int vchol;             // part 1 of Wf holds the Cholesky factor L: V = |L^T d|^2
   float* G;              // [tiles][144][128]: g, when the forces are not formed here
@@ -216,8 +219,7 @@ __device__ __forceinline__ void mfma_pass_bf16(const float* As, const uint4* __r
 // (exact products, FP32 accumulation); the dropped x1 w2 + x2 w1 + x2 w2 are below
 // 2^-23 |x||w|, the size of an FP32 rounding. K = 144 runs as five 32-wide steps
 // as in the two-way form; column blocks go in groups of three so that the six products
-// of a block are five other MFMAs apart. TRI: W = L lower-triangular, the blocks with
-// 16 j > 32 ks + 31 vanish.
+// of a block are five other MFMAs apart.
 // x0 = bf16(v), x1 = bf16(v - x0), x2 = v - x0 - x1: the last remainder has at most 8
 // significant bits, so its BF16 pattern is the upper half of its FP32 pattern (exact)
 __device__ __forceinline__ void split8x3(const float4 (&u)[2], bf8& x0, bf8& x1, bf8& x2) {
@@ -249,16 +251,10 @@ __device__ __forceinline__ void load_a8(const float* As, int wave, int l16, int 
   }
 }
 
-// Steps (ks, jg) in order; with TRI only the groups with 3 jg <= 2 ks + 1. One register
-// buffer of B fragments: the products run B part 2 first and part 0 last, and each part's
-// fragments for the next step are loaded as soon as its last product here is issued; the
-// next K step's A values are loaded at the start of a K step's last group.
-template <bool TRI>
-__host__ __device__ constexpr bool x6_active(int ks, int jg) {
-  return !TRI || 3 * jg <= 2 * ks + 1;
-}
-
-template <bool TRI>
+// Steps (ks, jg) in order. One register buffer of B fragments: the products run B part 2
+// first and part 0 last, and each part's fragments for the next step are loaded as soon as
+// its last product here is issued; the next K step's A values are loaded at the start of a
+// K step's last group.
 __device__ __forceinline__ void mfma_pass_bf16x6(const float* As, const uint4* __restrict__ W, int wave,
                                                  int lane, f4 (&acc)[2][NCB]) {
   const int l16 = lane & 15, grp = lane >> 4;
@@ -274,7 +270,7 @@ __device__ __forceinline__ void mfma_pass_bf16x6(const float* As, const uint4* _
   for (int jj = 0; jj < 3; ++jj)
 #pragma unroll
     for (int pt = 0; pt < 3; ++pt)
-      if (!TRI || jj <= 1) b[jj][pt] = __builtin_bit_cast(bf8, Wp[(jj * 3 + pt) * 64]);
+      b[jj][pt] = __builtin_bit_cast(bf8, Wp[(jj * 3 + pt) * 64]);
 #pragma unroll
   for (int i = 0; i < 2; ++i) load_a8(As, wave, l16, grp, i, 0, araw[i]);
 #pragma unroll
@@ -283,9 +279,8 @@ __device__ __forceinline__ void mfma_pass_bf16x6(const float* As, const uint4* _
     for (int i = 0; i < 2; ++i) split8x3(araw[i], a[0][i], a[1][i], a[2][i]);
 #pragma unroll
     for (int jg = 0; jg < NCB / 3; ++jg) {
-      if (!x6_active<TRI>(ks, jg)) continue;
-      // the next active step
-      const bool same = jg + 1 < NCB / 3 && x6_active<TRI>(ks, jg + 1);
+      // the next step
+      const bool same = jg + 1 < NCB / 3;
       const int nks = same ? ks : ks + 1, njg = same ? jg + 1 : 0;
       const bool more = nks < NKS;
       if (more && !same) {
@@ -294,15 +289,13 @@ __device__ __forceinline__ void mfma_pass_bf16x6(const float* As, const uint4* _
       }
 #define X6_PROD(PA, PB)                                                                       \
   _Pragma("unroll") for (int jj = 0; jj < 3; ++jj) {                                          \
-    if (TRI && 3 * jg + jj > 2 * ks + 1) continue;                                            \
     _Pragma("unroll") for (int i = 0; i < 2; ++i) acc[i][3 * jg + jj] =                       \
         __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA][i], b[jj][PB], acc[i][3 * jg + jj], 0, 0, 0); \
   }
 #define X6_NEXT(PT)                                                                           \
   if (more) {                                                                                 \
     _Pragma("unroll") for (int jj = 0; jj < 3; ++jj)                                          \
-      if (!TRI || 3 * njg + jj <= 2 * nks + 1)                                                \
-        b[jj][PT] = __builtin_bit_cast(bf8, Wp[((nks * NCB + 3 * njg + jj) * 3 + PT) * 64]);   \
+      b[jj][PT] = __builtin_bit_cast(bf8, Wp[((nks * NCB + 3 * njg + jj) * 3 + PT) * 64]);     \
   }
       X6_PROD(0, 2)
       X6_NEXT(2)
@@ -455,6 +448,80 @@ __device__ __forceinline__ void row_sumsq(const f4 (&acc)[2][NCB], float (&out)[
     }
 }
 
+// Variance of the split forms in FP64: Z~ = D~ L on v_mfma_f64_16x16x4_f64 (lane (m, q)
+// supplies A[m][k] and B[k][n = m] for k = 4q + t of the chunk, as in the FP32 pass; D~ is
+// exact in FP64, L is the FP64 Cholesky factor), V~ = |Z~|^2 summed in FP64. The FP64
+// instruction returns row q + 4 r of the block in accumulator r of lane (n, q) (the FP32
+// one row 4 q + r), so out[i][r] belongs to row 16 i + q + 4 r. A near-
+// cancelling d^T Sigma d (an environment close to the sparse set: V << sigma^2 |d|^2) then
+// keeps FP64 accuracy in the form itself; only the rounding of d~ remains. Column blocks go
+// in three groups of three (six independent accumulators per k-step); the group's chunks
+// start at its first block (L[k][n] = 0 for k < n) and the B fragments of the next chunk
+// load while the current one runs.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void var_pass_f64(const float* As, const double* __restrict__ L, int wave, int lane,
+                                             double (&out)[2][4]) {
+  const int l16 = lane & 15, grp = lane >> 4;
+  double ss[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ss[i][r] = 0.0;
+  const double* Lp = L + lane;
+#pragma unroll
+  for (int jg = 0; jg < 3; ++jg) {
+    d4 acc[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) acc[i][jj] = d4{0.0, 0.0, 0.0, 0.0};
+    double bA[3][4], bB[3][4];
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (jj == 0) bA[jj][t] = Lp[(((3 * jg + jj) * NKC + 3 * jg) * 4 + t) * 64];
+#pragma unroll
+    for (int kc = 3 * jg; kc < NKC; ++kc) {
+      const bool odd = (kc - 3 * jg) & 1;
+      double (&cur)[3][4] = odd ? bB : bA;
+      double (&nxt)[3][4] = odd ? bA : bB;
+      if (kc + 1 < NKC) {
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          if (3 * jg + jj <= kc + 1)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) nxt[jj][t] = Lp[(((3 * jg + jj) * NKC + kc + 1) * 4 + t) * 64];
+      }
+      float4 a[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const float4*>(&As[(wave * 32 + i * 16 + l16) * AS + kc * 16 + 4 * grp]);
+      const float av[2][4] = {{a[0].x, a[0].y, a[0].z, a[0].w}, {a[1].x, a[1].y, a[1].z, a[1].w}};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+          if (3 * jg + jj > kc) continue;     // block above the diagonal of L
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[i][t], cur[jj][t], acc[i][jj], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ss[i][r] = fma(acc[i][jj][r], acc[i][jj][r], ss[i][r]);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[i][r] = sum16d(ss[i][r]);
+}
+
 // Row-dots Y_row . d_row of the 8 rows a lane touches; all 16 lanes of a group get the sum.
 __device__ __forceinline__ void row_dots(const float* As, const f4 (&acc)[2][NCB], int wave, int lane,
                                          float (&out)[2][4]) {
@@ -471,36 +538,50 @@ __device__ __forceinline__ void row_dots(const float* As, const f4 (&acc)[2][NCB
     }
 }
 
+// Atom of a row (-1: padding); for given vectors (GIVEN) row r < n_given is "atom" r.
+template <bool GIVEN>
+__device__ __forceinline__ int atom_of(const FusedArgs& a, int row) {
+  return GIVEN ? (row < a.n_given ? row : -1) : a.aor[row];
+}
+
 // Model operands of the bucket that holds rows [row0, row0 + 128).
 struct TileModel {
   const float4* Wf;
   const uint4* Wb;
   const uint64_t* W8;
   const uint4* W6;
-  const uint4* L6;
+  const double* L64;
   float bsc;
 };
 __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
-  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.W6[0], a.L6[0], a.bscale[0]};
+  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.W6[0], a.L64[0], a.bscale[0]};
 #pragma unroll
   for (int k = 1; k < 4; ++k)   // static indexing keeps the argument arrays out of scratch
     if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k])
-      m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.W6[k], a.L6[k], a.bscale[k]};
+      m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.W6[k], a.L64[k], a.bscale[k]};
   return m;
 }
 
+// Per-row scalars of the tile: |d~| (FP32), |d~|^2 in FP64 (split forms), the FP8 row scale.
+struct RowScalars {
+  float* nrm;
+  double* nrm2;
+  float* rsc;
+};
+
 // 1. descriptors of the tile's rows into the LDS tile (thread t of 256: row t/2, half t&1);
-// the densities are left in c for the adjoint phase of the same rows.
-template <int PREC>
-__device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float* nrm_s, float* rsc_s, int row0,
+// the densities are left in c for the adjoint phase of the same rows. With given
+// descriptors (D_in) the lane pair copies its row instead and c stays zero.
+template <int PREC, bool GIVEN>
+__device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, const RowScalars& rs, int row0,
                                            int t, float (&c)[NR][NQ]) {
   const int rl = t >> 1, h = t & 1;
-  const int i = a.aor[row0 + rl];
+  const int i = atom_of<GIVEN>(a, row0 + rl);
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) c[n][q] = 0.f;
-  if (i >= 0) accumulate_half(a.v, row0 + rl, h, c);
+  if (i >= 0 && !GIVEN) accumulate_half(a.v, row0 + rl, h, c);
   // one B2 pass: the unnormalised d~ goes into the tile; 1/|d~| is applied in the
   // epilogue (Y is linear in the row, so Y(d) = Y(d~)/|d~|)
   // |d~|^2: FP64 in the split forms (their norms stay FP64), FP32 in the FP32 form (144
@@ -508,49 +589,83 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, float*
   typedef typename std::conditional<PREC == FLARE_FP32, float, double>::type NormT;
   NormT nrm2 = 0;
   float amax = 0.f;     // max |d~_k| (FP8 row scale)
-  float* rowp = As + rl * AS + 2 * h;
-  int k = 0;
+  if (GIVEN) {
+    // lane h copies components 72 h .. 72 h + 71 of its row (zeros for padding rows)
+    const float4* src = reinterpret_cast<const float4*>(a.D_in + (size_t)(row0 + rl) * ND1 + 72 * h);
+    float* dst = As + rl * AS + 72 * h;
 #pragma unroll
-  for (int na = 0; na < NR; ++na) {
+    for (int q = 0; q < 18; ++q) {
+      const float4 v = i >= 0 ? src[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      nrm2 += (NormT)(v.x * v.x + v.y * v.y) + (NormT)(v.z * v.z + v.w * v.w);
+      if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+      *reinterpret_cast<float4*>(dst + 4 * q) = v;
+    }
+  } else {
+    float* rowp = As + rl * AS + 2 * h;
+    int k = 0;
 #pragma unroll
-    for (int nb = na; nb < NR; ++nb) {
-      const float2 mine = b2_half(c[na], c[nb], h);    // this lane's two components
-      nrm2 += (NormT)(mine.x * mine.x + mine.y * mine.y);
-      if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
-      *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
-      ++k;
+    for (int na = 0; na < NR; ++na) {
+#pragma unroll
+      for (int nb = na; nb < NR; ++nb) {
+        const float2 mine = b2_half(c[na], c[nb], h);    // this lane's two components
+        nrm2 += (NormT)(mine.x * mine.x + mine.y * mine.y);
+        if (PREC == FLARE_FP8_SPLIT) amax = fmaxf(amax, fmaxf(fabsf(mine.x), fabsf(mine.y)));
+        *reinterpret_cast<float2*>(rowp + 4 * k) = mine;
+        ++k;
+      }
     }
   }
   if (PREC == FLARE_FP32) nrm2 += xor1((float)nrm2);    // the row's other half
   else nrm2 += xor1d((double)nrm2);
+  if (GIVEN) nrm2 = i >= 0 ? 1 : 0;     // given vectors: no normalisation
   const float nrm = (float)sqrt(nrm2);   // sqrtf in the FP32 form
   if (PREC == FLARE_FP8_SPLIT) {
     amax = fmaxf(amax, xor1(amax));
     int ex = 0;
     frexpf(amax > 0.f ? amax : 1.f, &ex);      // amax = f 2^ex, f in [0.5, 1)
-    if (h == 0) rsc_s[rl] = ldexpf(1.f, 4 - ex);   // |s_r d~| < 16
+    if (h == 0) rs.rsc[rl] = ldexpf(1.f, 4 - ex);   // |s_r d~| < 16
   }
   if (h == 0) {
-    nrm_s[rl] = nrm;
+    rs.nrm[rl] = nrm;
+    if (PREC != FLARE_FP32) rs.nrm2[rl] = (double)nrm2;
     if (i >= 0) a.nrm[i] = nrm;
   }
 }
 
 // 2/3. quadratic forms and epilogue on a complete descriptor tile; leaves g in the tile
 // when the energy pass runs. Wave w of the 4 owns rows 32w .. 32w + 31.
-template <int PREC>
-__device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const float* nrm_s,
-                                            const float* rsc_s, int row0, int t, const TileModel& tm) {
+// V64: the variance in FP64 (split forms); otherwise through the FP32 factor (or the full
+// Sigma in the FP32 form without a factor).
+template <int PREC, bool V64, bool GIVEN>
+__device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const RowScalars& rs, int row0, int t,
+                                            const TileModel& tm) {
   const int lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, grp = lane >> 4;
+  const float* nrm_s = rs.nrm;
+  const float* rsc_s = rs.rsc;
   f4 acc[2][NCB];
   float dots[2][4];
-  if (a.mode & 2) {
-    if (PREC == FLARE_BF16X6_SPLIT) {
-      // Z = D L from the three-way BF16 parts of D and L
-      mfma_pass_bf16x6<true>(As, tm.L6, wave, lane, acc);
-      row_sumsq<true>(acc, dots);
-    } else if (PREC != FLARE_FP32 || a.vchol) {
+  if ((a.mode & 2) && V64) {
+    // split forms: V = |L^T d~|^2 / |d~|^2 with FP64 products, sums and division
+    double vv[2][4];
+    var_pass_f64(As, tm.L64, wave, lane, vv);
+    if (l16 == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rl = wave * 32 + i * 16 + grp + 4 * r;     // FP64 accumulator layout
+          const int atom = atom_of<GIVEN>(a, row0 + rl);
+          const double n2 = rs.nrm2[rl];
+          if (atom >= 0) {
+            const float v = n2 > 0.0 ? (float)(vv[i][r] / n2) : 0.f;
+            a.v_int[atom] = v;
+            a.v_row[row0 + rl] = v;
+          }
+        }
+    }
+  } else if (a.mode & 2) {
+    if (a.vchol) {
       // Z = D L on FP32 cores, L lower-triangular
       mfma_pass<1, true>(As, tm.Wf, wave, lane, acc);
       row_sumsq<PREC != FLARE_FP32>(acc, dots);
@@ -564,7 +679,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int rl = wave * 32 + i * 16 + 4 * grp + r;
-          const int atom = a.aor[row0 + rl];
+          const int atom = atom_of<GIVEN>(a, row0 + rl);
           const float nv = nrm_s[rl];
           if (atom >= 0) {
             const float v = nv > 0.f ? dots[i][r] / (nv * nv) : 0.f;
@@ -578,7 +693,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
     if (PREC == FLARE_BF16_SPLIT) {
       mfma_pass_bf16<0>(As, tm.Wb, wave, lane, acc);
     } else if (PREC == FLARE_BF16X6_SPLIT) {
-      mfma_pass_bf16x6<false>(As, tm.W6, wave, lane, acc);
+      mfma_pass_bf16x6(As, tm.W6, wave, lane, acc);
     } else if (PREC == FLARE_FP8_SPLIT) {
       mfma_pass_fp8(As, rsc_s, tm.W8, wave, lane, acc);
       // undo the power-of-two scales: Y~ = acc / (16 s_r s_b), exact
@@ -599,7 +714,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rl = wave * 32 + i * 16 + 4 * grp + r;
-        const int atom = a.aor[row0 + rl];
+        const int atom = atom_of<GIVEN>(a, row0 + rl);
         const float nv = nrm_s[rl];
         const float inv2 = nv > 0.f ? 1.f / (nv * nv) : 0.f;
         const float e = dots[i][r] * inv2;        // e = Y~ . d~ / |d~|^2
@@ -622,24 +737,26 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 __device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t,
                                               float (&c)[NR][NQ]) {
   const int rl = t >> 1, h = t & 1;
-  if (a.aor[row0 + rl] < 0) return;
+  if (atom_of<false>(a, row0 + rl) < 0) return;     // descriptor rows only
   u_transform_half(As + rl * AS, 1, h, c);
   adjoint_pairs_half(a.v, row0 + rl, h, c, a.f_own);
 }
 
 // One tile per work-group, phases in sequence (descriptor export, energies or variances
 // without forces: g leaves as G[tile][k][row] for the separate adjoint kernel).
-template <int PREC>
+template <int PREC, bool V64, bool GIVEN>
 __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) float As[FR * AS];
   __shared__ float nrm_s[FR];
+  __shared__ double nrm2_s[FR];   // split forms: |d~|^2 in FP64
   __shared__ float rsc_s[FR];     // FP8 split form: power-of-two row scale s_r
+  const RowScalars rs{nrm_s, nrm2_s, rsc_s};
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const int t = threadIdx.x;
   {
     float c[NR][NQ];
-    desc_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, c);
+    desc_phase<PREC, GIVEN>(a, As, rs, row0, t, c);
   }
   __syncthreads();
   if (a.D_out) {
@@ -649,7 +766,7 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
       a.D_out[(size_t)(row0 + r) * ND1 + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
     }
   }
-  forms_phase<PREC>(a, As, nrm_s, rsc_s, row0, t, tile_model(a, row0));
+  forms_phase<PREC, V64, GIVEN>(a, As, rs, row0, t, tile_model(a, row0));
   if (a.mode & 1) {
     __syncthreads();
     float* G = a.G + (size_t)tile * ND1 * FR;
@@ -681,25 +798,25 @@ __device__ __forceinline__ void wave_phase_fence() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int PREC>
+template <int PREC, bool V64>
 __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub) {
   __shared__ __attribute__((aligned(16))) float As[WW][WR * AS];
   __shared__ float nrm_s[WW][WR];
+  __shared__ double nrm2_s[WW][WR];
   __shared__ float rsc_s[WW][WR];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = gridDim.x * WW;
   float* A = As[wv];
-  float* ns = nrm_s[wv];
-  float* rs = rsc_s[wv];
+  const RowScalars rs{nrm_s[wv], nrm2_s[wv], rsc_s[wv]};
   for (int st = blockIdx.x * WW + wv; st < nsub; st += nw) {
     const int row0 = st * WR;
     float c[NR][NQ];
-    desc_phase<PREC>(a, A, ns, rs, row0, lane, c);
+    desc_phase<PREC, false>(a, A, rs, row0, lane, c);
     wave_phase_fence();
     // the matrix-core phase issues first when both waves of a SIMD are ready: its MFMAs
     // keep the shared datapath busy for 32 cycles each, the other wave fills the gaps
     __builtin_amdgcn_s_setprio(1);
-    forms_phase<PREC>(a, A, ns, rs, row0, lane, tile_model(a, row0));
+    forms_phase<PREC, V64, false>(a, A, rs, row0, lane, tile_model(a, row0));
     __builtin_amdgcn_s_setprio(0);
     wave_phase_fence();
     adjoint_phase(a, A, row0, lane, c);
@@ -711,6 +828,55 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
 
 void make_fp8_fragments(const float* vals, int groups, uint64_t* out) {
   k_fp8_fragments<<<(groups * 64 + 255) / 256, 256>>>(vals, groups, out);
+}
+
+// Launch k_fused144 (one tile per work-group) for the model's arithmetic.
+template <bool GIVEN>
+void launch_tiles(const flare_model* m, const FusedArgs& a, int ntiles, hipStream_t st) {
+  const bool v64 = m->var64;
+  if (m->precision == FLARE_BF16_SPLIT) {
+    if (v64) k_fused144<FLARE_BF16_SPLIT, true, GIVEN><<<ntiles, FT, 0, st>>>(a);
+    else k_fused144<FLARE_BF16_SPLIT, false, GIVEN><<<ntiles, FT, 0, st>>>(a);
+  } else if (m->precision == FLARE_BF16X6_SPLIT) {
+    if (v64) k_fused144<FLARE_BF16X6_SPLIT, true, GIVEN><<<ntiles, FT, 0, st>>>(a);
+    else k_fused144<FLARE_BF16X6_SPLIT, false, GIVEN><<<ntiles, FT, 0, st>>>(a);
+  } else if (m->precision == FLARE_FP8_SPLIT) {
+    if (v64) k_fused144<FLARE_FP8_SPLIT, true, GIVEN><<<ntiles, FT, 0, st>>>(a);
+    else k_fused144<FLARE_FP8_SPLIT, false, GIVEN><<<ntiles, FT, 0, st>>>(a);
+  } else {
+    k_fused144<FLARE_FP32, false, GIVEN><<<ntiles, FT, 0, st>>>(a);
+  }
+}
+
+// Quadratic forms of given 144-wide vectors (rows 0 .. n-1) with the model block of single-
+// species bucket `bucket`: e_r = d_r^T beta d_r, v_r = d_r^T Sigma d_r, by the same forms
+// phase as the descriptor path. Per-row scratch: the state's e_row, v_row, G1 and nrm.
+void forms_given_144(flare_state* s, int bucket, int n, const float* d, float* e, float* v) {
+  const int rows = (n + FR - 1) / FR * FR;
+  if (rows == 0) return;
+  const flare_model* m = s->model;
+  FusedArgs a{};
+  a.aor = nullptr;
+  a.n_given = n;
+  a.D_in = d;
+  a.nbk = 1;
+  a.row0[0] = 0;
+  a.row1[0] = rows;
+  a.Wf[0] = reinterpret_cast<const float4*>(m->Wf[bucket]);
+  a.Wb[0] = reinterpret_cast<const uint4*>(m->Wb[bucket]);
+  a.W8[0] = m->W8[bucket];
+  a.W6[0] = reinterpret_cast<const uint4*>(m->W6[bucket]);
+  a.L64[0] = m->L64[bucket];
+  a.bscale[0] = m->beta_scale[bucket];
+  a.vchol = m->vchol ? 1 : 0;
+  a.G = s->G1.p;
+  a.nrm = s->nrm;
+  a.e_int = e;
+  a.v_int = v;
+  a.e_row = s->e_row.p;
+  a.v_row = s->v_row.p;
+  a.mode = 3;
+  launch_tiles<true>(m, a, rows / FR, s->stream);
 }
 
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
@@ -727,7 +893,7 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     a.Wb[k] = reinterpret_cast<const uint4*>(s->model->Wb[k]);
     a.W8[k] = s->model->W8[k];
     a.W6[k] = reinterpret_cast<const uint4*>(s->model->W6[k]);
-    a.L6[k] = reinterpret_cast<const uint4*>(s->model->L6[k]);
+    a.L64[k] = s->model->L64[k];
     a.bscale[k] = s->model->beta_scale[k];
   }
   a.vchol = s->model->vchol ? 1 : 0;
@@ -745,24 +911,24 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     // energies + forces: persistent work-groups, one per CU, waves independent
     const int nsub = s->rows1 / WR;
     const int grid = std::min(256, (nsub + WW - 1) / WW);
-    if (s->model->precision == FLARE_BF16_SPLIT)
-      k_fused144_w<FLARE_BF16_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
-    else if (s->model->precision == FLARE_BF16X6_SPLIT)
-      k_fused144_w<FLARE_BF16X6_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
-    else if (s->model->precision == FLARE_FP8_SPLIT)
-      k_fused144_w<FLARE_FP8_SPLIT><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
-    else
-      k_fused144_w<FLARE_FP32><<<grid, WW * 64, 0, s->stream>>>(a, nsub);
+    const flare_model* m = s->model;
+    const bool v64 = m->var64;
+    hipStream_t st = s->stream;
+    if (m->precision == FLARE_BF16_SPLIT) {
+      if (v64) k_fused144_w<FLARE_BF16_SPLIT, true><<<grid, WW * 64, 0, st>>>(a, nsub);
+      else k_fused144_w<FLARE_BF16_SPLIT, false><<<grid, WW * 64, 0, st>>>(a, nsub);
+    } else if (m->precision == FLARE_BF16X6_SPLIT) {
+      if (v64) k_fused144_w<FLARE_BF16X6_SPLIT, true><<<grid, WW * 64, 0, st>>>(a, nsub);
+      else k_fused144_w<FLARE_BF16X6_SPLIT, false><<<grid, WW * 64, 0, st>>>(a, nsub);
+    } else if (m->precision == FLARE_FP8_SPLIT) {
+      if (v64) k_fused144_w<FLARE_FP8_SPLIT, true><<<grid, WW * 64, 0, st>>>(a, nsub);
+      else k_fused144_w<FLARE_FP8_SPLIT, false><<<grid, WW * 64, 0, st>>>(a, nsub);
+    } else {
+      k_fused144_w<FLARE_FP32, false><<<grid, WW * 64, 0, st>>>(a, nsub);
+    }
     return;
   }
-  if (s->model->precision == FLARE_BF16_SPLIT)
-    k_fused144<FLARE_BF16_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
-  else if (s->model->precision == FLARE_BF16X6_SPLIT)
-    k_fused144<FLARE_BF16X6_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
-  else if (s->model->precision == FLARE_FP8_SPLIT)
-    k_fused144<FLARE_FP8_SPLIT><<<ntiles, FT, 0, s->stream>>>(a);
-  else
-    k_fused144<FLARE_FP32><<<ntiles, FT, 0, s->stream>>>(a);
+  launch_tiles<false>(s->model, a, ntiles, s->stream);
 }
 
 }  // namespace flare

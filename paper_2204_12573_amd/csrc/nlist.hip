@@ -629,6 +629,7 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   HIPCHK(s->Gx.reserve((size_t)rx * ND + 64));
   HIPCHK(s->Yx.reserve((size_t)rx * ND + 64));
   HIPCHK(s->Px.reserve((size_t)rx * 4 + 64));
+  if (s->model->var64) HIPCHK(s->Px64.reserve((size_t)rx * 9 + 64));
   HIPCHK(hipMemsetAsync(s->atom_of_row1.p, 0xff, (r1 + 1) * sizeof(int), st));
   HIPCHK(hipMemsetAsync(s->atom_of_rowx.p, 0xff, (rx + 1) * sizeof(int), st));
   if (n > 0) {

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
                                                       const float* __restrict__ D,
                                                       const float* __restrict__ Y,
                                                       const float* __restrict__ P,
-                                                      const int* __restrict__ aor,
+                                                      const int* __restrict__ aor, int n_given,
                                                       const float* __restrict__ nrm,
                                                       float* __restrict__ G,
                                                       float* __restrict__ e_int,
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= rows) return;
-  const int atom = aor[row];
+  const int atom = aor ? aor[row] : (row < n_given ? row : -1);   // no table: given vectors
   if (atom < 0) return;
   const float* p = P + (size_t)row * 4;
   const bool has_e = mode & 1, has_v = mode & 2;
@@ -241,14 +241,108 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
   for (int k = lane; k < ND; k += 64) g[k] = s2 * (y[k] - e * d[k]);
 }
 
+// Variance of the mixed rows in the split forms, in FP64: V_i = |L_s^T d_i|^2 with the FP64
+// Cholesky factor of Sigma_s on v_mfma_f64_16x16x4_f64 (exact products of the FP32 row and
+// the FP64 factor, FP64 sums), so the near-cancelling d^T Sigma d keeps FP64 accuracy in the
+// form. A wave owns 16 rows and a group of four column blocks of Z = D L: for every K
+// chunk from the group's first block (L[k][n] = 0 for k < n) lane (m, q) supplies
+// D[row m][16 kc + 4 q + t] and the fragments L[16 kc + 4 q + t][16 cb + m] (fragment order
+// [cb][kc][t][lane]); four independent accumulators per k-step. Accumulator r of lane
+// (n, q) holds row q + 4 r of the block (the FP64 instruction's layout). The group's sum of
+// squares per row goes to P64[row][group]; k_var544_finish adds the groups in a fixed order.
+constexpr int XCB = ND / 16;                 // 34 column blocks
+constexpr int XG = 4;                        // column blocks per wave
+constexpr int NXG = (XCB + XG - 1) / XG;     // 9 groups
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct VarArgs {
+  const float* D;          // [rows][544]
+  int rows;                // padded rows (a multiple of 64)
+  int split_row;           // rows >= split_row belong to the second bucket (Pt centre)
+  const double* L[2];      // per bucket: fragments of the factor
+  double* P64;             // [rows][NXG]
+};
+
+__global__ __launch_bounds__(256) void k_var544_f64(VarArgs q) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, grp = lane >> 4;
+  const int task = blockIdx.x * 4 + wave;        // (16-row block, column group)
+  const int rb = task / NXG, g = task % NXG;
+  const int row0 = rb * 16;
+  if (row0 >= q.rows) return;
+  const double* __restrict__ L = (row0 >= q.split_row ? q.L[1] : q.L[0]) + lane;
+  const float* __restrict__ drow = q.D + (size_t)(row0 + l16) * ND + 4 * grp;
+  d4 acc[XG];
+#pragma unroll
+  for (int u = 0; u < XG; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+  const int cb0 = g * XG;
+  for (int kc = cb0; kc < XCB; ++kc) {
+    const float4 a = *reinterpret_cast<const float4*>(drow + kc * 16);
+    const double av[4] = {(double)a.x, (double)a.y, (double)a.z, (double)a.w};
+    double b[XG][4];
+#pragma unroll
+    for (int u = 0; u < XG; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        b[u][t] = (cb0 + u < XCB && cb0 + u <= kc) ? L[(((size_t)(cb0 + u) * XCB + kc) * 4 + t) * 64] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < XG; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], b[u][t], acc[u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double ss = 0.0;
+#pragma unroll
+    for (int u = 0; u < XG; ++u) ss = fma(acc[u][r], acc[u][r], ss);
+    ss = sum16d(ss);
+    if (l16 == 0) q.P64[(size_t)(row0 + grp + 4 * r) * NXG + g] = ss;
+  }
+}
+
+// V of each mixed row from its group sums (fixed order), rounded to FP32 once.
+__global__ __launch_bounds__(256) void k_var544_finish(int rows, const double* __restrict__ P64,
+                                                       const int* __restrict__ aor, int n_given,
+                                                       float* __restrict__ v_int, float* __restrict__ v_row) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= rows) return;
+  const int atom = aor ? aor[row] : (row < n_given ? row : -1);
+  if (atom < 0) return;
+  double v = 0.0;
+#pragma unroll
+  for (int g = 0; g < NXG; ++g) v += P64[(size_t)row * NXG + g];
+  v_int[atom] = (float)v;
+  v_row[row] = (float)v;
+}
+
+void var544_f64(flare_state* s, const float* D, int rows, int split_row, const int* aor, int n_given,
+                float* v_int, float* v_row) {
+  VarArgs q{};
+  q.D = D;
+  q.rows = rows;
+  q.split_row = split_row;
+  q.L[0] = s->model->Lx64[0];
+  q.L[1] = s->model->Lx64[1];
+  q.P64 = s->Px64.p;
+  const int tasks = rows / 16 * NXG;
+  k_var544_f64<<<(tasks + 3) / 4, 256, 0, s->stream>>>(q);
+  k_var544_finish<<<(rows + 255) / 256, 256, 0, s->stream>>>(rows, s->Px64.p, aor, n_given, v_int, v_row);
+}
+
 }  // namespace
 
 // Quadratic forms of the mixed-environment rows (544-wide), split over four column tiles.
+// In the split forms the variance runs in FP64 (var544_f64) and the tiles cover beta only.
 void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
-  const int mode = (want_e ? 1 : 0) | (want_v ? 2 : 0);
   const int rows = s->rowsx;
-  if (!mode || rows == 0) return;
+  if ((!want_e && !want_v) || rows == 0) return;
   const flare_model* m = s->model;
+  if (want_v && m->var64) {
+    var544_f64(s, s->Dx.p, rows, s->bucket_row0[5], s->atom_of_rowx.p, 0, s->v_int, s->v_row.p + s->rows1);
+    want_v = false;
+    if (!want_e) return;
+  }
+  const int mode = (want_e ? 1 : 0) | (want_v ? 2 : 0);
   QArgs q{};
   q.mode = mode;
   q.nbk = 2;
@@ -270,8 +364,47 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   const int ntiles = 2 * parts;   // 272 columns per tile
   k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
   k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
-                                                        s->atom_of_rowx.p, s->nrm, s->Gx.p, s->e_int, s->v_int,
+                                                        s->atom_of_rowx.p, 0, s->nrm, s->Gx.p, s->e_int, s->v_int,
                                                         s->e_row.p + s->rows1, s->v_row.p + s->rows1);
+}
+
+// Quadratic forms of given 544-wide vectors (rows 0 .. n-1) with the model of mixed bucket
+// `bucket` (4: H centre, 5: Pt centre): e_r = d_r^T beta_s d_r, v_r = d_r^T Sigma_s d_r, by
+// the same kernels as the descriptor path. The vectors are copied into the state's padded
+// row buffer Dx (zeros past n); scratch: Yx, Px, Px64, Gx, e_row, v_row, nrm.
+int forms_given_544(flare_state* s, int bucket, int n, const float* d, float* e, float* v) {
+  const int rows = (n + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+  if (rows == 0) return 0;
+  const flare_model* m = s->model;
+  hipError_t err = hipMemcpyAsync(s->Dx.p, d, (size_t)n * ND * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
+  if (err == hipSuccess)
+    err = hipMemsetAsync(s->Dx.p + (size_t)n * ND, 0, (size_t)(rows - n) * ND * sizeof(float), s->stream);
+  if (err != hipSuccess) return (int)err;
+  // the rows of one bucket: the Pt-centre model from row split = 0 when bucket 5
+  const int split = bucket == 5 ? 0 : rows;
+  QArgs q{};
+  q.nbk = 1;
+  q.row0[0] = 0;
+  q.row1[0] = rows;
+  q.W[0] = m->W[bucket];
+  q.L[0] = m->Lx[bucket - 4];
+  q.sumsq = m->vchol ? 1 : 0;
+  q.D = s->Dx.p;
+  q.aor = nullptr;
+  q.Y = s->Yx.p;
+  q.P = s->Px.p;
+  int mode = 3;
+  if (m->var64) {
+    var544_f64(s, s->Dx.p, rows, split, nullptr, n, v, s->v_row.p);
+    mode = 1;
+  }
+  q.mode = mode;
+  if (mode == 1) q.W[0] = m->W[bucket];
+  const int ntiles = 2 * (mode == 3 ? 2 : 1);
+  k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
+  k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p, nullptr, n,
+                                                        s->nrm, s->Gx.p, e, v, s->e_row.p, s->v_row.p);
+  return 0;
 }
 
 }  // namespace flare

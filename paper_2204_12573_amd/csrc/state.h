@@ -80,7 +80,9 @@ struct RedTask {
 
 struct flare_model {
   int device = 0;
-  int precision = FLARE_FP32;
+  int precision = FLARE_FP32;     // arithmetic form of the energy pass (FLARE_FP32 .. FLARE_BF16X6_SPLIT)
+  int flags = 0;                  // the precision argument as given (form | FLARE_VAR_FP32)
+  bool var64 = false;             // variance on the FP64 matrix cores (split forms without FLARE_VAR_FP32)
   // variances from Cholesky factors (part 1 of Wf holds L, Lx the 544-wide factors)
   bool vchol = false;
   double r_cut = 0.0;
@@ -100,13 +102,18 @@ struct flare_model {
   // instruction the kernel uses for d; lo' = fp8(16 (x - hi)). s_b = 2^k keeps |s_b beta| <= 16.
   uint64_t* W8[4] = {};
   float beta_scale[4] = {1.f, 1.f, 1.f, 1.f};
-  // Three-way BF16 form (precision FLARE_BF16X6_SPLIT): beta and the Cholesky factor L as
-  // [K step 5][column block 9][part 3][lane 64] x 8 bf16, parts x0 + x1 + x2 = FP32 value.
+  // Three-way BF16 form (precision FLARE_BF16X6_SPLIT): beta as [K step 5][column block 9]
+  // [part 3][lane 64] x 8 bf16, parts x0 + x1 + x2 = FP32 value.
   uint16_t* W6[4] = {};
-  uint16_t* L6[4] = {};
-  // Mixed buckets in the split form: L of the 544 x 544 Sigma_s, [544][544] FP32, stored
+  // Cholesky factor L of the 544 x 544 Sigma_s (mixed buckets), [544][544] FP32, stored
   // like W (row n = column n of L).
   float* Lx[2] = {};
+  // Split forms: Cholesky factors in FP64 for the variance on the FP64 matrix cores, in
+  // fragment order [column block][K chunk][k-step 4][lane 64]: element L[16 kc + 4 (lane / 16)
+  // + t][16 cb + lane % 16]. Single-species buckets: the factor of the bucket's 144 x 144
+  // block of Sigma (9 x 9 blocks); mixed buckets: the factor of Sigma_s (34 x 34 blocks).
+  double* L64[4] = {};
+  double* Lx64[2] = {};
 };
 
 struct flare_state {
@@ -176,6 +183,7 @@ struct flare_state {
   flare::DevBuf<int> scan_scratch;
   flare::DevBuf<int> atom_of_row1, atom_of_rowx;
   flare::DevBuf<float> D1, G1, Dx, Gx, Yx, Px;       // descriptors, gradients, mixed Y, partials
+  flare::DevBuf<double> Px64;                        // mixed rows, split forms: FP64 variance partials
   flare::DevBuf<flare::RedTask> d_tasks;
   flare::DevBuf<int> d_first_task;                   // [n_struct + 1] task range of each cell
   flare::DevBuf<double> red_e;                       // [tasks][2] (sum, compensation)
@@ -229,6 +237,9 @@ void compute_descriptors_mixed(flare_state* s);
 void export_descriptors(flare_state* s, float* d_out, float* norm_out);
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out);
 void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v);
+// quadratic forms of given vectors with the model of one bucket (fused.hip, qform.hip)
+void forms_given_144(flare_state* s, int bucket, int n, const float* d, float* e, float* v);
+int forms_given_544(flare_state* s, int bucket, int n, const float* d, float* e, float* v);
 // adjoint terms of the 544-wide rows, and of the 144-wide rows if rows144 (from G1)
 void compute_forces(flare_state* s, bool rows144);
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,

@@ -18,13 +18,16 @@ MASSES = np.array([1.008, 195.084])   # amu, H and Pt
 class Model:
     """Mapped per-species (beta_s, Sigma_s), FP64 host arrays [S, n_d, n_d] (Eqs. 1-2)."""
 
-    def __init__(self, beta, sigma, r_cut=4.5, n_rad=8, l_max=3, precision=B.FP32):
+    def __init__(self, beta, sigma, r_cut=4.5, n_rad=8, l_max=3, precision=B.FP32, _handle=None):
         lib = B.load()
-        beta = np.ascontiguousarray(beta, dtype=np.float64)
-        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-        h = ctypes.c_void_p()
-        B.check(lib.flare_model_create(ctypes.byref(h), beta.shape[0], n_rad, l_max, float(r_cut),
-                                       B.ptr(beta), B.ptr(sigma), precision))
+        if _handle is None:
+            beta = np.ascontiguousarray(beta, dtype=np.float64)
+            sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+            h = ctypes.c_void_p()
+            B.check(lib.flare_model_create(ctypes.byref(h), beta.shape[0], n_rad, l_max, float(r_cut),
+                                           B.ptr(beta), B.ptr(sigma), precision))
+        else:
+            h = _handle
         self.handle = h
         self.r_cut = r_cut
         d = ctypes.c_int()
@@ -34,6 +37,29 @@ class Model:
         B.check(lib.flare_model_info(h, ctypes.byref(p), ctypes.byref(c)))
         self.precision = p.value
         self.variance_cholesky = bool(c.value)   # V = |L^T d|^2 (else the full Sigma)
+
+    @classmethod
+    def from_sparse_set(cls, d_sparse, alpha, n_sparse, signal_var, noise, r_cut=4.5, n_rad=8, l_max=3,
+                        precision=B.FP32, want_matrices=False):
+        """The mapped model of a sparse set (flare_model_from_sparse_set, built on the device
+        in FP64): d_sparse [n_S, n_d] normalised descriptors grouped by central species
+        (n_sparse[s] rows of species s, species 0 first), alpha [n_S] the mean weights,
+        signal_var sigma^2, noise on the sparse-set kernel diagonal. With want_matrices the
+        device FP64 beta and gamma [S, n_d, n_d] are returned as well."""
+        lib = B.load()
+        d = torch.as_tensor(np.ascontiguousarray(d_sparse, np.float64)).cuda()
+        a = torch.as_tensor(np.ascontiguousarray(alpha, np.float64)).cuda()
+        ns = np.ascontiguousarray(n_sparse, np.int32)
+        nd = d.shape[1]
+        bm = torch.empty((len(ns), nd, nd), dtype=torch.float64, device="cuda") if want_matrices else None
+        gm = torch.empty_like(bm) if want_matrices else None
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        B.check(lib.flare_model_from_sparse_set(ctypes.byref(h), len(ns), n_rad, l_max, float(r_cut), B.ptr(ns),
+                                                B.ptr(d), B.ptr(a), float(signal_var), float(noise), precision,
+                                                B.ptr(bm), B.ptr(gm)))
+        m = cls(None, None, r_cut, n_rad, l_max, precision, _handle=h)
+        return (m, bm, gm) if want_matrices else m
 
     def __del__(self):
         if getattr(self, "handle", None):
@@ -246,6 +272,17 @@ class Evaluator:
                                                    B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species),
                                                    B.ptr(MASSES), float(dt), float(t_target), float(tau),
                                                    B.ptr(thermo)))
+
+    def quadratic_forms(self, bucket, d_rows):
+        """e = d^T beta d and V = d^T Sigma d of given FP32 vectors (device [n, 144 or 544])
+        with the model of environment bucket `bucket` (flare_quadratic_forms); discards the
+        resident descriptors."""
+        n = d_rows.shape[0]
+        e = torch.empty(n, dtype=torch.float32, device=self.device)
+        v = torch.empty(n, dtype=torch.float32, device=self.device)
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_quadratic_forms(self.handle, int(bucket), n, B.ptr(d_rows), B.ptr(e), B.ptr(v)))
+        return e, v
 
     def coordination(self, pos, prev=None):
         """H coordination numbers (device int32 [N], caller order) of `pos`, the positions last
