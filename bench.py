@@ -48,7 +48,7 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def profiled_traffic(kernel="k_fused144_w<0>"):
+def profiled_traffic(kernel="k_fused144_w<0, false>"):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
     try:
@@ -314,24 +314,34 @@ def precision_16m(engine, torch, small, beta, sigma, half_width=13.1, evals=5):
             "forms": forms}
 
 
-def serving(engine, torch, beta, sigma, n_req, rate):
+def serving(engine, torch, beta, sigma, n_req, rate, warmup=1000, pool=2000):
+    """Open-loop Poisson stream of warmup + n_req requests (structures drawn from a pool of
+    distinct slabs of log-uniform size); statistics over the n_req after the warm-up."""
+    import sys as _sys
+
     from paper_2204_12573_amd import binding, serve
+    _sys.setswitchinterval(1e-4)       # quick hand-offs between the scheduler and lane threads
     out = {}
-    reqs_proto = serve.poisson_requests(n_req, rate=rate, seed=7)
+    reqs_proto = serve.poisson_requests(warmup + n_req, rate=rate, seed=7, pool=pool)
     for name, prec, lanes, mb in [("batched_split", binding.BF16_SPLIT, 2, 10**9),
                                   ("one_at_a_time_fp32", binding.FP32, 1, 1)]:
         reqs = [serve.Request(r.rid, r.arrival, r.pos, r.species, r.box) for r in reqs_proto]
         model = engine.Model(beta, sigma, precision=prec)
         ex = serve.GpuExecutor(model, n_lanes=lanes, lane_atoms=400_000)
-        # warm up the lanes on the first few structures
+        # first use of each lane outside the stream
         serve.Scheduler(ex, max_batch=mb).run([serve.Request(-1 - k, 0.0, r.pos, r.species, r.box)
                                                for k, r in enumerate(reqs[:4])])
         torch.cuda.synchronize()
-        _, stats = serve.Scheduler(ex, max_batch=mb).run(reqs)
-        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+        _, stats = serve.Scheduler(ex, max_batch=mb).run(reqs, warmup=warmup)
+        stats = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+        stats["lanes"] = lanes
+        stats["lane_state_bytes"] = int(ex.lane_bytes)
+        out[name] = stats
+        ex.close()
         del ex, model
-    out["offered"] = {"rate_req_s": rate, "requests": n_req,
-                      "mean_atoms": float(sum(r.n for r in reqs_proto) / n_req)}
+    out["offered"] = {"rate_req_s": rate, "requests": n_req, "warmup_requests": warmup,
+                      "distinct_structures": pool,
+                      "mean_atoms": float(sum(r.n for r in reqs_proto[warmup:]) / n_req)}
     return out
 
 
@@ -369,7 +379,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the split-precision, serving and autograd legs")
-    ap.add_argument("--serve-requests", type=int, default=1200)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--no-huge", action="store_true", help="skip the ~16 M-atom precision leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy, a kernel of known traffic for counter scaling")

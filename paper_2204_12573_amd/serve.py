@@ -2,13 +2,15 @@
 
 Requests are periodic cells of uneven size (active-learning candidate screening). The
 scheduler keeps several *lanes*: one HIP stream, one device-resident evaluation state
-(neighbour list, descriptors, gradients) and pinned host staging buffers each. Whenever
-a lane is free it takes the oldest waiting requests (FIFO) up to the lane's HBM
-footprint budget, uploads them, and enqueues one launch sequence for the whole batch
-(list build, descriptors, energies + forces + variances, download). Requests arriving
-while batches run wait in the queue and are admitted as soon as a lane frees up; with
-two or more lanes the batches of different lanes overlap on the device. Latency is
-measured from a request's arrival to its results being on the host.
+(neighbour list, descriptors, gradients; every buffer sized when the lane is made, its
+bytes read back with flare_memory_bytes) and pinned host staging buffers each, served by a
+host thread of its own. Whenever a lane is free it takes the oldest waiting requests (FIFO)
+as long as the batch fits the lane's state (atoms, estimated pairs, cells), and its thread
+uploads them and runs one launch sequence for the whole batch (list build, descriptors,
+energies + forces + variances, download), so a lane waiting for its list build never holds
+up the scheduler or the other lanes. Requests arriving while batches run wait in the queue
+and are admitted as soon as a lane frees up; the batches of different lanes overlap on the
+device. Latency is measured from a request's arrival to its results being on the host.
 
 Per-cell results do not depend on the batch composition (the library computes each row
 independently and gathers forces in a fixed order), so a structure gives the same bits
@@ -17,6 +19,7 @@ alone and in any mix.
 from __future__ import annotations
 
 import dataclasses
+import threading
 import time
 from collections import deque
 
@@ -47,27 +50,23 @@ class Request:
 
 
 class Footprint:
-    """Device bytes a batch needs: per-atom arrays, per-pair list, sliced slots
-    (with padding headroom) and descriptor/gradient rows."""
+    """What a batch needs of a lane's state: its atoms and an estimate of its listed pairs
+    (pairs_per_atom; bulk Pt(111) has 18 at the list radius, a surface or H atom fewer)."""
 
-    def __init__(self, pairs_per_atom=22.0, slot_overhead=1.6):
+    def __init__(self, pairs_per_atom=22.0):
         self.ppa = pairs_per_atom
-        self.slot = slot_overhead
 
     def atoms_pairs(self, n_atoms):
         return n_atoms, int(self.ppa * n_atoms) + 64
 
-    def bytes(self, n_atoms):
-        n, p = self.atoms_pairs(n_atoms)
-        per_atom = 4 * 16 + 8 * 12 + 4 * 6 + 8 * 32   # int arrays, FP64 SoA, FP32 outputs, pair cache
-        per_pair = 4 * 4                                # j, shift, reverse, slot of pair
-        per_slot = 4 * 3 + 16 * 3                       # slot ints, fixed pair vector, geometry, reverse term
-        rows = 2 * 144 * 4 + 16 + 5 * 4                 # descriptor + gradient, own force, row copies
-        return n * (per_atom + rows) + p * (per_pair + self.slot * per_slot)
+    def fits(self, n_atoms, n_cells, lane_atoms):
+        """A batch of n_atoms in n_cells fits a lane made for lane_atoms atoms."""
+        return n_atoms <= lane_atoms and n_cells <= lane_atoms + 1
 
 
 class GpuExecutor:
-    """Lanes on the GPU: each has its own torch stream and flare state."""
+    """Lanes on the GPU: each has its own torch stream, flare state, pinned staging and a
+    host thread that runs its batches (launch() hands a batch over and returns at once)."""
 
     def __init__(self, model, n_lanes=2, lane_atoms=400_000, footprint=None, want_var=True):
         import torch
@@ -84,22 +83,41 @@ class GpuExecutor:
             st = torch.cuda.Stream()
             n, p = self.fp.atoms_pairs(lane_atoms)
             ev = engine.Evaluator(model, max_atoms=n, max_pairs=p, stream=st)
-            self.lanes.append({"stream": st, "ev": ev, "busy": None,
-                               "pin_pos": torch.empty((3, n), dtype=torch.float64).pin_memory(),
-                               "pin_sp": torch.empty(n, dtype=torch.int32).pin_memory(),
-                               "dev_pos": torch.empty((3, n), dtype=torch.float64, device="cuda"),
-                               "dev_sp": torch.empty(n, dtype=torch.int32, device="cuda"),
-                               "host": {"e": torch.empty(n, dtype=torch.float32).pin_memory(),
-                                        "f": torch.empty((3, n), dtype=torch.float32).pin_memory(),
-                                        "sigma": torch.empty(n, dtype=torch.float32).pin_memory(),
-                                        "E": torch.empty(n, dtype=torch.float64).pin_memory()}})
+            lane = {"stream": st, "ev": ev, "busy": None, "result": None, "error": None,
+                    "work": threading.Event(), "ready": threading.Event(),
+                    "pin_pos": torch.empty((3, n), dtype=torch.float64).pin_memory(),
+                    "pin_sp": torch.empty(n, dtype=torch.int32).pin_memory(),
+                    "dev_pos": torch.empty((3, n), dtype=torch.float64, device="cuda"),
+                    "dev_sp": torch.empty(n, dtype=torch.int32, device="cuda"),
+                    "host": {"e": torch.empty(n, dtype=torch.float32).pin_memory(),
+                             "f": torch.empty((3, n), dtype=torch.float32).pin_memory(),
+                             "sigma": torch.empty(n, dtype=torch.float32).pin_memory(),
+                             "E": torch.empty(n, dtype=torch.float64).pin_memory()}}
+            lane["thread"] = threading.Thread(target=self._worker, args=(lane,), daemon=True)
+            lane["thread"].start()
+            self.lanes.append(lane)
         self.lane_atoms = lane_atoms
-        self.budget = self.fp.bytes(lane_atoms)
+        # the device memory a lane holds: its state, fixed when the lane is made
+        self.lane_bytes = self.lanes[0]["ev"].memory_bytes(with_model=False)
 
-    def launch(self, k, batch):
-        """Upload and enqueue one batch on lane k (returns after the list build)."""
+    def _worker(self, lane):
         torch = self.torch
-        lane = self.lanes[k]
+        torch.cuda.set_device(0)
+        while True:
+            lane["work"].wait()
+            lane["work"].clear()
+            batch = lane["busy"]
+            if batch is None:
+                return
+            try:
+                lane["result"] = self._run(lane, batch)
+            except Exception as exc:      # reported to the scheduler by poll()
+                lane["error"] = exc
+            lane["ready"].set()
+
+    def _run(self, lane, batch):
+        """Upload one batch, build its list, evaluate E, F, sigma, download (waits)."""
+        torch = self.torch
         n = sum(r.n for r in batch)
         offs = np.zeros(len(batch) + 1, np.int32)
         offs[1:] = np.cumsum([r.n for r in batch])
@@ -127,18 +145,7 @@ class GpuExecutor:
             if self.want_var:
                 host["sigma"] = hb["sigma"][:n]
                 host["sigma"].copy_(out["sigma"], non_blocking=True)
-            done = torch.cuda.Event()
-            done.record(st)
-        lane["busy"] = (batch, offs, host, done)
-
-    def poll(self, k):
-        lane = self.lanes[k]
-        if lane["busy"] is None:
-            return None
-        batch, offs, host, done = lane["busy"]
-        if not done.query():
-            return None
-        lane["busy"] = None
+        st.synchronize()
         e = host["e"].numpy()
         f = host["f"].numpy()
         E = host["E"].numpy()
@@ -151,8 +158,31 @@ class GpuExecutor:
                 r.sigma = sg[a:a + r.n].copy()
         return batch
 
+    def launch(self, k, batch):
+        """Hand one batch to lane k's thread (returns at once)."""
+        lane = self.lanes[k]
+        lane["busy"] = batch
+        lane["ready"].clear()
+        lane["work"].set()
+
+    def poll(self, k):
+        lane = self.lanes[k]
+        if lane["busy"] is None or not lane["ready"].is_set():
+            return None
+        lane["busy"] = None
+        if lane["error"] is not None:
+            exc, lane["error"] = lane["error"], None
+            raise exc
+        return lane["result"]
+
     def idle(self, k):
         return self.lanes[k]["busy"] is None
+
+    def close(self):
+        for lane in self.lanes:
+            lane["busy"] = None
+            lane["work"].set()
+            lane["thread"].join()
 
     @property
     def n_lanes(self):
@@ -169,25 +199,26 @@ class Scheduler:
         self.ex = executor
         self.clock = clock
         self.max_batch = max_batch
-        self.spin = spin            # called when nothing is ready (tests advance a fake clock)
+        # called when nothing is ready: tests advance a fake clock; by default a short sleep
+        # that lets the lane threads run
+        self.spin = spin if spin is not None else (lambda: time.sleep(2e-5))
 
     def _form_batch(self, queue):
         fp = self.ex.fp
-        batch, used, atoms = [], 0, 0
+        batch, atoms = [], 0
         while queue and len(batch) < self.max_batch:
             r = queue[0]
-            b = fp.bytes(atoms + r.n) - used if batch else fp.bytes(r.n)
-            if batch and (used + b > self.ex.budget or atoms + r.n > self.ex.lane_atoms):
+            if not fp.fits(atoms + r.n, len(batch) + 1, self.ex.lane_atoms):
+                if not batch:
+                    raise ValueError(f"request {r.rid} with {r.n} atoms exceeds a lane ({self.ex.lane_atoms})")
                 break
-            if not batch and r.n > self.ex.lane_atoms:
-                raise ValueError(f"request {r.rid} with {r.n} atoms exceeds a lane ({self.ex.lane_atoms})")
             batch.append(queue.popleft())
-            used = fp.bytes(atoms + r.n)
             atoms += r.n
         return batch
 
-    def run(self, requests):
-        """Serve `requests` (sorted by arrival, arrival times relative to the start)."""
+    def run(self, requests, warmup=0):
+        """Serve `requests` (sorted by arrival, arrival times relative to the start); the
+        first `warmup` requests by arrival are served but left out of the statistics."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = deque()
         done = []
@@ -217,28 +248,51 @@ class Scheduler:
                     stats["batches"] += 1
                     stats["batch_atoms"].append(sum(r.n for r in batch))
                     progressed = True
-            if not progressed and self.spin is not None:
+            if not progressed:
                 self.spin()
-        span = max(r.t_done for r in done) - min(r.arrival for r in done)
-        lat = np.array([r.latency for r in done])
-        atoms = sum(r.n for r in done)
+        ordered = sorted(done, key=lambda r: r.arrival)
+        timed = ordered[warmup:] if warmup < len(ordered) else ordered
+        span = max(r.t_done for r in timed) - min(r.arrival for r in timed)
+        lat = np.array([r.latency for r in timed])
+        wait = np.array([r.t_start - r.arrival for r in timed])
+        atoms = sum(r.n for r in timed)
+        sizes = np.array([r.n for r in timed])
+        edges = np.percentile(sizes, np.linspace(0, 100, 11))
+        deciles = []
+        for q in range(10):
+            m = (sizes >= edges[q]) & ((sizes < edges[q + 1]) if q < 9 else (sizes <= edges[q + 1]))
+            if m.any():
+                deciles.append({"atoms": [int(sizes[m].min()), int(sizes[m].max())],
+                                "p50_ms": round(float(np.percentile(lat[m], 50) * 1e3), 3),
+                                "p99_ms": round(float(np.percentile(lat[m], 99) * 1e3), 3)})
         stats.update({
-            "requests": total,
+            "requests": len(timed),
+            "warmup_requests": len(ordered) - len(timed),
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3),
-            "throughput_req_s": total / span,
+            "queue_wait_p50_ms": float(np.percentile(wait, 50) * 1e3),
+            "queue_wait_p99_ms": float(np.percentile(wait, 99) * 1e3),
+            "throughput_req_s": len(timed) / span,
             "throughput_Matom_s": atoms / span / 1e6,
             "mean_batch_atoms": float(np.mean(stats["batch_atoms"])),
+            "by_size_decile": deciles,
         })
         del stats["batch_atoms"]
         return done, stats
 
 
-def poisson_requests(n, rate, sizes=(100, 50_000), seed=0):
-    """Open-loop arrivals: Poisson process of `rate` per second, slabs of log-uniform size."""
+def poisson_requests(n, rate, sizes=(100, 50_000), seed=0, pool=None):
+    """Open-loop arrivals: Poisson process of `rate` per second, slabs of log-uniform size.
+    With `pool`, the structures are drawn (seeded, with repetition) from `pool` distinct
+    slabs of the same distribution, which bounds the host memory of long streams."""
     from . import structures as S
-    out = []
-    for k, (t, st) in enumerate(S.serving_requests(n, rate=rate, lo=sizes[0], hi=sizes[1], seed=seed)):
-        out.append(Request(k, t, st.pos, st.species.astype(np.int32), st.box))
-    return out
+    if pool is None or pool >= n:
+        return [Request(k, t, st.pos, st.species.astype(np.int32), st.box)
+                for k, (t, st) in enumerate(S.serving_requests(n, rate=rate, lo=sizes[0], hi=sizes[1], seed=seed))]
+    base = S.serving_requests(pool, rate=rate, lo=sizes[0], hi=sizes[1], seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    pick = rng.integers(0, pool, n)
+    return [Request(k, float(t[k]), base[p][1].pos, base[p][1].species.astype(np.int32), base[p][1].box)
+            for k, p in enumerate(pick)]

@@ -1,5 +1,6 @@
 """Scheduler logic of the serving loop on the CPU with a fake executor and a fake clock:
-FIFO admission, footprint budget, lane overlap, latency bookkeeping."""
+FIFO admission, lane capacity, lane overlap, latency bookkeeping, warm-up exclusion and
+the per-size-decile latencies."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,6 @@ class FakeExecutor:
         self.clock, self.per_atom, self.per_batch = clock, per_atom, per_batch
         self.fp = serve.Footprint()
         self.lane_atoms = lane_atoms
-        self.budget = self.fp.bytes(lane_atoms)
         self.busy = [None] * n_lanes
         self.launched = []
 
@@ -38,7 +38,7 @@ class FakeExecutor:
 
     def launch(self, k, batch):
         n = sum(r.n for r in batch)
-        assert self.fp.bytes(n) <= self.budget or len(batch) == 1
+        assert self.fp.fits(n, len(batch), self.lane_atoms)
         self.busy[k] = (batch, self.clock() + self.per_batch + self.per_atom * n)
         self.launched.append([r.rid for r in batch])
 
@@ -57,7 +57,7 @@ def _reqs(sizes, arrivals):
             for k, (n, t) in enumerate(zip(sizes, arrivals))]
 
 
-def test_fifo_and_budget():
+def test_fifo_and_capacity():
     clock = FakeClock()
     ex = FakeExecutor(clock)
     sched = serve.Scheduler(ex, clock=clock, spin=clock.advance)
@@ -74,6 +74,19 @@ def test_fifo_and_budget():
         assert r.t_start >= r.arrival and r.t_done > r.t_start
         assert np.all(r.e == r.n)
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
+    assert stats["queue_wait_p99_ms"] <= stats["p99_ms"]
+    dec = stats["by_size_decile"]
+    assert len(dec) == 10 and sum(1 for _ in dec) == 10
+    assert dec[0]["atoms"][0] == sizes.min() and dec[-1]["atoms"][1] == sizes.max()
+
+
+def test_warmup_left_out_of_the_statistics():
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    sizes = [200] * 30
+    arrivals = np.arange(30) * 1e-3
+    done, stats = serve.Scheduler(ex, clock=clock, spin=clock.advance).run(_reqs(sizes, arrivals), warmup=10)
+    assert len(done) == 30 and stats["requests"] == 20 and stats["warmup_requests"] == 10
 
 
 def test_continuous_batching_beats_one_at_a_time():
