@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the split-precision, serving and autograd legs")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--no-huge", action="store_true", help="skip the ~16 M-atom precision leg")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "bf16x6", "bf16x6-var32"],
+                    help="arithmetic form of the main MD leg (default fp32; the others for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy, a kernel of known traffic for counter scaling")
     args = ap.parse_args()
@@ -406,7 +408,10 @@ def main():
     st = S.config_large()
     beta, sigma = S.random_model(544)
     n = st.n
-    ev, model, el, tm = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup, 0)
+    from paper_2204_12573_amd import binding as B
+    main_prec = {"fp32": 0, "bf16": B.BF16_SPLIT, "fp8": B.FP8_SPLIT, "bf16x6": B.BF16X6_SPLIT,
+                 "bf16x6-var32": B.BF16X6_SPLIT | B.VAR_FP32}[args.precision]
+    ev, model, el, tm = md_throughput(engine, torch, st, beta, sigma, args.steps, args.warmup, main_prec)
     npairs, counts = ev.list_info()
     status = ev.status()
     log(f"atoms {n}, pairs {npairs}, buckets {counts.tolist()}")
@@ -489,7 +494,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "H2 gas over Pt(111) 100x100x24, ~1.0 M atoms, NVE dt 0.5 fs, rebuild every 10",
                    "atoms": n, "pairs": int(npairs), "rows144": n144, "rows544": n544,
-                   "n_desc": 544, "r_cut": 4.5, "skin": 0.2, "precision": "fp32"},
+                   "n_desc": 544, "r_cut": 4.5, "skin": 0.2, "precision": args.precision},
         "roofline": roofline,
         "step_roofline": step_roofline,
         "stage_us_per_launch": stage_us,

@@ -150,16 +150,24 @@ int flare_descriptor_dim(const flare_model* model, int* n_d);
 /*
  * Create evaluation state for up to max_atoms atoms and max_pairs directed list pairs.
  * stream: a hipStream_t (passed as void*; NULL = the default stream). The state keeps
- * the neighbour list, the descriptors and the gradients on the device between calls,
- * and grows its descriptor buffers at list builds when the environment mix needs it.
- * One state serves one stream; calls on one state must not overlap.
+ * the neighbour list, the descriptors and the gradients on the device between calls.
+ * Every device buffer is allocated here, sized from max_atoms and max_pairs: per atom,
+ * per listed pair, per row (max_atoms plus the 128-row padding of the six environment
+ * classes), the sliced pair layout (max_pairs * 5/4 + 12,288 slots), cell-list bins
+ * (4 max_atoms, at least 65,536; wider bins are used when the cells need more), cells
+ * (max_atoms + 1) and a workspace of 16,384 mixed-environment rows (the 544-wide rows are
+ * processed in chunks of that many). No later call allocates device memory, except the
+ * first flare_virial (its task sums; flare_virial_noalloc allocates nothing).
+ * flare_memory_bytes reports the total. One state serves one stream; calls on one state
+ * must not overlap.
  */
 int flare_state_create(flare_state** out, const flare_model* model, int max_atoms,
                        long long max_pairs, void* stream);
 int flare_state_destroy(flare_state* state);
 
 /*
- * Build the neighbour list (SYNCHRONISING: waits for the stream once to size buffers).
+ * Build the neighbour list (SYNCHRONISING: waits for the stream once, at the end, to read
+ * the sizes the build found on the device and its status words; allocates nothing).
  *   x, y, z       DEVICE FP64 [n_atoms] positions (any periodic image)
  *   species       DEVICE int32 [n_atoms]
  *   n_struct      number of cells; struct_offsets_host HOST int32 [n_struct+1]
@@ -170,8 +178,9 @@ int flare_state_destroy(flare_state* state);
  * w = x - L*floor(x/L) and the squared distance evaluated in FP64 as
  * (dx*dx + dy*dy) + dz*dz without fused multiply-add; (i, i, 0) is excluded.
  * Errors: FLARE_E_ARG, FLARE_E_BOX, FLARE_E_SPECIES, FLARE_E_NONFINITE,
- * FLARE_E_CAPACITY (n_atoms > max_atoms or pairs > max_pairs: the list is not usable;
- * create a larger state), FLARE_E_OOM, FLARE_E_HIP.
+ * FLARE_E_CAPACITY (n_atoms > max_atoms, more than max_atoms + 1 cells, pairs > max_pairs,
+ * or a sliced layout beyond its slots: the list is not usable; create a larger state),
+ * FLARE_E_HIP.
  */
 int flare_neighbors(flare_state* state, int n_atoms, const double* x, const double* y,
                     const double* z, const int32_t* species, int n_struct,
@@ -238,8 +247,8 @@ int flare_forces(flare_state* state, const double* cell_scale, float* fx, float*
  * evaluation, which must be for the current positions (FLARE_E_STALE otherwise).
  *   virial_struct  DEVICE FP64 [n_struct][9], row-major W_xx W_xy W_xz W_yx ... W_zz.
  * Per-atom terms are summed in FP32 over each atom's pairs in list order, then in FP64
- * over the cell's atoms in a fixed order (deterministic). Grows two internal buffers
- * (36 bytes per atom) on the first call.
+ * over the cell's atoms in a fixed order (deterministic). Allocates one internal buffer
+ * (the FP64 task sums, 72 bytes per reduction task of up to 2,048 atoms) on the first call.
  */
 int flare_virial(flare_state* state, double* virial_struct);
 

@@ -38,12 +38,15 @@ __global__ __launch_bounds__(TA) void k_adjoint144(SlotView v, const int* __rest
 // the row (G^ from the row's 544 gradient components: (H,H) and (Pt,Pt) blocks doubled on
 // the diagonal, the (H,Pt) block shared by both orders), and the row's slots are split
 // over the lanes (k = L, L + 16, ...), each pair reading u of its neighbour species from LDS.
-__global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows1,
+// Rows [r0, r0 + gridDim.x * MROWS) of the mixed class; G holds the chunk's gradients
+// (row r - r0).
+__global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows1, int r0,
                                                             const int* __restrict__ atom_of_row,
                                                             const float* __restrict__ G, float4* __restrict__ f_own) {
   __shared__ __attribute__((aligned(16))) float cs[MROWS * MSTRIDE];
   const int rl = threadIdx.x >> 4, L = threadIdx.x & 15;
-  const int row = blockIdx.x * MROWS + rl;
+  const int local = blockIdx.x * MROWS + rl;
+  const int row = r0 + local;
   const int R = rows1 + row;
   const int i = atom_of_row[row];
   float c[NLM];
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows
 #pragma unroll
   for (int lm = 0; lm < NLM; ++lm) u[lm] = 0.f;
   if (i >= 0) {
-    const float* g = G + (size_t)row * ND;
+    const float* g = G + (size_t)local * ND;
     const int sa = L >> 3, na = L & 7;
 #pragma unroll 2
     for (int b = 0; b < 2 * NR; ++b) {
@@ -113,19 +116,17 @@ __global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows
 
 }  // namespace
 
-void compute_forces(flare_state* s, bool rows144) {
+void adjoint_rows144(flare_state* s) {
   const SlotView v = slot_view(s);
-  if (rows144) {
-    StageTimer tm(s, FLARE_T_FORCE1);
-    if (s->rows1 > 0)
-      k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1.p, s->G1.p, s->f_own.p);
-  }
-  {
-    StageTimer tm(s, FLARE_T_FORCEX);
-    if (s->rowsx > 0)
-      k_adjoint_mixed<<<s->rowsx / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, s->atom_of_rowx.p, s->Gx.p,
-                                                                    s->f_own.p);
-  }
+  StageTimer tm(s, FLARE_T_FORCE1);
+  if (s->rows1 > 0) k_adjoint144<<<s->rows1 / 128, TA, 0, s->stream>>>(v, s->atom_of_row1, s->G1, s->f_own);
+}
+
+void adjoint_mixed_chunk(flare_state* s, int r0, int nr) {
+  const SlotView v = slot_view(s);
+  StageTimer tm(s, FLARE_T_FORCEX);
+  if (nr > 0)
+    k_adjoint_mixed<<<nr / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, r0, s->atom_of_rowx, s->Gx, s->f_own);
 }
 
 }  // namespace flare

@@ -14,26 +14,12 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-PairView pair_view(const flare_state* s) {
-  PairView v;
-  v.n = s->n_atoms;
-  v.sp = s->sp;
-  v.sid = s->sid;
-  v.grids = s->d_grids.p;
-  v.nl_off = s->nl_off;
-  v.nl_j = s->nl_j;
-  v.nl_s = s->nl_s;
-  v.rc = (float)s->model->r_cut;
-  v.rc2 = s->model->r_cut * s->model->r_cut;
-  return v;
-}
-
 SlotView slot_view(const flare_state* s) {
   SlotView v;
-  v.geom = s->geom.p;
-  v.slice_base = s->slice_base.p;
-  v.rev = s->slot_rev.p;
-  v.w_in = s->w_in.p;
+  v.geom = s->geom;
+  v.slice_base = s->slice_base;
+  v.rev = s->slot_rev;
+  v.w_in = s->w_in;
   v.rc = (float)s->model->r_cut;
   return v;
 }
@@ -197,6 +183,78 @@ std::vector<double> f64_fragments(const std::vector<double>& L, int n) {
 }
 
 }  // namespace
+
+// Every device array of a state, with its size in bytes for the capacities of the state.
+template <class F>
+static void state_arrays(flare_state* s, F&& f) {
+  const size_t n = (size_t)s->max_atoms, P = (size_t)s->max_pairs, R = (size_t)s->row_cap;
+  const size_t SL = (size_t)s->slice_cap, SC = (size_t)s->slot_cap, BC = (size_t)s->bin_cap;
+  const size_t NC = (size_t)s->cell_cap, TC = (size_t)s->task_cap, X = (size_t)s->mix_cap;
+  const size_t keys = (size_t)list_key_count() * s->nblk_cap + 1;
+  const size_t scan_n = std::max({BC + 1, n + 1, keys, SL + 1});
+  f((void**)&s->perm, n * 4);
+  f((void**)&s->sp, n * 4);
+  f((void**)&s->sid, n * 4);
+  f((void**)&s->bin, n * 4);
+  f((void**)&s->envmask, n * 4);
+  f((void**)&s->bucket, n * 4);
+  f((void**)&s->row_of, n * 4);
+  f((void**)&s->nl_cnt, n * 4);
+  f((void**)&s->nl_off, (n + 1) * 4);
+  f((void**)&s->w, n * sizeof(double4));
+  f((void**)&s->wf, n * sizeof(float4));
+  f((void**)&s->off, 3 * n * 8);
+  f((void**)&s->dlt, n * 16);
+  f((void**)&s->xb, 3 * n * 8);
+  f((void**)&s->inv_perm, n * 4);
+  f((void**)&s->nrm, n * 4);
+  f((void**)&s->e_int, n * 4);
+  f((void**)&s->v_int, n * 4);
+  f((void**)&s->crec, n * sizeof(CallerRec));
+  f((void**)&s->sorted, n * 4);
+  f((void**)&s->row_caller, (n + 1) * 4);
+  f((void**)&s->slot0, n * 4);
+  f((void**)&s->pair_cache, (size_t)list_pair_cache() * n * sizeof(int2));
+  f((void**)&s->nl_j, P * 4);
+  f((void**)&s->nl_s, P * 4);
+  f((void**)&s->nl_rev, P * 4);
+  f((void**)&s->d_grids, NC * sizeof(CellGrid));
+  f((void**)&s->d_struct_off, (NC + 1) * 4);
+  f((void**)&s->bin_count, (BC + 1) * 4);
+  f((void**)&s->bin_start, (BC + 1) * 4);
+  f((void**)&s->bin_fill, (BC + 1) * 4);
+  f((void**)&s->blk_bucket, keys * 4);
+  f((void**)&s->blk_bucket_scan, (keys + 1) * 4);
+  f((void**)&s->scan_scratch, scan_scratch_ints((long long)scan_n) * 4);
+  f((void**)&s->d_tasks, TC * sizeof(RedTask));
+  f((void**)&s->d_first_task, (NC + 1) * 4);
+  f((void**)&s->red_e, TC * 2 * 8);
+  f((void**)&s->red_s, TC * 4);
+  f((void**)&s->atom_of_row1, (R + 1) * 4);
+  f((void**)&s->atom_of_rowx, (R + 1) * 4);
+  f((void**)&s->cnt_row, R * 4);
+  f((void**)&s->sid_row, R * 4);
+  f((void**)&s->e_row, R * 4);
+  f((void**)&s->v_row, R * 4);
+  f((void**)&s->row_out, R * 16);
+  f((void**)&s->f_own, R * 16);
+  f((void**)&s->G1, R * ND1 * 4);
+  f((void**)&s->Dx, X * ND * 4);
+  f((void**)&s->Gx, X * ND * 4);
+  f((void**)&s->Yx, X * ND * 4);
+  f((void**)&s->Px, X * 4 * 4);
+  f((void**)&s->Px64, X * 9 * 8);
+  f((void**)&s->slice_len, (SL + 1) * 4);
+  f((void**)&s->slice_base, (SL + 1) * 4);
+  f((void**)&s->slot_atom, SC * 4);
+  f((void**)&s->slot_j, SC * 4);
+  f((void**)&s->slot_rev, SC * 4);
+  f((void**)&s->slot_d0, SC * 16);
+  f((void**)&s->geom, SC * 16);
+  f((void**)&s->w_in, SC * 16);
+  f((void**)&s->d_status, 64);
+  f((void**)&s->d_layout, (size_t)list_layout_words() * 4 + 64);
+}
 
 extern "C" {
 
@@ -449,51 +507,13 @@ int flare_descriptor_dim(const flare_model* m, int* n_d) {
 }
 
 static void free_state(flare_state* s) {
-  void* ptrs[] = {s->perm, s->sp,  s->sid, s->bin,   s->envmask, s->bucket, s->row_of, s->nl_cnt,
-                  s->nl_off, s->w, s->off, s->dlt,   s->nrm,     s->e_int,  s->v_int,
-                  s->o_bin, s->o_sid, s->o_w, s->o_off, s->sorted, s->nl_j, s->nl_s, s->nl_rev, s->slot_of_pair, s->d_status,
-                  s->d_info};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  state_arrays(s, [](void** p, size_t) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  });
   if (s->h_info) (void)hipHostFree(s->h_info);
-  s->d_grids.release();
-  s->d_struct_off.release();
-  s->bin_count.release();
-  s->bin_start.release();
-  s->bin_fill.release();
-  s->blk_bucket.release();
-  s->blk_bucket_scan.release();
-  s->scan_scratch.release();
-  s->atom_of_row1.release();
-  s->atom_of_rowx.release();
-  s->D1.release();
-  s->G1.release();
-  s->Dx.release();
-  s->Gx.release();
-  s->Yx.release();
-  s->Px.release();
-  s->Px64.release();
-  s->d_tasks.release();
-  s->d_first_task.release();
-  s->red_e.release();
-  s->red_s.release();
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
   s->red_w.release();
-  s->slice_len.release();
-  s->slice_base.release();
-  s->slot_atom.release();
-  s->slot_j.release();
-  s->slot_d0.release();
-  s->slot_rev.release();
-  s->geom.release();
-  s->f_own.release();
-  s->w_in.release();
-  s->pair_cache.release();
-  s->row_out.release();
-  s->row_caller.release();
-  s->cnt_row.release();
-  s->sid_row.release();
-  s->e_row.release();
-  s->v_row.release();
 }
 
 int flare_state_create(flare_state** out, const flare_model* model, int max_atoms,
@@ -508,39 +528,24 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   s->stream = (hipStream_t)stream;
   s->max_atoms = max_atoms;
   s->max_pairs = max_pairs;
+  // capacities of everything a list build and a step can need (see flare.h)
+  s->row_cap = (max_atoms + NBUCKET * TILE_ROWS + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+  s->slice_cap = s->row_cap / 32;
+  s->slot_cap = (max_pairs + max_pairs / 4 + 32LL * 64 * NBUCKET + 31) / 32 * 32;
+  s->bin_cap = (int)std::min<long long>(std::max<long long>(4LL * max_atoms, 1 << 16), 1LL << 30);
+  s->cell_cap = max_atoms + 1;
+  s->task_cap = s->cell_cap + max_atoms / 2048 + 1;
+  s->nblk_cap = (max_atoms + 255) / 256;
+  s->mix_cap = std::min(s->row_cap, MIX_ROWS);
   hipError_t e = hipGetDevice(&s->device);
-  const size_t n = (size_t)max_atoms;
-  auto al = [&](void** p, size_t bytes) {
+  state_arrays(s, [&](void** p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 4);
     if (e == hipSuccess) s->fixed_bytes += (long long)(bytes ? bytes : 4);
-  };
-  al((void**)&s->perm, n * 4);
-  al((void**)&s->sp, n * 4);
-  al((void**)&s->sid, n * 4);
-  al((void**)&s->bin, n * 4);
-  al((void**)&s->envmask, n * 4);
-  al((void**)&s->bucket, n * 4);
-  al((void**)&s->row_of, n * 4);
-  al((void**)&s->nl_cnt, n * 4);
-  al((void**)&s->nl_off, (n + 1) * 4);
-  al((void**)&s->w, n * 32);
-  al((void**)&s->off, 3 * n * 8);
-  al((void**)&s->dlt, n * 16);
-  al((void**)&s->nrm, n * 4);
-  al((void**)&s->e_int, n * 4);
-  al((void**)&s->v_int, n * 4);
-  al((void**)&s->o_bin, n * 4);
-  al((void**)&s->o_sid, n * 4);
-  al((void**)&s->o_w, 3 * n * 8);
-  al((void**)&s->o_off, 3 * n * 8);
-  al((void**)&s->sorted, n * 4);
-  al((void**)&s->nl_j, (size_t)max_pairs * 4);
-  al((void**)&s->nl_s, (size_t)max_pairs * 4);
-  al((void**)&s->nl_rev, (size_t)max_pairs * 4);
-  al((void**)&s->slot_of_pair, (size_t)max_pairs * 4);
-  al((void**)&s->d_status, 64);
-  al((void**)&s->d_info, 64);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_info, 64, hipHostMallocDefault);
+  });
+  s->h_stage_bytes = (size_t)s->cell_cap * sizeof(CellGrid) + 2 * ((size_t)s->cell_cap + 1) * sizeof(int) +
+                     (size_t)s->task_cap * sizeof(RedTask) + 64;
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_info, 256, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_stage, s->h_stage_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(s->d_status, 0, 64, s->stream);
   if (e != hipSuccess) {
     set_error(std::string("state allocation: ") + hipGetErrorString(e));
@@ -584,36 +589,50 @@ int flare_neighbors(flare_state* s, int n_atoms, const double* x, const double* 
       "struct offsets must start at 0 and end at n_atoms");
   for (int c = 0; c < n_struct; ++c)
     ARG(struct_offsets_host[c + 1] >= struct_offsets_host[c], "struct offsets must be non-decreasing");
+  if (n_struct > s->cell_cap) {
+    set_error("more cells than the state holds (max_atoms + 1)");
+    return FLARE_E_CAPACITY;
+  }
   const double rl = s->model->r_cut + skin;
   s->grids.resize(n_struct);
   s->struct_off.assign(struct_offsets_host, struct_offsets_host + n_struct + 1);
-  long long nbins = 0;
-  for (int c = 0; c < n_struct; ++c) {
-    CellGrid& g = s->grids[c];
+  for (int c = 0; c < n_struct; ++c)
     for (int ax = 0; ax < 3; ++ax) {
       const double L = boxes_host[3 * c + ax];
       if (!(std::isfinite(L) && L > 0.0)) {
         set_error("box side must be positive and finite");
         return FLARE_E_BOX;
       }
-      // bins at least r_list (with a relative margin far above rounding) wide
-      long long nb = (long long)std::floor(L / (rl * (1.0 + 1e-9)));
-      nb = std::max(1LL, std::min(nb, 4096LL));
-      const double h = L / (double)nb;
-      g.L[ax] = L;
-      g.nb[ax] = (int)nb;
-      g.inv_h[ax] = (double)nb / L;
-      g.K[ax] = (int)std::ceil(rl / h);
-      if (g.K[ax] > 100) {
-        set_error("box side too small for the list radius");
-        return FLARE_E_BOX;
-      }
     }
-    g.bin_base = (int)nbins;
-    g.atom_base = struct_offsets_host[c];
-    nbins += (long long)g.nb[0] * g.nb[1] * g.nb[2];
-    if (nbins > (1LL << 30)) {
-      set_error("too many bins");
+  // bins at least r_list wide (with a relative margin far above rounding); when the cells
+  // need more bins than the state holds, wider ones (a factor 2^(1/3) per try, so the
+  // search visits more candidates but the list is the same)
+  long long nbins = 0;
+  for (double widen = 1.0;; widen *= 1.2599210498948732) {
+    nbins = 0;
+    for (int c = 0; c < n_struct; ++c) {
+      CellGrid& g = s->grids[c];
+      for (int ax = 0; ax < 3; ++ax) {
+        const double L = boxes_host[3 * c + ax];
+        long long nb = (long long)std::floor(L / (rl * widen * (1.0 + 1e-9)));
+        nb = std::max(1LL, std::min(nb, 4096LL));
+        const double h = L / (double)nb;
+        g.L[ax] = L;
+        g.nb[ax] = (int)nb;
+        g.inv_h[ax] = (double)nb / L;
+        g.K[ax] = (int)std::ceil(rl / h);
+        if (g.K[ax] > 100) {
+          set_error("box side too small for the list radius");
+          return FLARE_E_BOX;
+        }
+      }
+      g.bin_base = (int)nbins;
+      g.atom_base = struct_offsets_host[c];
+      nbins += (long long)g.nb[0] * g.nb[1] * g.nb[2];
+    }
+    if (nbins <= s->bin_cap) break;
+    if (nbins <= n_struct) {        // one bin per cell already
+      set_error("more cells than the state's bins");
       return FLARE_E_CAPACITY;
     }
   }
@@ -693,6 +712,20 @@ int flare_neighbors_export(flare_state* s, long long* offsets, int32_t* j_out, i
   return FLARE_OK;
 }
 
+// The mixed (544-wide) rows in chunks of mix_cap rows: descriptors (exported to d_out in
+// caller order when given), quadratic forms (energies and gradients when want_e or want_f,
+// variances when want_v), adjoint terms when want_f.
+static void mixed_rows(flare_state* s, float* d_out, bool want_e, bool want_v, bool want_f) {
+  for (int r0 = 0; r0 < s->rowsx; r0 += s->mix_cap) {
+    const int nr = std::min(s->mix_cap, s->rowsx - r0);
+    desc_mixed_chunk(s, r0, nr, d_out);
+    forms_mixed_chunk(s, r0, nr, want_e || want_f, want_v);
+    if (want_f) adjoint_mixed_chunk(s, r0, nr);
+  }
+  // with one chunk the workspace keeps the gradients of these positions for a later backward
+  if ((want_e || want_f) && s->rowsx <= s->mix_cap) s->gx_gen = s->pos_gen;
+}
+
 int flare_descriptors(flare_state* s, const double* x, const double* y, const double* z, float* d_out,
                       float* norm_out) {
   ARG(s, "null state");
@@ -708,9 +741,10 @@ int flare_descriptors(flare_state* s, const double* x, const double* y, const do
   }
   if (d_out || norm_out) {
     // the single-species rows come from the fused kernel run without quadratic forms
-    fused_quadratic_forms(s, 0, s->D1.p);
-    compute_descriptors_mixed(s);
-    export_descriptors(s, d_out, norm_out);
+    if (d_out) CHK(hipMemsetAsync(d_out, 0, (size_t)s->n_atoms * ND * sizeof(float), s->stream));
+    fused_quadratic_forms(s, FORMS_DESCRIPTORS, d_out);
+    mixed_rows(s, d_out, false, false, false);
+    export_norms(s, norm_out);
   }
   CHK(hipGetLastError());
   s->have_desc = true;
@@ -733,13 +767,8 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
     StageTimer tm(s, FLARE_T_QFORM1);
     fused_quadratic_forms(s, 1 | (want_v ? 2 : 0) | (want_f ? 4 : 0), nullptr);
   }
-  compute_descriptors_mixed(s);
-  {
-    StageTimer tm(s, FLARE_T_QFORMX);
-    mixed_quadratic_forms(s, true, want_v);
-  }
+  mixed_rows(s, nullptr, true, want_v, want_f);
   if (want_f) {
-    compute_forces(s, false);
     s->w_gen = s->pos_gen;
     s->g_gen = -1;          // the 144-wide gradients stayed on chip
   } else {
@@ -763,7 +792,11 @@ int flare_forces(flare_state* s, const double* cell_scale, float* fx, float* fy,
     return FLARE_E_STALE;
   }
   if (s->w_gen != s->pos_gen) {
-    compute_forces(s, true);
+    // the 144-wide rows from the gradients the energies left resident, the mixed rows
+    // recomputed chunk by chunk
+    adjoint_rows144(s);
+    if (s->gx_gen == s->pos_gen) adjoint_mixed_chunk(s, 0, s->rowsx);
+    else mixed_rows(s, nullptr, true, false, true);
     s->w_gen = s->pos_gen;
   }
   {
@@ -800,11 +833,7 @@ int flare_variance(flare_state* s, float* var_atom, float* sigma_atom, float* si
       StageTimer tm(s, FLARE_T_QFORM1);
       fused_quadratic_forms(s, 2, nullptr);
     }
-    compute_descriptors_mixed(s);
-    {
-      StageTimer tm(s, FLARE_T_QFORMX);
-      mixed_quadratic_forms(s, false, true);
-    }
+    mixed_rows(s, nullptr, false, true, false);
     s->v_gen = s->pos_gen;
   }
   {
@@ -822,23 +851,13 @@ int flare_quadratic_forms(flare_state* s, int bucket, int n_rows, const float* d
   ARG(bucket >= 0 && bucket < NBUCKET, "bucket must be 0..5");
   ARG(n_rows >= 0 && n_rows <= s->max_atoms, "n_rows must be in [0, max_atoms]");
   ARG(n_rows == 0 || (d_rows && e_out && var_out), "null device array");
-  const int w = bucket_width(bucket);
-  const size_t rows = (size_t)(n_rows + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
   // the resident descriptors of the last flare_descriptors call are overwritten
   s->have_desc = false;
-  s->v_gen = s->g_gen = s->w_gen = -1;
+  s->v_gen = s->g_gen = s->w_gen = s->gx_gen = -1;
   if (n_rows == 0) return FLARE_OK;
-  CHK(s->e_row.reserve(rows + 1));
-  CHK(s->v_row.reserve(rows + 1));
-  if (w == ND1) {
-    CHK(s->G1.reserve(rows * ND1 + 64));
+  if (bucket_width(bucket) == ND1) {
     forms_given_144(s, bucket, n_rows, d_rows, e_out, var_out);
   } else {
-    CHK(s->Dx.reserve(rows * ND + 64));
-    CHK(s->Yx.reserve(rows * ND + 64));
-    CHK(s->Gx.reserve(rows * ND + 64));
-    CHK(s->Px.reserve(rows * 4 + 64));
-    CHK(s->Px64.reserve(rows * 9 + 64));
     const int e = forms_given_544(s, bucket, n_rows, d_rows, e_out, var_out);
     if (e) CHK((hipError_t)e);
   }
@@ -858,11 +877,7 @@ int flare_uncertainty_monitor(flare_state* s, double threshold, float* sigma_max
       StageTimer tm(s, FLARE_T_QFORM1);
       fused_quadratic_forms(s, 2, nullptr);
     }
-    compute_descriptors_mixed(s);
-    {
-      StageTimer tm(s, FLARE_T_QFORMX);
-      mixed_quadratic_forms(s, false, true);
-    }
+    mixed_rows(s, nullptr, false, true, false);
     s->v_gen = s->pos_gen;
   }
   {
@@ -982,21 +997,11 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
     b += 4LL * 2 * ND1 * ND1 * sizeof(float);
     if (m->precision == FLARE_BF16_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * 8 * sizeof(uint16_t);
     if (m->precision == FLARE_FP8_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * sizeof(uint64_t);
-    if (m->precision == FLARE_BF16X6_SPLIT) b += 2 * 4LL * 5 * 9 * 3 * 64 * 8 * sizeof(uint16_t);
+    if (m->precision == FLARE_BF16X6_SPLIT) b += 4LL * 5 * 9 * 3 * 64 * 8 * sizeof(uint16_t);
     if (m->vchol) b += 2LL * ND * ND * sizeof(float);
+    if (m->var64) b += (4LL * ND1 * ND1 + 2LL * ND * ND) * sizeof(double);
   }
-  if (s) {
-    b += s->fixed_bytes;
-    b += s->d_grids.bytes() + s->d_struct_off.bytes() + s->bin_count.bytes() + s->bin_start.bytes() +
-         s->bin_fill.bytes() + s->blk_bucket.bytes() + s->blk_bucket_scan.bytes() + s->scan_scratch.bytes() +
-         s->atom_of_row1.bytes() + s->atom_of_rowx.bytes() + s->D1.bytes() + s->G1.bytes() + s->Dx.bytes() +
-         s->Gx.bytes() + s->Yx.bytes() + s->Px.bytes() + s->d_tasks.bytes() + s->d_first_task.bytes() +
-         s->red_e.bytes() + s->red_s.bytes() + s->slice_len.bytes() + s->slice_base.bytes() +
-         s->slot_atom.bytes() + s->slot_j.bytes() + s->slot_d0.bytes() +
-         s->slot_rev.bytes() + s->geom.bytes() + s->f_own.bytes() + s->w_in.bytes() + s->pair_cache.bytes() + s->red_w.bytes() +
-         s->cnt_row.bytes() + s->sid_row.bytes() + s->e_row.bytes() + s->v_row.bytes() +
-         s->row_out.bytes() + s->row_caller.bytes();
-  }
+  if (s) b += s->fixed_bytes + (long long)s->red_w.bytes();
   *bytes = b;
   return FLARE_OK;
 }

@@ -22,6 +22,7 @@ constexpr int NDX = NX * (LMAX + 1);     // 256: cross block
 constexpr int ND = 2 * ND1 + NDX;        // 544
 constexpr int NBUCKET = 6;
 constexpr int TILE_ROWS = 128;           // row padding of every bucket (GEMM tile height)
+constexpr int MIX_ROWS = 16384;          // mixed (544-wide) rows processed together, a multiple of TILE_ROWS
 
 // Environment class = OR of (1 << species) over listed neighbours: 1 H-only, 2 Pt-only,
 // 3 mixed, 0 none. Buckets: (H, H-only) (Pt, H-only) (H, Pt-only) (Pt, Pt-only)

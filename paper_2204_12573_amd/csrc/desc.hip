@@ -18,12 +18,16 @@ namespace {
 
 // One mixed row per 16 lanes (mixed.h): channel densities into LDS, then the 136 B2
 // channel pairs spread over the row's lanes (pair P = L + 16q), the norm summed in FP64
-// across the lanes, and the normalised row written as float4 per pair.
-__global__ __launch_bounds__(MTHREADS) void k_desc_mixed(SlotView v, int rows1, const int* __restrict__ atom_of_row,
-                                                         float* __restrict__ D, float* __restrict__ nrm_out) {
+// across the lanes, and the normalised row written as float4 per pair: into the chunk's
+// workspace D (row - r0) and, when exporting, into d_out at the atom's caller index.
+__global__ __launch_bounds__(MTHREADS) void k_desc_mixed(SlotView v, int rows1, int r0,
+                                                         const int* __restrict__ atom_of_row,
+                                                         const int* __restrict__ perm, float* __restrict__ D,
+                                                         float* __restrict__ nrm_out, float* __restrict__ d_out) {
   __shared__ __attribute__((aligned(16))) float cs[MROWS * MSTRIDE];
   const int rl = threadIdx.x >> 4, L = threadIdx.x & 15;
-  const int row = blockIdx.x * MROWS + rl;
+  const int local = blockIdx.x * MROWS + rl;
+  const int row = r0 + local;
   const int i = atom_of_row[row];
   float c[NLM];
 #pragma unroll
@@ -60,37 +64,36 @@ __global__ __launch_bounds__(MTHREADS) void k_desc_mixed(SlotView v, int rows1, 
   nrm2 = sum16d(nrm2);                    // the row's 16 lanes form one DPP row
   const float nrm = (float)sqrt(nrm2);
   const float scale = nrm > 0.f ? 1.f / nrm : 0.f;
-  float4* out = reinterpret_cast<float4*>(D + (size_t)row * ND);
+  float4* out = reinterpret_cast<float4*>(D + (size_t)local * ND);
+  float4* ext = d_out && i >= 0 ? reinterpret_cast<float4*>(d_out + (size_t)perm[i] * ND) : nullptr;
 #pragma unroll
   for (int q = 0; q < NQP; ++q) {
     const int P = L + 16 * q;
-    if (P < NPAIR) out[P] = make_float4(d[q].x * scale, d[q].y * scale, d[q].z * scale, d[q].w * scale);
+    if (P < NPAIR) {
+      const float4 o = make_float4(d[q].x * scale, d[q].y * scale, d[q].z * scale, d[q].w * scale);
+      out[P] = o;
+      if (ext) ext[P] = o;
+    }
   }
   if (L == 0 && i >= 0) nrm_out[i] = nrm;
 }
 
 constexpr int NTG = 256;
 
-// Internal position of each atom for this step, x + off in FP64, checked against its
-// reference position w (the wrapped position at the list build): the displacement since the
-// build must stay within half the skin. The displacement itself is kept in FP32: it is
-// smaller than half the skin, so its rounding is far below that of the pair vectors.
-__global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict__ perm,
-                                                    const double* __restrict__ x,
-                                                    const double* __restrict__ y,
-                                                    const double* __restrict__ z,
-                                                    const double* __restrict__ off,
-                                                    const double4* __restrict__ w,
-                                                    float4* __restrict__ dlt, double lim2,
-                                                    int* __restrict__ status) {
-  const int i = blockIdx.x * NTG + threadIdx.x;
-  if (i >= n) return;
-  const int a = perm[i];
-  const double4 wi = w[i];
-  const double d0 = (x[a] + off[i]) - wi.x;
-  const double d1 = (y[a] + off[(size_t)n + i]) - wi.y;
-  const double d2 = (z[a] + off[2 * (size_t)n + i]) - wi.z;
-  dlt[i] = make_float4((float)d0, (float)d1, (float)d2, 0.f);
+// Displacement of every atom since the list build, x - xb in FP64, in caller order (the
+// loads coalesced), stored in FP32 at the atom's internal index. It must stay within half
+// the skin; it is kept in FP32 because it is smaller than half the skin, so its rounding is
+// far below that of the pair vectors.
+__global__ __launch_bounds__(NTG) void k_disp(int n, const int* __restrict__ inv_perm,
+                                              const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ z, const double* __restrict__ xb,
+                                              float4* __restrict__ dlt, double lim2, int* __restrict__ status) {
+  const int a = blockIdx.x * NTG + threadIdx.x;
+  if (a >= n) return;
+  const double d0 = x[a] - xb[a];
+  const double d1 = y[a] - xb[(size_t)n + a];
+  const double d2 = z[a] - xb[2 * (size_t)n + a];
+  dlt[inv_perm[a]] = make_float4((float)d0, (float)d1, (float)d2, 0.f);
   const double d2s = d0 * d0 + d1 * d1 + d2 * d2;
   if (!(d2s <= lim2)) {
     if (!isfinite(d2s)) atomicOr(status, FLARE_FLAG_NONFINITE);
@@ -98,11 +101,13 @@ __global__ __launch_bounds__(NTG) void k_gather_pos(int n, const int* __restrict
   }
 }
 
-// Per-step geometry of every slot. The pair vector is split as
+// Per-step geometry of every listed pair. The pair vector is split as
 //   Delta = [(w_j - w_i) + s*L] + (delta_j - delta_i),
 // the bracket fixed at the list build (FP64, stored rounded to FP32 with the neighbour's
 // species in .w) and the displacements since the build added in FP32; kept when
 // |Delta|^2 < r_c^2, written as (u^, r) with the sign of r carrying the neighbour species.
+// One thread per slot (its loads independent of each other's); padding slots keep the zero
+// geometry the list build gave them.
 __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __restrict__ slot_atom,
                                               const int* __restrict__ slot_j,
                                               const float4* __restrict__ slot_d0,
@@ -111,45 +116,28 @@ __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __res
   const long long slot = (long long)blockIdx.x * NTG + threadIdx.x;
   if (slot >= nslots) return;
   const int i = slot_atom[slot];
+  if (i < 0) return;
+  const float4 d0 = slot_d0[slot];
+  const float4 dj = dlt[slot_j[slot]], di = dlt[i];
+  const float fx = d0.x + (dj.x - di.x), fy = d0.y + (dj.y - di.y), fz = d0.z + (dj.z - di.z);
+  const float r2 = fx * fx + fy * fy + fz * fz;
   float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (i >= 0) {
-    const float4 d0 = slot_d0[slot];
-    const float4 dj = dlt[slot_j[slot]], di = dlt[i];
-    const float fx = d0.x + (dj.x - di.x), fy = d0.y + (dj.y - di.y), fz = d0.z + (dj.z - di.z);
-    const float r2 = fx * fx + fy * fy + fz * fz;
-    if (r2 < rc2) {
-      const float r = sqrtf(r2);
-      const float inv = 1.f / r;
-      out = make_float4(fx * inv, fy * inv, fz * inv, d0.w * r);
-    }
+  if (r2 < rc2) {
+    const float r = sqrtf(r2);
+    const float inv = 1.f / r;
+    out = make_float4(fx * inv, fy * inv, fz * inv, d0.w * r);
   }
   geom[slot] = out;
 }
 
-__global__ __launch_bounds__(NTG) void k_export_desc(int n, const int* __restrict__ perm,
-                                                     const int* __restrict__ bucket,
-                                                     const int* __restrict__ row_of,
-                                                     const float* __restrict__ D1,
-                                                     const float* __restrict__ Dx,
-                                                     const float* __restrict__ nrm,
-                                                     float* __restrict__ d_out,
-                                                     float* __restrict__ norm_out) {
+// |d~| of every atom in caller order (0 for an atom without neighbours).
+__global__ __launch_bounds__(NTG) void k_export_norms(int n, const int* __restrict__ perm,
+                                                      const int* __restrict__ bucket,
+                                                      const float* __restrict__ nrm,
+                                                      float* __restrict__ norm_out) {
   const int i = blockIdx.x * NTG + threadIdx.x;
   if (i >= n) return;
-  const int a = perm[i];
-  const int b = bucket[i];
-  if (norm_out) norm_out[a] = b < 0 ? 0.f : nrm[i];
-  if (!d_out) return;
-  float* o = d_out + (size_t)a * ND;
-  for (int k = 0; k < ND; ++k) o[k] = 0.f;
-  if (b < 0) return;
-  const int r = row_of[i];
-  if (b < 4) {
-    const int start = bucket_env(b) == 0 ? 0 : ND - ND1;
-    for (int k = 0; k < ND1; ++k) o[start + k] = D1[(size_t)r * ND1 + k];
-  } else {
-    for (int k = 0; k < ND; ++k) o[k] = Dx[(size_t)r * ND + k];
-  }
+  norm_out[perm[i]] = bucket[i] < 0 ? 0.f : nrm[i];
 }
 
 }  // namespace
@@ -158,30 +146,30 @@ void gather_positions(flare_state* s, const double* x, const double* y, const do
   const int n = s->n_atoms;
   if (n == 0) return;
   const double lim = 0.5 * s->skin;
-  k_gather_pos<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, x, y, z, s->off, s->w, s->dlt,
-                                                           lim * lim, s->d_status);
+  k_disp<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->inv_perm, x, y, z, s->xb, s->dlt, lim * lim,
+                                                     s->d_status);
 }
 
 void pair_geometry(flare_state* s) {
   const long long ns = s->n_slots;
   if (ns == 0) return;
   const double rc = s->model->r_cut;
-  k_geom<<<(int)((ns + NTG - 1) / NTG), NTG, 0, s->stream>>>(ns, s->slot_atom.p, s->slot_j.p, s->slot_d0.p,
-                                                             s->dlt, (float)(rc * rc), s->geom.p);
+  k_geom<<<(int)((ns + NTG - 1) / NTG), NTG, 0, s->stream>>>(ns, s->slot_atom, s->slot_j, s->slot_d0, s->dlt,
+                                                             (float)(rc * rc), s->geom);
 }
 
-void compute_descriptors_mixed(flare_state* s) {
+void desc_mixed_chunk(flare_state* s, int r0, int nr, float* d_out) {
   const SlotView v = slot_view(s);
   StageTimer tm(s, FLARE_T_DESCX);
-  if (s->rowsx > 0)
-    k_desc_mixed<<<s->rowsx / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, s->atom_of_rowx.p, s->Dx.p, s->nrm);
+  if (nr > 0)
+    k_desc_mixed<<<nr / MROWS, MTHREADS, 0, s->stream>>>(v, s->rows1, r0, s->atom_of_rowx, s->perm, s->Dx, s->nrm,
+                                                         d_out);
 }
 
-void export_descriptors(flare_state* s, float* d_out, float* norm_out) {
+void export_norms(flare_state* s, float* norm_out) {
   const int n = s->n_atoms;
-  if (n == 0 || (!d_out && !norm_out)) return;
-  k_export_desc<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, s->bucket, s->row_of, s->D1.p,
-                                                            s->Dx.p, s->nrm, d_out, norm_out);
+  if (n == 0 || !norm_out) return;
+  k_export_norms<<<(n + NTG - 1) / NTG, NTG, 0, s->stream>>>(n, s->perm, s->bucket, s->nrm, norm_out);
 }
 
 }  // namespace flare

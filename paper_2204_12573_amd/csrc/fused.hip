@@ -60,7 +60,10 @@ struct FusedArgs {
   float* v_int;
   float* e_row;          // the same per row
   float* v_row;
-  float* D_out;          // optional [rows][144] normalised descriptors
+  float* D_out;          // optional normalised descriptors in caller order, [n][544]: the
+                         // row's block from component dstart of its bucket (others untouched)
+  const int* perm;       // internal -> caller index (with D_out)
+  int dstart[4];         // first component of each bucket's block in the 544 vector
 };
 
 // TRI: W = L lower-triangular, blocks of chunk kc with column block j > kc vanish. The
@@ -552,13 +555,14 @@ struct TileModel {
   const uint4* W6;
   const double* L64;
   float bsc;
+  int dstart;
 };
 __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
-  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.W6[0], a.L64[0], a.bscale[0]};
+  TileModel m{a.Wf[0], a.Wb[0], a.W8[0], a.W6[0], a.L64[0], a.bscale[0], a.dstart[0]};
 #pragma unroll
   for (int k = 1; k < 4; ++k)   // static indexing keeps the argument arrays out of scratch
     if (k < a.nbk && row0 >= a.row0[k] && row0 < a.row1[k])
-      m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.W6[k], a.L64[k], a.bscale[k]};
+      m = TileModel{a.Wf[k], a.Wb[k], a.W8[k], a.W6[k], a.L64[k], a.bscale[k], a.dstart[k]};
   return m;
 }
 
@@ -759,14 +763,16 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
     desc_phase<PREC, GIVEN>(a, As, rs, row0, t, c);
   }
   __syncthreads();
-  if (a.D_out) {
+  const TileModel tm = tile_model(a, row0);
+  if (!GIVEN && a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
       const int r = idx / ND1, k = idx % ND1;
+      const int i = atom_of<false>(a, row0 + r);
       const float nv = nrm_s[r];
-      a.D_out[(size_t)(row0 + r) * ND1 + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
+      if (i >= 0) a.D_out[(size_t)a.perm[i] * ND + tm.dstart + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
     }
   }
-  forms_phase<PREC, V64, GIVEN>(a, As, rs, row0, t, tile_model(a, row0));
+  forms_phase<PREC, V64, GIVEN>(a, As, rs, row0, t, tm);
   if (a.mode & 1) {
     __syncthreads();
     float* G = a.G + (size_t)tile * ND1 * FR;
@@ -869,21 +875,21 @@ void forms_given_144(flare_state* s, int bucket, int n, const float* d, float* e
   a.L64[0] = m->L64[bucket];
   a.bscale[0] = m->beta_scale[bucket];
   a.vchol = m->vchol ? 1 : 0;
-  a.G = s->G1.p;
+  a.G = s->G1;
   a.nrm = s->nrm;
   a.e_int = e;
   a.v_int = v;
-  a.e_row = s->e_row.p;
-  a.v_row = s->v_row.p;
+  a.e_row = s->e_row;
+  a.v_row = s->v_row;
   a.mode = 3;
   launch_tiles<true>(m, a, rows / FR, s->stream);
 }
 
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
-  if (s->rows1 == 0 || (!mode && !d_out)) return;
+  if (s->rows1 == 0 || (!(mode & (3 | FORMS_DESCRIPTORS)) && !d_out)) return;
   FusedArgs a{};
   a.v = slot_view(s);
-  a.aor = s->atom_of_row1.p;
+  a.aor = s->atom_of_row1;
   a.nbk = 4;
   for (int k = 0; k < 4; ++k) {
     const int padded = (s->bucket_count[k] + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
@@ -897,14 +903,16 @@ void fused_quadratic_forms(flare_state* s, int mode, float* d_out) {
     a.bscale[k] = s->model->beta_scale[k];
   }
   a.vchol = s->model->vchol ? 1 : 0;
-  a.G = s->G1.p;
-  a.f_own = s->f_own.p;
+  a.G = s->G1;
+  a.f_own = s->f_own;
   a.nrm = s->nrm;
   a.e_int = s->e_int;
   a.v_int = s->v_int;
-  a.e_row = s->e_row.p;
-  a.v_row = s->v_row.p;
+  a.e_row = s->e_row;
+  a.v_row = s->v_row;
   a.D_out = d_out;
+  a.perm = s->perm;
+  for (int k = 0; k < 4; ++k) a.dstart[k] = bucket_env(k) == 0 ? 0 : ND - ND1;
   const int ntiles = s->rows1 / FR;
   a.mode = mode & 3;
   if ((mode & 5) == 5) {

@@ -15,6 +15,7 @@
 // 128-bit LDS load: k-step t, lane group g uses k = 4g + t (the same map for A and B,
 // which is all a sum over k requires). LDS rows are padded to 20 floats, which spreads
 // the eight 16-byte reads of each lane octet over distinct banks.
+#include <algorithm>
 #include <type_traits>
 
 #include "state.h"
@@ -244,12 +245,14 @@ __global__ __launch_bounds__(256) void k_qform_finish(int rows, int mode, int nt
 // Variance of the mixed rows in the split forms, in FP64: V_i = |L_s^T d_i|^2 with the FP64
 // Cholesky factor of Sigma_s on v_mfma_f64_16x16x4_f64 (exact products of the FP32 row and
 // the FP64 factor, FP64 sums), so the near-cancelling d^T Sigma d keeps FP64 accuracy in the
-// form. A wave owns 16 rows and a group of four column blocks of Z = D L: for every K
-// chunk from the group's first block (L[k][n] = 0 for k < n) lane (m, q) supplies
-// D[row m][16 kc + 4 q + t] and the fragments L[16 kc + 4 q + t][16 cb + m] (fragment order
-// [cb][kc][t][lane]); four independent accumulators per k-step. Accumulator r of lane
-// (n, q) holds row q + 4 r of the block (the FP64 instruction's layout). The group's sum of
-// squares per row goes to P64[row][group]; k_var544_finish adds the groups in a fixed order.
+// form. A wave owns 32 rows (two 16-row blocks, which share every B fragment) and a group of
+// four column blocks of Z = D L: for every K chunk from the group's first block (L[k][n] = 0
+// for k < n) lane (m, q) supplies D[row m][16 kc + 4 q + t] and the fragments
+// L[16 kc + 4 q + t][16 cb + m] (fragment order [cb][kc][t][lane]); eight independent
+// accumulators per k-step, and the next chunk's fragments load while this one runs.
+// Accumulator r of lane (n, q) holds row q + 4 r of the block (the FP64 instruction's
+// layout). The group's sum of squares per row goes to P64[row][group]; k_var544_finish adds
+// the groups in a fixed order.
 constexpr int XCB = ND / 16;                 // 34 column blocks
 constexpr int XG = 4;                        // column blocks per wave
 constexpr int NXG = (XCB + XG - 1) / XG;     // 9 groups
@@ -266,38 +269,60 @@ struct VarArgs {
 __global__ __launch_bounds__(256) void k_var544_f64(VarArgs q) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, grp = lane >> 4;
-  const int task = blockIdx.x * 4 + wave;        // (16-row block, column group)
+  const int task = blockIdx.x * 4 + wave;        // (32-row block, column group)
   const int rb = task / NXG, g = task % NXG;
-  const int row0 = rb * 16;
+  const int row0 = rb * 32;
   if (row0 >= q.rows) return;
+  // the split between the two buckets falls on a 128-row boundary: one factor per wave
   const double* __restrict__ L = (row0 >= q.split_row ? q.L[1] : q.L[0]) + lane;
-  const float* __restrict__ drow = q.D + (size_t)(row0 + l16) * ND + 4 * grp;
-  d4 acc[XG];
+  const float* __restrict__ d0 = q.D + (size_t)(row0 + l16) * ND + 4 * grp;
+  const float* __restrict__ d1 = d0 + (size_t)16 * ND;
+  d4 acc[2][XG];
 #pragma unroll
-  for (int u = 0; u < XG; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int u = 0; u < XG; ++u) acc[i][u] = d4{0.0, 0.0, 0.0, 0.0};
   const int cb0 = g * XG;
-  for (int kc = cb0; kc < XCB; ++kc) {
-    const float4 a = *reinterpret_cast<const float4*>(drow + kc * 16);
-    const double av[4] = {(double)a.x, (double)a.y, (double)a.z, (double)a.w};
-    double b[XG][4];
+  auto load_b = [&](int kc, double (&b)[XG][4]) {
 #pragma unroll
     for (int u = 0; u < XG; ++u)
 #pragma unroll
       for (int t = 0; t < 4; ++t)
         b[u][t] = (cb0 + u < XCB && cb0 + u <= kc) ? L[(((size_t)(cb0 + u) * XCB + kc) * 4 + t) * 64] : 0.0;
+  };
+  double bA[XG][4], bB[XG][4];
+  load_b(cb0, bA);
+  for (int kc = cb0; kc < XCB; kc += 2) {
+    // two chunks per trip, one B buffer each; the next one's loads ahead of the MFMAs
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int half = 0; half < 2; ++half) {
+      const int k = kc + half;
+      if (k >= XCB) break;
+      double (&cur)[XG][4] = half ? bB : bA;
+      double (&nxt)[XG][4] = half ? bA : bB;
+      if (k + 1 < XCB) load_b(k + 1, nxt);
+      const float4 a0 = *reinterpret_cast<const float4*>(d0 + k * 16);
+      const float4 a1 = *reinterpret_cast<const float4*>(d1 + k * 16);
+      const double av[2][4] = {{a0.x, a0.y, a0.z, a0.w}, {a1.x, a1.y, a1.z, a1.w}};
 #pragma unroll
-      for (int u = 0; u < XG; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], b[u][t], acc[u], 0, 0, 0);
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < XG; ++u)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            acc[i][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][t], cur[u][t], acc[i][u], 0, 0, 0);
+    }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    double ss = 0.0;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int u = 0; u < XG; ++u) ss = fma(acc[u][r], acc[u][r], ss);
-    ss = sum16d(ss);
-    if (l16 == 0) q.P64[(size_t)(row0 + grp + 4 * r) * NXG + g] = ss;
-  }
+    for (int r = 0; r < 4; ++r) {
+      double ss = 0.0;
+#pragma unroll
+      for (int u = 0; u < XG; ++u) ss = fma(acc[i][u][r], acc[i][u][r], ss);
+      ss = sum16d(ss);
+      if (l16 == 0) q.P64[(size_t)(row0 + 16 * i + grp + 4 * r) * NXG + g] = ss;
+    }
 }
 
 // V of each mixed row from its group sums (fixed order), rounded to FP32 once.
@@ -323,22 +348,26 @@ void var544_f64(flare_state* s, const float* D, int rows, int split_row, const i
   q.split_row = split_row;
   q.L[0] = s->model->Lx64[0];
   q.L[1] = s->model->Lx64[1];
-  q.P64 = s->Px64.p;
-  const int tasks = rows / 16 * NXG;
+  q.P64 = s->Px64;
+  const int tasks = rows / 32 * NXG;
   k_var544_f64<<<(tasks + 3) / 4, 256, 0, s->stream>>>(q);
-  k_var544_finish<<<(rows + 255) / 256, 256, 0, s->stream>>>(rows, s->Px64.p, aor, n_given, v_int, v_row);
+  k_var544_finish<<<(rows + 255) / 256, 256, 0, s->stream>>>(rows, s->Px64, aor, n_given, v_int, v_row);
 }
 
 }  // namespace
 
-// Quadratic forms of the mixed-environment rows (544-wide), split over four column tiles.
-// In the split forms the variance runs in FP64 (var544_f64) and the tiles cover beta only.
-void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
-  const int rows = s->rowsx;
-  if ((!want_e && !want_v) || rows == 0) return;
+// Quadratic forms of the mixed-environment rows [r0, r0 + nr) (544-wide, one chunk of the
+// workspace: Dx row r - r0), split over four column tiles. In the split forms the variance
+// runs in FP64 (var544_f64) and the tiles cover beta only.
+void forms_mixed_chunk(flare_state* s, int r0, int nr, bool want_e, bool want_v) {
+  if ((!want_e && !want_v) || nr == 0) return;
+  StageTimer tm(s, FLARE_T_QFORMX);
   const flare_model* m = s->model;
+  const int* aor = s->atom_of_rowx + r0;
+  float* e_row = s->e_row + s->rows1 + r0;
+  float* v_row = s->v_row + s->rows1 + r0;
   if (want_v && m->var64) {
-    var544_f64(s, s->Dx.p, rows, s->bucket_row0[5], s->atom_of_rowx.p, 0, s->v_int, s->v_row.p + s->rows1);
+    var544_f64(s, s->Dx, nr, s->bucket_row0[5] - r0, aor, 0, s->v_int, v_row);
     want_v = false;
     if (!want_e) return;
   }
@@ -349,23 +378,22 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
   for (int k = 0; k < 2; ++k) {
     const int bk = 4 + k;
     const int padded = (s->bucket_count[bk] + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
-    q.row0[k] = s->bucket_row0[bk];
-    q.row1[k] = s->bucket_row0[bk] + padded;
+    q.row0[k] = s->bucket_row0[bk] - r0;     // chunk-local rows
+    q.row1[k] = s->bucket_row0[bk] + padded - r0;
     q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)ND * ND);
   }
   // with Cholesky factors the Sigma columns come from L (V = |d L|^2)
   q.sumsq = m->vchol ? 1 : 0;
   for (int k = 0; k < 2; ++k) q.L[k] = m->Lx[k];
-  q.D = s->Dx.p;
-  q.aor = s->atom_of_rowx.p;
-  q.Y = s->Yx.p;
-  q.P = s->Px.p;
+  q.D = s->Dx;
+  q.aor = aor;
+  q.Y = s->Yx;
+  q.P = s->Px;
   const int parts = ((mode & 1) ? 1 : 0) + ((mode & 2) ? 1 : 0);
   const int ntiles = 2 * parts;   // 272 columns per tile
-  k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
-  k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p,
-                                                        s->atom_of_rowx.p, 0, s->nrm, s->Gx.p, s->e_int, s->v_int,
-                                                        s->e_row.p + s->rows1, s->v_row.p + s->rows1);
+  k_qform<ND, 17, 1><<<dim3(nr / 64, ntiles), NTQ, 0, s->stream>>>(q);
+  k_qform_finish<<<(nr + 3) / 4, 256, 0, s->stream>>>(nr, mode, ntiles, s->Dx, s->Yx, s->Px, aor, 0, s->nrm, s->Gx,
+                                                      s->e_int, s->v_int, e_row, v_row);
 }
 
 // Quadratic forms of given 544-wide vectors (rows 0 .. n-1) with the model of mixed bucket
@@ -373,37 +401,40 @@ void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v) {
 // the same kernels as the descriptor path. The vectors are copied into the state's padded
 // row buffer Dx (zeros past n); scratch: Yx, Px, Px64, Gx, e_row, v_row, nrm.
 int forms_given_544(flare_state* s, int bucket, int n, const float* d, float* e, float* v) {
-  const int rows = (n + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
-  if (rows == 0) return 0;
   const flare_model* m = s->model;
-  hipError_t err = hipMemcpyAsync(s->Dx.p, d, (size_t)n * ND * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
-  if (err == hipSuccess)
-    err = hipMemsetAsync(s->Dx.p + (size_t)n * ND, 0, (size_t)(rows - n) * ND * sizeof(float), s->stream);
-  if (err != hipSuccess) return (int)err;
-  // the rows of one bucket: the Pt-centre model from row split = 0 when bucket 5
-  const int split = bucket == 5 ? 0 : rows;
-  QArgs q{};
-  q.nbk = 1;
-  q.row0[0] = 0;
-  q.row1[0] = rows;
-  q.W[0] = m->W[bucket];
-  q.L[0] = m->Lx[bucket - 4];
-  q.sumsq = m->vchol ? 1 : 0;
-  q.D = s->Dx.p;
-  q.aor = nullptr;
-  q.Y = s->Yx.p;
-  q.P = s->Px.p;
-  int mode = 3;
-  if (m->var64) {
-    var544_f64(s, s->Dx.p, rows, split, nullptr, n, v, s->v_row.p);
-    mode = 1;
+  for (int c0 = 0; c0 < n; c0 += s->mix_cap) {
+    const int nc = std::min(s->mix_cap, n - c0);
+    const int rows = (nc + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+    hipError_t err = hipMemcpyAsync(s->Dx, d + (size_t)c0 * ND, (size_t)nc * ND * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s->stream);
+    if (err == hipSuccess && rows > nc)
+      err = hipMemsetAsync(s->Dx + (size_t)nc * ND, 0, (size_t)(rows - nc) * ND * sizeof(float), s->stream);
+    if (err != hipSuccess) return (int)err;
+    // every row of the chunk has the model of `bucket`: the Pt-centre factor from row 0 for
+    // bucket 5, the H-centre one throughout for bucket 4
+    const int split = bucket == 5 ? 0 : rows;
+    QArgs q{};
+    q.nbk = 1;
+    q.row0[0] = 0;
+    q.row1[0] = rows;
+    q.W[0] = m->W[bucket];
+    q.L[0] = m->Lx[bucket - 4];
+    q.sumsq = m->vchol ? 1 : 0;
+    q.D = s->Dx;
+    q.aor = nullptr;
+    q.Y = s->Yx;
+    q.P = s->Px;
+    int mode = 3;
+    if (m->var64) {
+      var544_f64(s, s->Dx, rows, split, nullptr, nc, v + c0, s->v_row);
+      mode = 1;
+    }
+    q.mode = mode;
+    const int ntiles = 2 * (mode == 3 ? 2 : 1);
+    k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
+    k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx, s->Yx, s->Px, nullptr, nc,
+                                                          s->nrm, s->Gx, e + c0, v + c0, s->e_row, s->v_row);
   }
-  q.mode = mode;
-  if (mode == 1) q.W[0] = m->W[bucket];
-  const int ntiles = 2 * (mode == 3 ? 2 : 1);
-  k_qform<ND, 17, 1><<<dim3(rows / 64, ntiles), NTQ, 0, s->stream>>>(q);
-  k_qform_finish<<<(rows + 3) / 4, 256, 0, s->stream>>>(rows, mode, ntiles, s->Dx.p, s->Yx.p, s->Px.p, nullptr, n,
-                                                        s->nrm, s->Gx.p, e, v, s->e_row.p, s->v_row.p);
   return 0;
 }
 

@@ -298,10 +298,10 @@ void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float
   if (n == 0) return;
   const int rows = s->rows1 + s->rowsx;
   if (rows > 0)
-    k_outputs_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, fx != nullptr, s->slice_base.p, s->f_own.p,
-                                                              s->w_in.p, s->cnt_row.p, s->sid_row.p, cell_scale,
-                                                              s->e_row.p, s->row_out.p);
-  k_outputs_atoms<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->row_caller.p, s->row_out.p, s->v_row.p, e_atom, fx,
+    k_outputs_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, fx != nullptr, s->slice_base, s->f_own,
+                                                              s->w_in, s->cnt_row, s->sid_row, cell_scale,
+                                                              s->e_row, s->row_out);
+  k_outputs_atoms<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->row_caller, s->row_out, s->v_row, e_atom, fx,
                                                            fy, fz, var_atom, sigma_atom);
 }
 
@@ -309,20 +309,20 @@ void reduce_cells(flare_state* s, double* e_struct, float* sigma_max, float thr,
   if (!e_struct && !sigma_max && !run_max) return;
   const int nt = (int)s->tasks.size();
   if (nt == 0) return;
-  k_reduce_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->e_int, s->v_int, e_struct != nullptr,
-                                           sigma_max != nullptr || run_max != nullptr, s->red_e.p, s->red_s.p);
+  k_reduce_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks, s->bucket, s->e_int, s->v_int, e_struct != nullptr,
+                                           sigma_max != nullptr || run_max != nullptr, s->red_e, s->red_s);
   if (s->n_struct > 0)
-    k_reduce_cells<<<s->n_struct, NC, 0, s->stream>>>(s->red_e.p, s->red_s.p, s->d_first_task.p, e_struct,
+    k_reduce_cells<<<s->n_struct, NC, 0, s->stream>>>(s->red_e, s->red_s, s->d_first_task, e_struct,
                                                       sigma_max, thr, run_max, over, s->d_status);
 }
 
 void virial_cells(flare_state* s, double* virial_struct, double* red_w) {
   const int nt = (int)s->tasks.size();
   if (nt > 0)
-    k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, s->bucket, s->row_of, s->rows1, s->slice_base.p,
-                                             s->geom.p, s->w_in.p, s->nl_cnt, red_w);
+    k_virial_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks, s->bucket, s->row_of, s->rows1, s->slice_base,
+                                             s->geom, s->w_in, s->nl_cnt, red_w);
   if (s->n_struct > 0)
-    k_virial_cells<<<s->n_struct, NC, 0, s->stream>>>(red_w, s->d_first_task.p, virial_struct);
+    k_virial_cells<<<s->n_struct, NC, 0, s->stream>>>(red_w, s->d_first_task, virial_struct);
 }
 
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,

@@ -29,19 +29,6 @@ struct DevBuf {
   }
 };
 
-// Read-only view of the per-step pair data, passed to kernels by value.
-struct PairView {
-  int n;                              // atoms
-  const int* sp;                      // species
-  const int* sid;                     // cell of each atom
-  const CellGrid* grids;              // per cell
-  const int* nl_off;                  // [n+1]
-  const int* nl_j;                    // neighbour (internal index)
-  const int32_t* nl_s;                // packed image shift
-  float rc;
-  double rc2;
-};
-
 // HIP-event stage timers (enabled on demand; see flare_timers_enable).
 struct Timers {
   bool on = false;
@@ -68,6 +55,14 @@ struct SlotView {
 __host__ __device__ inline int slot_of(const int* slice_base, int R, int k) {
   return (slice_base[R >> 5] + k) * 32 + (R & 31);
 }
+
+// Caller-order record of one atom written by the first pass of the list build and read
+// once, by the bin-sorted gather: one 64-byte line per atom.
+struct __attribute__((aligned(64))) CallerRec {
+  double wx, wy, wz;         // wrapped position
+  double ox, oy, oz;         // image offset: wrapped = x + offset
+  int bin, cell, pad0, pad1;
+};
 
 // Reduction task: a contiguous internal atom range of one cell.
 struct RedTask {
@@ -130,6 +125,8 @@ struct flare_state {
   long long v_gen = -1;      // positions the variances were computed for
   long long g_gen = -1;      // positions the energy gradients were computed for
   long long w_gen = -1;      // positions the per-pair adjoint terms were computed for
+  long long gx_gen = -1;     // positions the mixed rows' gradients in the workspace are for
+                             // (only when all mixed rows fit one chunk)
   long long fixed_bytes = 0; // device bytes of the fixed-size arrays
   int n_atoms = 0;
   int n_struct = 0;
@@ -146,6 +143,16 @@ struct flare_state {
   std::vector<flare::RedTask> tasks;
   std::vector<int> first_task;
 
+  // ---- capacities, fixed at flare_state_create (no device allocation after it) ----
+  int row_cap = 0;           // rows of both width classes: max_atoms + bucket padding
+  int slice_cap = 0;         // row_cap / 32
+  long long slot_cap = 0;    // slots of the sliced pair layout
+  int bin_cap = 0;           // cell-list bins over all cells of a build
+  int cell_cap = 0;          // cells (structures) per build
+  int task_cap = 0;          // reduction tasks
+  int nblk_cap = 0;          // 256-atom blocks
+  int mix_cap = 0;           // mixed rows processed together (the 544-wide workspace)
+
   // ---- per-atom device arrays (capacity max_atoms) ----
   int* perm = nullptr;       // internal -> caller index
   int* sp = nullptr;         // species, internal order
@@ -156,55 +163,71 @@ struct flare_state {
   int* row_of = nullptr;     // row of each internal atom inside its width class (-1: none)
   int* nl_cnt = nullptr;
   int* nl_off = nullptr;     // [max_atoms + 1]
-  double4* w = nullptr;      // [N] wrapped positions at the list build (x, y, z, 0)
+  double4* w = nullptr;      // [N] wrapped positions at the list build (x, y, z, species)
+  float4* wf = nullptr;      // [N] the same rounded to FP32 (species in .w), for the search's first test
   double* off = nullptr;     // [3][N] image offset: internal position = x + off
-  float4* dlt = nullptr;     // [N] displacement of the current step from w, FP32 (x, y, z, 0)
+  float4* dlt = nullptr;     // [N] displacement of the current step from the build, FP32 (x, y, z, 0)
+  double* xb = nullptr;      // [3][N] positions at the list build, caller order
+  int* inv_perm = nullptr;   // [N] caller -> internal index
   float* nrm = nullptr;      // |d~| per internal atom
   float* e_int = nullptr;
   float* v_int = nullptr;
-  // caller-order temporaries of the list build
-  int* o_bin = nullptr;
-  int* o_sid = nullptr;
-  double* o_w = nullptr;     // [3][N]
-  double* o_off = nullptr;   // [3][N]
+  flare::CallerRec* crec = nullptr;   // list build: caller-order wrapped position, image offset, bin, cell
   int* sorted = nullptr;     // bin-sorted caller indices
+  int* row_caller = nullptr; // [N] row of each atom, caller order (-1: none)
+  int* slot0 = nullptr;      // [N] slot of each internal atom's first pair (-1: no row)
+  int2* pair_cache = nullptr;  // list build: first PAIR_CACHE pairs of each atom, [k][N]
 
-  // ---- per-pair ----
+  // ---- per-pair (capacity max_pairs) ----
   int* nl_j = nullptr;       // internal index of the neighbour
   int32_t* nl_s = nullptr;   // packed image shift
-  int* nl_rev = nullptr;     // index of the reverse pair (j, i, -s) in j's list
-  int* slot_of_pair = nullptr;
+  int* nl_rev = nullptr;     // position of the reverse pair (j, i, -s) inside j's list
 
-  // ---- grow-at-build buffers ----
-  flare::DevBuf<flare::CellGrid> d_grids;
-  flare::DevBuf<int> d_struct_off;
-  flare::DevBuf<int> bin_count, bin_start, bin_fill;
-  flare::DevBuf<int> blk_bucket, blk_bucket_scan;   // [6][nblk]
-  flare::DevBuf<int> scan_scratch;
-  flare::DevBuf<int> atom_of_row1, atom_of_rowx;
-  flare::DevBuf<float> D1, G1, Dx, Gx, Yx, Px;       // descriptors, gradients, mixed Y, partials
-  flare::DevBuf<double> Px64;                        // mixed rows, split forms: FP64 variance partials
-  flare::DevBuf<flare::RedTask> d_tasks;
-  flare::DevBuf<int> d_first_task;                   // [n_struct + 1] task range of each cell
-  flare::DevBuf<double> red_e;                       // [tasks][2] (sum, compensation)
-  flare::DevBuf<float> red_s;                        // [tasks]
-  // sliced pair layout (grown at list builds)
+  // ---- per cell, bin, block ----
+  flare::CellGrid* d_grids = nullptr;   // [cell_cap]
+  int* d_struct_off = nullptr;          // [cell_cap + 1]
+  int* bin_count = nullptr;             // [bin_cap + 1]
+  int* bin_start = nullptr;
+  int* bin_fill = nullptr;
+  int* blk_bucket = nullptr;            // [NKEY][nblk_cap]
+  int* blk_bucket_scan = nullptr;
+  int* scan_scratch = nullptr;
+  flare::RedTask* d_tasks = nullptr;    // [task_cap]
+  int* d_first_task = nullptr;          // [cell_cap + 1] task range of each cell
+  double* red_e = nullptr;              // [task_cap][2] (sum, compensation)
+  float* red_s = nullptr;               // [task_cap]
+
+  // ---- per row (capacity row_cap; 144-wide rows, then mixed rows) ----
+  int* atom_of_row1 = nullptr;
+  int* atom_of_rowx = nullptr;
+  int* cnt_row = nullptr;               // pairs
+  int* sid_row = nullptr;               // cell
+  float* e_row = nullptr;               // per step: e_i, V_i
+  float* v_row = nullptr;
+  float4* row_out = nullptr;            // per step: (F_i, e_i) in row order
+  float4* f_own = nullptr;              // per row: sum of de_i/dDelta over its own pairs
+  float* G1 = nullptr;                  // [row_cap / 128][144][128] gradients (energies without forces)
+  // mixed rows, one chunk of mix_cap rows at a time
+  float* Dx = nullptr;                  // [mix_cap][544] descriptors
+  float* Gx = nullptr;                  // gradients
+  float* Yx = nullptr;                  // D beta
+  float* Px = nullptr;                  // [mix_cap][4] partial row sums
+  double* Px64 = nullptr;               // [mix_cap][9] FP64 variance partials (split forms)
+
+  // ---- sliced pair layout (capacity slot_cap) ----
   int n_slices = 0;
   long long n_slots = 0;
-  flare::DevBuf<int> slice_len, slice_base;          // [slices (+1)]
-  flare::DevBuf<int> slot_atom, slot_j, slot_rev;
-  flare::DevBuf<float4> slot_d0;                     // per slot: (w_j - w_i) + s*L in FP32, neighbour species sign
-  flare::DevBuf<float4> geom;                        // per slot, per step
-  flare::DevBuf<float4> f_own;                       // per row: sum of de_i/dDelta over its own pairs
-  flare::DevBuf<float4> w_in;                        // per slot: w of the reverse pair
-  flare::DevBuf<int2> pair_cache;                    // list build: first pairs of each atom
-  // per row (144-wide rows, then mixed rows), so that the output pass reads them in row order
-  flare::DevBuf<int> cnt_row, sid_row;               // pairs, cell
-  flare::DevBuf<float> e_row, v_row;                 // per step: e_i, V_i
-  flare::DevBuf<float4> row_out;                     // per step: (F_i, e_i) in row order
-  flare::DevBuf<int> row_caller;                     // [N] row of each atom, caller order (-1: none)
+  int* slice_len = nullptr;             // [slice_cap + 1]
+  int* slice_base = nullptr;
+  int* slot_atom = nullptr;              // row's atom (padding: -1)
+  int* slot_j = nullptr;
+  int* slot_rev = nullptr;
+  float4* slot_d0 = nullptr;            // per slot: (w_j - w_i) + s*L in FP32, neighbour species sign
+  float4* geom = nullptr;               // per slot, per step
+  float4* w_in = nullptr;               // per slot: w of the reverse pair
+
   // virial task sums (allocated at the first flare_virial call)
-  flare::DevBuf<double> red_w;                       // [tasks][9]
+  flare::DevBuf<double> red_w;          // [tasks][9]
 
   flare::Timers timers;
 
@@ -212,12 +235,13 @@ struct flare_state {
   int* d_status = nullptr;   // [0] caller-visible status word (sticky), [1] list-build checks
   int flags_at_build = 0;    // word [0] as the last list build found it
   int flags_pending = 0;     // flags moved to the host by list builds, not yet returned by flare_status
-  int* d_info = nullptr;     // small device results read at list builds
-  int* h_info = nullptr;     // pinned host copy
+  int* d_layout = nullptr;   // list build: sizes formed on the device (see nlist.hip)
+  int* h_info = nullptr;     // pinned host copy of d_layout, read once per build
+  char* h_stage = nullptr;   // pinned staging of the per-cell host data of a build
+  size_t h_stage_bytes = 0;
 };
 
 namespace flare {
-PairView pair_view(const flare_state* s);
 SlotView slot_view(const flare_state* s);
 
 // Records the stage's start event on construction and its stop event on destruction.
@@ -228,20 +252,33 @@ struct StageTimer {
   StageTimer(flare_state* st, int stg);
   ~StageTimer();
 };
+// list-build constants for the capacities of a state (nlist.hip)
+int list_key_count();      // sort keys of the row order (per 256-atom block)
+int list_pair_cache();     // pairs per atom kept by the counting pass
+int list_layout_words();   // ints of the device layout record
 // launchers (nlist.hip, desc.hip, qform.hip, adjoint.hip, reduce.hip)
 int build_list(flare_state* s, const double* x, const double* y, const double* z,
                const int32_t* species);
 void gather_positions(flare_state* s, const double* x, const double* y, const double* z);
 void pair_geometry(flare_state* s);
-void compute_descriptors_mixed(flare_state* s);
-void export_descriptors(flare_state* s, float* d_out, float* norm_out);
+// 144-wide rows: mode bit 0 energies and gradients, bit 1 variances, bit 2 forces in the same
+// kernel, FORMS_DESCRIPTORS the descriptors (and norms) alone; d_out (caller order, [n][544],
+// zeroed by the caller) receives their descriptors
+constexpr int FORMS_DESCRIPTORS = 8;
 void fused_quadratic_forms(flare_state* s, int mode, float* d_out);
-void mixed_quadratic_forms(flare_state* s, bool want_e, bool want_v);
+// mixed rows [r0, r0 + nr) of the 544-wide class (nr <= mix_cap, r0 a multiple of mix_cap),
+// in the chunk workspace Dx/Yx/Gx/Px: descriptors (and their export to caller order),
+// quadratic forms, adjoint terms
+void desc_mixed_chunk(flare_state* s, int r0, int nr, float* d_out);
+void forms_mixed_chunk(flare_state* s, int r0, int nr, bool want_e, bool want_v);
+void adjoint_mixed_chunk(flare_state* s, int r0, int nr);
+// |d~| of every atom in caller order
+void export_norms(flare_state* s, float* norm_out);
 // quadratic forms of given vectors with the model of one bucket (fused.hip, qform.hip)
 void forms_given_144(flare_state* s, int bucket, int n, const float* d, float* e, float* v);
 int forms_given_544(flare_state* s, int bucket, int n, const float* d, float* e, float* v);
-// adjoint terms of the 544-wide rows, and of the 144-wide rows if rows144 (from G1)
-void compute_forces(flare_state* s, bool rows144);
+// adjoint terms of the 144-wide rows from G1 (separate from the energies)
+void adjoint_rows144(flare_state* s);
 void finalize_outputs(flare_state* s, float* e_atom, float* fx, float* fy, float* fz,
                       float* var_atom, float* sigma_atom, const double* cell_scale = nullptr);
 // per-cell E and max sigma; with run_max, the uncertainty monitor (threshold thr, counts in over)

@@ -235,10 +235,10 @@ void nvt_first(flare_state* s, double* x, double* y, double* z, double* vx, doub
                const float* fx, const float* fy, const float* fz, const int32_t* species, const double* masses,
                double dt, double t0, double tau, double* thermo) {
   const int nc = s->n_struct, nt = (int)s->tasks.size();
-  if (nc > 0) k_nh_open<<<(nc + NC - 1) / NC, NC, 0, s->stream>>>(nc, s->d_struct_off.p, thermo, dt, t0, tau);
+  if (nc > 0) k_nh_open<<<(nc + NC - 1) / NC, NC, 0, s->stream>>>(nc, s->d_struct_off, thermo, dt, t0, tau);
   const double h0 = 0.5 * dt * KAPPA / masses[0], h1 = 0.5 * dt * KAPPA / masses[1];
   if (nt > 0)
-    k_nvt_first<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, x, y, z, vx, vy, vz, fx, fy, fz, species, thermo, h0, h1,
+    k_nvt_first<<<nt, NT, 0, s->stream>>>(s->d_tasks, x, y, z, vx, vy, vz, fx, fy, fz, species, thermo, h0, h1,
                                           dt);
 }
 
@@ -248,10 +248,10 @@ void nvt_second(flare_state* s, double* vx, double* vy, double* vz, const float*
   const int nc = s->n_struct, nt = (int)s->tasks.size();
   const double h0 = 0.5 * dt * KAPPA / masses[0], h1 = 0.5 * dt * KAPPA / masses[1];
   if (nt > 0)
-    k_nvt_second<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, vx, vy, vz, fx, fy, fz, species, thermo, h0, h1, masses[0],
-                                           masses[1], dt, update ? 1 : 0, s->red_e.p);
+    k_nvt_second<<<nt, NT, 0, s->stream>>>(s->d_tasks, vx, vy, vz, fx, fy, fz, species, thermo, h0, h1, masses[0],
+                                           masses[1], dt, update ? 1 : 0, s->red_e);
   if (nc > 0)
-    k_nh_close<<<nc, NC, 0, s->stream>>>(s->red_e.p, s->d_first_task.p, s->d_struct_off.p, thermo, dt, t0, tau,
+    k_nh_close<<<nc, NC, 0, s->stream>>>(s->red_e, s->d_first_task, s->d_struct_off, thermo, dt, t0, tau,
                                          update ? 1 : 0);
 }
 
@@ -259,11 +259,11 @@ void coordination(flare_state* s, const double* x, const double* y, const double
                   const int32_t* prev, int64_t* events) {
   const int n = s->n_atoms, nc = s->n_struct, nt = (int)s->tasks.size();
   if (n > 0)
-    k_coord<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->sp, s->sid, s->d_grids.p, x, y, z, s->off,
+    k_coord<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->perm, s->sp, s->sid, s->d_grids, x, y, z, s->off,
                                                      s->nl_off, s->nl_j, s->nl_s, coord);
   if (prev && events) {
-    if (nt > 0) k_events_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks.p, prev, coord, s->red_e.p);
-    if (nc > 0) k_events_cells<<<(nc + NC - 1) / NC, NC, 0, s->stream>>>(nc, s->red_e.p, s->d_first_task.p, events);
+    if (nt > 0) k_events_tasks<<<nt, NT, 0, s->stream>>>(s->d_tasks, prev, coord, s->red_e);
+    if (nc > 0) k_events_cells<<<(nc + NC - 1) / NC, NC, 0, s->stream>>>(nc, s->red_e, s->d_first_task, events);
   }
 }
 

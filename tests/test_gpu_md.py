@@ -57,3 +57,28 @@ def test_displaced_interval_raises_at_the_rebuild():
     assert ev.interval_status() & Bd.FLAG_DISPLACED
     assert ev.status() & Bd.FLAG_DISPLACED
     assert ev.status() == 0      # read and cleared
+
+
+def test_state_memory_fixed_across_rebuilds():
+    """Every buffer of a state is allocated at flare_state_create: 20 NVE steps with a list
+    rebuild every 5 change neither the state's device memory (flare_memory_bytes) nor the
+    device's free memory (no allocation by the library, and none by the driver loop)."""
+    b = S.config_cells(n_cells=3, seed=2)
+    beta, sigma = S.random_model(DEFAULT.n_desc)
+    model = engine.Model(beta, sigma)
+    ev = engine.Evaluator(model, max_atoms=b.n, max_pairs=64 * b.n)
+    held = ev.memory_bytes(with_model=False)
+    p, s = engine.to_device(b.pos, b.species)
+    v = torch.zeros_like(p)
+    print("case: memory across 20 NVE steps, 3 cells", flush=True)
+    md = engine.MD(ev, p, v, s, b.offsets, b.boxes, dt=0.5, skin=0.2, rebuild=5)
+    for _ in range(5):
+        md.step()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(20):
+        md.step()
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    assert ev.memory_bytes(with_model=False) == held
+    assert ev.status() == 0

@@ -94,6 +94,27 @@ def test_tiny_box_below_list_radius(model):
     _compare(res, ref)
 
 
+def test_list_radius_decisions_in_a_tall_box(model):
+    # pairs placed at the list radius to within 1e-15 .. 1e-4 relative, in a cell 1000 A tall
+    # (large coordinates: the largest FP32 rounding of positions, which the search's first
+    # test works with), some reaching across the periodic faces: every decision must be the
+    # FP64 one, as the oracle takes it
+    beta, sigma = model
+    rng = np.random.default_rng(31)
+    box = np.array([24.0, 21.0, 1000.0])
+    deltas = [0.0] + [sg * 10.0 ** -e for e in (15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4) for sg in (1, -1)]
+    a = rng.uniform(0, 1, (3 * len(deltas), 3)) * box
+    u = rng.standard_normal(a.shape)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    d = np.tile(deltas, 3)
+    b = a + (4.7 * (1.0 + d))[:, None] * u
+    pos = np.concatenate([a, b])
+    species = rng.integers(0, 2, len(pos)).astype(np.int32)
+    print(f"case: {len(a)} pairs at the list radius, 1000 A cell", flush=True)
+    res = gpu_eval(pos, species, box, beta, sigma)
+    _list_equal(res, pos, box, 4.7)
+
+
 def test_batch_of_cells(model):
     beta, sigma = model
     b = S.config_cells(n_cells=12, seed=2)
