@@ -160,13 +160,17 @@ def md_throughput(engine, torch, st, beta, sigma, steps, warmup, precision):
     for _ in range(warmup):
         md.step()
     torch.cuda.synchronize()
-    ev.timers(True)
-    ev.read_timers(reset=True)
     t0 = time.perf_counter()
     for _ in range(steps):
         md.step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the stage breakdown from further steps with the stage timers on (their events add
+    # queue packets between the kernels, so the timed steps above run without them)
+    ev.timers(True)
+    ev.read_timers(reset=True)
+    for _ in range(min(steps, 20)):
+        md.step()
     tm = ev.read_timers(reset=True)
     ev.timers(False)
     return ev, model, el, tm

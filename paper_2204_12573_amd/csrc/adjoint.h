@@ -128,8 +128,9 @@ __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int
       u[n][q] = h ? other : c[n][q];
       u[n][NQ + q] = h ? c[n][q] : other;
     }
-  const int base = v.slice_base[R >> 5];
-  const int len = v.slice_base[(R >> 5) + 1] - base;
+  const int S = wave_slice(R);
+  const int base = v.slice_base[S];
+  const int len = v.slice_base[S + 1] - base;
   const size_t s0 = (size_t)base * 32 + (R & 31);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
   // lane h takes slots k = h, h + 2, ...; the geometry and reverse index of its next two

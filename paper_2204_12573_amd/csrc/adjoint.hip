@@ -92,8 +92,9 @@ __global__ __launch_bounds__(MTHREADS) void k_adjoint_mixed(SlotView v, int rows
   for (int lm = 0; lm < NLM; ++lm) crow[cidx(L, lm)] = u[lm];
   __syncthreads();
   if (i < 0) return;
-  const int base = v.slice_base[R >> 5];
-  const int len = v.slice_base[(R >> 5) + 1] - base;
+  const int S = wave_slice(R);
+  const int base = v.slice_base[S];
+  const int len = v.slice_base[S + 1] - base;
   float sx = 0.f, sy = 0.f, sz = 0.f;
   for (int k = L; k < len; k += 16) {
     const size_t slot = (size_t)(base + k) * 32 + (R & 31);

@@ -167,6 +167,21 @@ void bf16x3_fragments(const std::vector<double>& M, uint16_t* out /* [5][9][3][6
         }
 }
 
+// FP32 fragments of an n x n matrix M (row-major, leading dimension ld) for
+// v_mfma_f32_16x16x4_f32 B operands: [K chunk n/16][column block n/16][lane 64][t 4],
+// element M[16 kc + 4 (lane / 16) + t][16 cb + lane % 16].
+std::vector<float> f32_fragments(const double* M, int ld, int n) {
+  const int nc = n / 16;
+  std::vector<float> f((size_t)nc * nc * 64 * 4);
+  for (int kc = 0; kc < nc; ++kc)
+    for (int cb = 0; cb < nc; ++cb)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 4; ++t)
+          f[(((size_t)kc * nc + cb) * 64 + lane) * 4 + t] =
+              (float)M[(size_t)(kc * 16 + 4 * (lane / 16) + t) * ld + cb * 16 + lane % 16];
+  return f;
+}
+
 // FP64 fragments of an n x n lower-triangular factor L (row-major) for
 // v_mfma_f64_16x16x4_f64 B operands: [cb][kc][t 4][lane 64], element
 // L[16 kc + 4 (lane / 16) + t][16 cb + lane % 16] (blocks with kc < cb are zero).
@@ -300,41 +315,17 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
   m->var64 = precision != FLARE_FP32 && !(flags & FLARE_VAR_FP32);
   m->r_cut = r_cut;
   CHK(hipGetDevice(&m->device));
-  // descriptor block of each bucket inside the packed 544 vector
-  const int start[NBUCKET] = {0, 0, ND - ND1, ND - ND1, 0, 0};
-  for (int b = 0; b < NBUCKET; ++b) {
-    const int nb = bucket_width(b);
-    const int s = b < 4 ? (b & 1) : (b - 4);    // central species
-    std::vector<float> w((size_t)2 * nb * nb);
-    const double* parts[2] = {beta_host + (size_t)s * ND * ND, sigma_host + (size_t)s * ND * ND};
-    for (int part = 0; part < 2; ++part)
-      for (int n = 0; n < nb; ++n)
-        for (int k = 0; k < nb; ++k)    // row n of the stored part = column n of the matrix
-          w[(size_t)part * nb * nb + (size_t)n * nb + k] =
-              (float)parts[part][(size_t)(start[b] + k) * ND + (start[b] + n)];
-    hipError_t e = hipMalloc((void**)&m->W[b], w.size() * sizeof(float));
-    if (e == hipSuccess) e = hipMemcpy(m->W[b], w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (b < 4 && e == hipSuccess) {
-      // fragment order for v_mfma_f32_16x16x4_f32 B operands: element
-      // [part][kc][cb][lane][t] = M[kc*16 + 4*(lane/16) + t][cb*16 + lane%16]
-      const int nkc = ND1 / 16, ncb = ND1 / 16;
-      std::vector<float> f((size_t)2 * nkc * ncb * 64 * 4);
-      for (int part = 0; part < 2; ++part)
-        for (int kc = 0; kc < nkc; ++kc)
-          for (int cb = 0; cb < ncb; ++cb)
-            for (int lane = 0; lane < 64; ++lane)
-              for (int t = 0; t < 4; ++t) {
-                const int k = kc * 16 + 4 * (lane / 16) + t, col = cb * 16 + lane % 16;
-                f[((((size_t)part * nkc + kc) * ncb + cb) * 64 + lane) * 4 + t] =
-                    (float)parts[part][(size_t)(start[b] + k) * ND + (start[b] + col)];
-              }
-      e = hipMalloc((void**)&m->Wf[b], f.size() * sizeof(float));
-      if (e == hipSuccess) e = hipMemcpy(m->Wf[b], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) {
-      set_error(std::string("model upload: ") + hipGetErrorString(e));
+  // beta and Sigma of each single-species bucket's 144-wide block in fragment order
+  for (int b = 0; b < 4; ++b) {
+    const int sp = b & 1;                          // central species
+    const int st = b < 2 ? 0 : ND - ND1;           // the block inside the packed 544 vector
+    std::vector<float> f0 = f32_fragments(beta_host + (size_t)sp * ND * ND + (size_t)st * ND + st, ND, ND1);
+    std::vector<float> f1 = f32_fragments(sigma_host + (size_t)sp * ND * ND + (size_t)st * ND + st, ND, ND1);
+    f0.insert(f0.end(), f1.begin(), f1.end());
+    const int rc = upload((void**)&m->Wf[b], f0.data(), f0.size() * sizeof(float));
+    if (rc != FLARE_OK) {
       flare_model_destroy(m);
-      return e == hipErrorOutOfMemory ? FLARE_E_OOM : FLARE_E_HIP;
+      return rc;
     }
   }
   // Cholesky factors of the Sigma blocks: V = |L^T d|^2, a sum of squares that does not
@@ -362,14 +353,7 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
   if (chol) {
     for (int b = 0; b < 4; ++b) {
       // FP32 fragments of L replace the Sigma part (part 1) of Wf
-      std::vector<float> f((size_t)nkc * ncb * 64 * 4);
-      for (int kc = 0; kc < nkc; ++kc)
-        for (int cb = 0; cb < ncb; ++cb)
-          for (int lane = 0; lane < 64; ++lane)
-            for (int t = 0; t < 4; ++t) {
-              const int k = kc * 16 + 4 * (lane / 16) + t, col = cb * 16 + lane % 16;
-              f[(((size_t)kc * ncb + cb) * 64 + lane) * 4 + t] = (float)L1[b][(size_t)k * ND1 + col];
-            }
+      std::vector<float> f = f32_fragments(L1[b].data(), ND1, ND1);
       hipError_t e = hipMemcpy(m->Wf[b] + (size_t)nkc * ncb * 64 * 4, f.data(), f.size() * sizeof(float),
                                hipMemcpyHostToDevice);
       if (e != hipSuccess) {
@@ -378,15 +362,23 @@ int flare_model_create(flare_model** out, int n_species, int n_rad, int l_max, d
         return FLARE_E_HIP;
       }
     }
-    for (int s = 0; s < NS; ++s) {
-      std::vector<float> lt((size_t)ND * ND);   // row n = column n of L
+  }
+  // the mixed buckets: beta, Sigma (and L) of the central species over all 544 components,
+  // row n of each stored part = column n of the matrix
+  for (int sp = 0; sp < NS; ++sp) {
+    const int parts = chol ? 3 : 2;
+    std::vector<float> w((size_t)parts * ND * ND);
+    for (int part = 0; part < parts; ++part) {
+      const double* M = part == 0 ? beta_host + (size_t)sp * ND * ND
+                                  : part == 1 ? sigma_host + (size_t)sp * ND * ND : Lx[sp].data();
       for (int n = 0; n < ND; ++n)
-        for (int k = 0; k < ND; ++k) lt[(size_t)n * ND + k] = (float)Lx[s][(size_t)k * ND + n];
-      int rc = upload((void**)&m->Lx[s], lt.data(), lt.size() * sizeof(float));
-      if (rc != FLARE_OK) {
-        flare_model_destroy(m);
-        return rc;
-      }
+        for (int k = 0; k < ND; ++k) w[((size_t)part * ND + n) * ND + k] = (float)M[(size_t)k * ND + n];
+    }
+    int rc = upload((void**)&m->Wx[sp], w.data(), (size_t)2 * ND * ND * sizeof(float));
+    if (rc == FLARE_OK && chol) rc = upload((void**)&m->Lx[sp], w.data() + (size_t)2 * ND * ND, (size_t)ND * ND * sizeof(float));
+    if (rc != FLARE_OK) {
+      flare_model_destroy(m);
+      return rc;
     }
   }
   if (m->var64) {
@@ -483,8 +475,6 @@ int flare_model_info(const flare_model* m, int* precision, int* variance_cholesk
 
 int flare_model_destroy(flare_model* m) {
   if (!m) return FLARE_OK;
-  for (int b = 0; b < NBUCKET; ++b)
-    if (m->W[b]) (void)hipFree(m->W[b]);
   for (int b = 0; b < 4; ++b) {
     if (m->Wf[b]) (void)hipFree(m->Wf[b]);
     if (m->Wb[b]) (void)hipFree(m->Wb[b]);
@@ -493,6 +483,7 @@ int flare_model_destroy(flare_model* m) {
     if (m->L64[b]) (void)hipFree(m->L64[b]);
   }
   for (int k = 0; k < 2; ++k) {
+    if (m->Wx[k]) (void)hipFree(m->Wx[k]);
     if (m->Lx[k]) (void)hipFree(m->Lx[k]);
     if (m->Lx64[k]) (void)hipFree(m->Lx64[k]);
   }
@@ -993,12 +984,11 @@ int flare_memory_bytes(const flare_model* m, const flare_state* s, long long* by
   ARG(bytes, "null pointer");
   long long b = 0;
   if (m) {
-    for (int k = 0; k < NBUCKET; ++k) b += (long long)2 * bucket_width(k) * bucket_width(k) * sizeof(float);
-    b += 4LL * 2 * ND1 * ND1 * sizeof(float);
+    b += (4LL * 2 * ND1 * ND1 + 2LL * 2 * ND * ND) * sizeof(float);   // Wf, Wx
+    if (m->vchol) b += 2LL * ND * ND * sizeof(float);                    // Lx
     if (m->precision == FLARE_BF16_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * 8 * sizeof(uint16_t);
     if (m->precision == FLARE_FP8_SPLIT) b += 4LL * 5 * 9 * 2 * 64 * sizeof(uint64_t);
     if (m->precision == FLARE_BF16X6_SPLIT) b += 4LL * 5 * 9 * 3 * 64 * 8 * sizeof(uint16_t);
-    if (m->vchol) b += 2LL * ND * ND * sizeof(float);
     if (m->var64) b += (4LL * ND1 * ND1 + 2LL * ND * ND) * sizeof(double);
   }
   if (s) b += s->fixed_bytes + (long long)s->red_w.bytes();

@@ -101,13 +101,12 @@ __global__ __launch_bounds__(NTG) void k_disp(int n, const int* __restrict__ inv
   }
 }
 
-// Per-step geometry of every listed pair. The pair vector is split as
+// Per-step geometry of every listed pair (slot_geom). The pair vector is split as
 //   Delta = [(w_j - w_i) + s*L] + (delta_j - delta_i),
 // the bracket fixed at the list build (FP64, stored rounded to FP32 with the neighbour's
-// species in .w) and the displacements since the build added in FP32; kept when
-// |Delta|^2 < r_c^2, written as (u^, r) with the sign of r carrying the neighbour species.
-// One thread per slot (its loads independent of each other's); padding slots keep the zero
-// geometry the list build gave them.
+// species in .w) and the displacements since the build added in FP32. One thread per slot
+// (its loads independent of each other's); padding slots keep the zero geometry the list
+// build gave them.
 __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __restrict__ slot_atom,
                                               const int* __restrict__ slot_j,
                                               const float4* __restrict__ slot_d0,
@@ -117,17 +116,7 @@ __global__ __launch_bounds__(NTG) void k_geom(long long nslots, const int* __res
   if (slot >= nslots) return;
   const int i = slot_atom[slot];
   if (i < 0) return;
-  const float4 d0 = slot_d0[slot];
-  const float4 dj = dlt[slot_j[slot]], di = dlt[i];
-  const float fx = d0.x + (dj.x - di.x), fy = d0.y + (dj.y - di.y), fz = d0.z + (dj.z - di.z);
-  const float r2 = fx * fx + fy * fy + fz * fz;
-  float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (r2 < rc2) {
-    const float r = sqrtf(r2);
-    const float inv = 1.f / r;
-    out = make_float4(fx * inv, fy * inv, fz * inv, d0.w * r);
-  }
-  geom[slot] = out;
+  geom[slot] = slot_geom(slot_d0[slot], dlt[slot_j[slot]], dlt[i], rc2);
 }
 
 // |d~| of every atom in caller order (0 for an atom without neighbours).

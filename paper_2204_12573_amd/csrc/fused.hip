@@ -810,7 +810,8 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
   __shared__ float nrm_s[WW][WR];
   __shared__ double nrm2_s[WW][WR];
   __shared__ float rsc_s[WW][WR];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform over the wave: scalar, and with it the sub-tile loop and rows
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int nw = gridDim.x * WW;
   float* A = As[wv];
   const RowScalars rs{nrm_s[wv], nrm2_s[wv], rsc_s[wv]};

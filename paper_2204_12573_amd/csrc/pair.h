@@ -11,14 +11,19 @@ struct PairGeom {
   float r, ux, uy, uz;
 };
 
+// The slice of row R, read as a wave-uniform (scalar) value: every caller's wave covers
+// rows of one 32-row slice, so all its active lanes have the same R / 32.
+__device__ __forceinline__ int wave_slice(int R) { return __builtin_amdgcn_readfirstlane(R >> 5); }
+
 // Visit the geometry of row R's slots in order, f(g, k), with the loads PD slots ahead of
 // their use: the loop body is unrolled PD times over a ring of PD registers, so no value
 // moves between registers. All rows of a wave share one slice (and its length), so the
-// trip count is uniform across the wave.
+// trip count is uniform across the wave (a scalar loop).
 template <int PD, class F>
 __device__ __forceinline__ void for_each_slot(const SlotView& v, int R, F f) {
-  const int base = v.slice_base[R >> 5];
-  const int len = v.slice_base[(R >> 5) + 1] - base;
+  const int S = wave_slice(R);
+  const int base = v.slice_base[S];
+  const int len = v.slice_base[S + 1] - base;
   const float4* p = v.geom + (size_t)base * 32 + (R & 31);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
   float4 buf[PD];
@@ -33,6 +38,19 @@ __device__ __forceinline__ void for_each_slot(const SlotView& v, int R, F f) {
       if (k0 + u < len) f(g, k0 + u);
     }
   }
+}
+
+// Geometry of one listed pair at the current positions: Delta = d0 + (delta_j - delta_i) in
+// FP32 (d0 fixed at the list build, delta the displacements since), kept when |Delta|^2 <
+// r_c^2, returned as (u^, r) with the sign of r carrying the neighbour species; zero outside
+// the cutoff and for padding (d0 = 0).
+__device__ __forceinline__ float4 slot_geom(const float4& d0, const float4& dj, const float4& di, float rc2) {
+  const float fx = d0.x + (dj.x - di.x), fy = d0.y + (dj.y - di.y), fz = d0.z + (dj.z - di.z);
+  const float r2 = fmaf(fz, fz, fmaf(fy, fy, fx * fx));
+  if (d0.w == 0.f || !(r2 < rc2)) return make_float4(0.f, 0.f, 0.f, 0.f);
+  const float r = sqrtf(r2);
+  const float inv = 1.f / r;
+  return make_float4(fx * inv, fy * inv, fz * inv, d0.w * r);
 }
 
 __device__ __forceinline__ bool unpack_geom(const float4& g, PairGeom& pg, int& sp) {

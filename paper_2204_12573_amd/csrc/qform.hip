@@ -266,14 +266,10 @@ struct VarArgs {
   double* P64;             // [rows][NXG]
 };
 
-__global__ __launch_bounds__(256) void k_var544_f64(VarArgs q) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// One column group g of one 32-row block.
+__device__ __forceinline__ void var544_group(const VarArgs& q, int row0, int g, int lane) {
   const int l16 = lane & 15, grp = lane >> 4;
-  const int task = blockIdx.x * 4 + wave;        // (32-row block, column group)
-  const int rb = task / NXG, g = task % NXG;
-  const int row0 = rb * 32;
-  if (row0 >= q.rows) return;
-  // the split between the two buckets falls on a 128-row boundary: one factor per wave
+  // the split between the two buckets falls on a 128-row boundary: one factor per block
   const double* __restrict__ L = (row0 >= q.split_row ? q.L[1] : q.L[0]) + lane;
   const float* __restrict__ d0 = q.D + (size_t)(row0 + l16) * ND + 4 * grp;
   const float* __restrict__ d1 = d0 + (size_t)16 * ND;
@@ -325,6 +321,23 @@ __global__ __launch_bounds__(256) void k_var544_f64(VarArgs q) {
     }
 }
 
+// Group g of a row block runs 34 - 4 g chunks, so groups g and 8 - g together run 36: the
+// first four tasks of every 32-row block are such pairs, the fifth the middle group alone
+// (18 chunks). Tasks go out longest first (all pairs, then the middle groups), so the
+// short ones fill in at the end.
+__global__ __launch_bounds__(256) void k_var544_f64(VarArgs q) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int task = blockIdx.x * 4 + wave;
+  const int nrb = q.rows / 32;
+  if (task < 4 * nrb) {
+    const int pr = task / nrb, rb = task % nrb;
+    var544_group(q, rb * 32, pr, lane);
+    var544_group(q, rb * 32, NXG - 1 - pr, lane);
+  } else if (task < 5 * nrb) {
+    var544_group(q, (task - 4 * nrb) * 32, NXG / 2, lane);
+  }
+}
+
 // V of each mixed row from its group sums (fixed order), rounded to FP32 once.
 __global__ __launch_bounds__(256) void k_var544_finish(int rows, const double* __restrict__ P64,
                                                        const int* __restrict__ aor, int n_given,
@@ -349,7 +362,7 @@ void var544_f64(flare_state* s, const float* D, int rows, int split_row, const i
   q.L[0] = s->model->Lx64[0];
   q.L[1] = s->model->Lx64[1];
   q.P64 = s->Px64;
-  const int tasks = rows / 32 * NXG;
+  const int tasks = rows / 32 * 5;      // per 32-row block: four pairs of groups and the middle group
   k_var544_f64<<<(tasks + 3) / 4, 256, 0, s->stream>>>(q);
   k_var544_finish<<<(rows + 255) / 256, 256, 0, s->stream>>>(rows, s->Px64, aor, n_given, v_int, v_row);
 }
@@ -380,7 +393,7 @@ void forms_mixed_chunk(flare_state* s, int r0, int nr, bool want_e, bool want_v)
     const int padded = (s->bucket_count[bk] + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
     q.row0[k] = s->bucket_row0[bk] - r0;     // chunk-local rows
     q.row1[k] = s->bucket_row0[bk] + padded - r0;
-    q.W[k] = m->W[bk] + ((mode & 1) ? 0 : (size_t)ND * ND);
+    q.W[k] = m->Wx[k] + ((mode & 1) ? 0 : (size_t)ND * ND);
   }
   // with Cholesky factors the Sigma columns come from L (V = |d L|^2)
   q.sumsq = m->vchol ? 1 : 0;
@@ -417,7 +430,7 @@ int forms_given_544(flare_state* s, int bucket, int n, const float* d, float* e,
     q.nbk = 1;
     q.row0[0] = 0;
     q.row1[0] = rows;
-    q.W[0] = m->W[bucket];
+    q.W[0] = m->Wx[bucket - 4];
     q.L[0] = m->Lx[bucket - 4];
     q.sumsq = m->vchol ? 1 : 0;
     q.D = s->Dx;

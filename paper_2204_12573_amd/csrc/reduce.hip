@@ -28,9 +28,23 @@ __global__ __launch_bounds__(NT) void k_outputs_rows(int rows, int want_f, const
   float sx = 0.f, sy = 0.f, sz = 0.f;
   if (want_f) {
     const int base = slice_base[R >> 5], len = cnt_row[R];   // the row's own pairs (no padding)
+    const float4* wp = w_in + (size_t)base * 32 + (R & 31);
     float rx = 0.f, ry = 0.f, rz = 0.f;
-    for (int k = 0; k < len; ++k) {
-      const float4 wr = w_in[(base + k) * 32 + (R & 31)];
+    int k = 0;
+    // four loads in flight at a time; the sums stay in slot order
+    for (; k + 4 <= len; k += 4) {
+      float4 wr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wr[u] = wp[(size_t)(k + u) * 32];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rx += wr[u].x;
+        ry += wr[u].y;
+        rz += wr[u].z;
+      }
+    }
+    for (; k < len; ++k) {
+      const float4 wr = wp[(size_t)k * 32];
       rx += wr.x;
       ry += wr.y;
       rz += wr.z;

@@ -78,16 +78,19 @@ struct flare_model {
   int precision = FLARE_FP32;     // arithmetic form of the energy pass (FLARE_FP32 .. FLARE_BF16X6_SPLIT)
   int flags = 0;                  // the precision argument as given (form | FLARE_VAR_FP32)
   bool var64 = false;             // variance on the FP64 matrix cores (split forms without FLARE_VAR_FP32)
-  // variances from Cholesky factors (part 1 of Wf holds L, Lx the 544-wide factors)
+  // variances from Cholesky factors (part 1 of Wf and Wxf holds L)
   bool vchol = false;
   double r_cut = 0.0;
-  // Per bucket: [2*nb][nb] row-major; rows 0..nb-1 hold the beta sub-block and rows
-  // nb..2nb-1 the Sigma sub-block of the central species, restricted to the bucket's
-  // descriptor block (nb = 144 for single-species buckets, 544 for mixed).
-  float* W[flare::NBUCKET] = {};
-  // Single-species buckets: the same matrices in MFMA fragment order,
-  // [part 2][K chunk 9][column block 9][lane 64] float4 (see fused.hip).
+  // Single-species buckets: beta (part 0) and Sigma or its Cholesky factor L (part 1) of
+  // the central species, restricted to the bucket's 144-wide block, in MFMA fragment
+  // order [part 2][K chunk 9][column block 9][lane 64] float4: element t of lane l of
+  // (kc, cb) is M[16 kc + 4 (l / 16) + t][16 cb + l % 16] (see fused.hip).
   float* Wf[4] = {};
+  // Mixed buckets (4: H centre, 5: Pt centre): beta then Sigma of the central species over
+  // all 544 components, [2][544][544] with row n = column n of the matrix (see qform.hip);
+  // with Cholesky factors, Lx holds L in the same form.
+  float* Wx[2] = {};
+  float* Lx[2] = {};
   // BF16 split form (precision FLARE_BF16_SPLIT), single-species buckets: beta as
   // [K step 5][column block 9][hi/lo 2][lane 64] x 8 bf16 (K padded 144 -> 160). In this
   // form the Sigma part of Wf holds the Cholesky factor L of Sigma (Sigma = L L^T).
@@ -100,9 +103,6 @@ struct flare_model {
   // Three-way BF16 form (precision FLARE_BF16X6_SPLIT): beta as [K step 5][column block 9]
   // [part 3][lane 64] x 8 bf16, parts x0 + x1 + x2 = FP32 value.
   uint16_t* W6[4] = {};
-  // Cholesky factor L of the 544 x 544 Sigma_s (mixed buckets), [544][544] FP32, stored
-  // like W (row n = column n of L).
-  float* Lx[2] = {};
   // Split forms: Cholesky factors in FP64 for the variance on the FP64 matrix cores, in
   // fragment order [column block][K chunk][k-step 4][lane 64]: element L[16 kc + 4 (lane / 16)
   // + t][16 cb + lane % 16]. Single-species buckets: the factor of the bucket's 144 x 144
@@ -211,7 +211,7 @@ struct flare_state {
   float* Dx = nullptr;                  // [mix_cap][544] descriptors
   float* Gx = nullptr;                  // gradients
   float* Yx = nullptr;                  // D beta
-  float* Px = nullptr;                  // [mix_cap][4] partial row sums
+  float* Px = nullptr;                  // [mix_cap][4] partial row sums of the column tiles
   double* Px64 = nullptr;               // [mix_cap][9] FP64 variance partials (split forms)
 
   // ---- sliced pair layout (capacity slot_cap) ----
