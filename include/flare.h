@@ -322,6 +322,28 @@ int flare_md_second_half(flare_state* state, double* vx, double* vy, double* vz,
                          const int32_t* species, const double* masses_host, double dt);
 
 /*
+ * One whole velocity-Verlet NVE step, the same arithmetic as the sequence
+ *   flare_md_first_half; flare_neighbors (when rebuild != 0, with the cells, boxes and skin
+ *   of the last flare_neighbors call); flare_descriptors; flare_energy_forces (with
+ *   forces); flare_md_second_half
+ * and the same results bit for bit, in fewer kernels: the drift also forms the
+ * displacements of the new positions, and the caller-order outputs carry the second half.
+ *   x, y, z, vx, vy, vz  DEVICE FP64 [n_atoms], read and written
+ *   fx, fy, fz           DEVICE FP32 [n_atoms]: in, the forces at the current positions;
+ *                        out, the forces at the new positions (required)
+ *   e_atom, var_atom, sigma_atom  DEVICE FP32 [n_atoms] or NULL; e_struct DEVICE FP64
+ *                        [n_struct] or NULL: the other outputs of flare_energy_forces
+ * A rebuild waits for the stream once (as flare_neighbors) and moves the status bits of
+ * the interval it ends to flare_interval_status / flare_status; its errors are those of
+ * flare_neighbors (positions and velocities are then already advanced by the first half).
+ * Without a rebuild the call does not wait.
+ */
+int flare_md_step(flare_state* state, double* x, double* y, double* z, double* vx, double* vy,
+                  double* vz, float* fx, float* fy, float* fz, const int32_t* species,
+                  const double* masses_host, double dt, int rebuild, float* e_atom,
+                  double* e_struct, float* var_atom, float* sigma_atom);
+
+/*
  * Nose-Hoover NVT halves (the paper's production runs, Section VI.A: 450 K). One
  * thermostat variable zeta per cell, no chain:
  *   dv/dt = KAPPA F/m - zeta v,  dzeta/dt = (2K / (N_f k_B T) - 1) / tau^2,  deta/dt = zeta,

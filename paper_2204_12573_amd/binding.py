@@ -56,6 +56,7 @@ SIGNATURES = {
     "flare_memory_bytes": (_i, [_p, _p, ctypes.POINTER(_ll)]),
     "flare_md_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
     "flare_md_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d]),
+    "flare_md_step": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _i, _p, _p, _p, _p]),
     "flare_nvt_first_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d, _d, _p]),
     "flare_nvt_second_half": (_i, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _d, _d, _d, _p]),
     "flare_kinetic": (_i, [_p, _p, _p, _p, _p, _p, _p]),

@@ -743,16 +743,9 @@ int flare_descriptors(flare_state* s, const double* x, const double* y, const do
   return FLARE_OK;
 }
 
-int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, float* fz, double* e_struct,
-                        float* var_atom, float* sigma_atom) {
-  ARG(s, "null state");
-  if (!s->have_desc) {
-    set_error("flare_energy_forces before flare_descriptors");
-    return FLARE_E_STALE;
-  }
-  const bool want_f = fx || fy || fz;
-  ARG(!want_f || (fx && fy && fz), "pass all three force arrays or none");
-  const bool want_v = var_atom || sigma_atom;
+// Energies (and gradients), forces and variances of the positions staged last, up to the
+// per-row results (row_out is formed by the output kernels).
+static void evaluate_forms(flare_state* s, bool want_f, bool want_v) {
   {
     // with forces, the fused kernel also runs the adjoint of the 144-wide rows in place
     StageTimer tm(s, FLARE_T_QFORM1);
@@ -765,6 +758,19 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
   } else {
     s->g_gen = s->pos_gen;
   }
+}
+
+int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, float* fz, double* e_struct,
+                        float* var_atom, float* sigma_atom) {
+  ARG(s, "null state");
+  if (!s->have_desc) {
+    set_error("flare_energy_forces before flare_descriptors");
+    return FLARE_E_STALE;
+  }
+  const bool want_f = fx || fy || fz;
+  ARG(!want_f || (fx && fy && fz), "pass all three force arrays or none");
+  const bool want_v = var_atom || sigma_atom;
+  evaluate_forms(s, want_f, want_v);
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, e_atom, fx, fy, fz, var_atom, sigma_atom);
@@ -910,6 +916,52 @@ int flare_md_second_half(flare_state* s, double* vx, double* vy, double* vz, con
     StageTimer tm(s, FLARE_T_MD);
     md_second(s, vx, vy, vz, fx, fy, fz, species, 1.0 / masses_host[0], 1.0 / masses_host[1], dt);
   }
+  CHK(hipGetLastError());
+  return FLARE_OK;
+}
+
+int flare_md_step(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz, float* fx,
+                  float* fy, float* fz, const int32_t* species, const double* masses_host, double dt, int rebuild,
+                  float* e_atom, double* e_struct, float* var_atom, float* sigma_atom) {
+  ARG(s && masses_host, "null pointer");
+  if (!s->have_list) {
+    set_error("flare_md_step needs a neighbour list (flare_neighbors)");
+    return FLARE_E_STALE;
+  }
+  ARG(s->n_atoms == 0 || (x && y && z && vx && vy && vz && fx && fy && fz && species), "null device array");
+  ARG(masses_host[0] > 0 && masses_host[1] > 0, "masses must be positive");
+  const double im0 = 1.0 / masses_host[0], im1 = 1.0 / masses_host[1];
+  {
+    StageTimer tm(s, FLARE_T_MD);
+    md_first_drift(s, x, y, z, vx, vy, vz, fx, fy, fz, species, im0, im1, dt, rebuild == 0);
+  }
+  if (rebuild) {
+    // the same cells, boxes and skin as the last flare_neighbors
+    s->have_list = false;
+    s->have_desc = false;
+    int rc;
+    {
+      StageTimer tm(s, FLARE_T_LIST);
+      rc = build_list(s, x, y, z, species);
+    }
+    if (rc != FLARE_OK) return rc;
+    s->have_list = true;
+  }
+  {
+    StageTimer tm(s, FLARE_T_DESC1);
+    if (rebuild) gather_positions(s, x, y, z);   // the displacements from the new build (zero)
+    pair_geometry(s);
+  }
+  s->have_desc = true;
+  s->pos_gen += 1;
+  const bool want_v = var_atom || sigma_atom;
+  evaluate_forms(s, true, want_v);
+  {
+    StageTimer tm(s, FLARE_T_OUT);
+    outputs_second_half(s, e_atom, fx, fy, fz, var_atom, sigma_atom, vx, vy, vz, species, im0, im1, dt);
+    reduce_cells(s, e_struct, nullptr);
+  }
+  if (want_v) s->v_gen = s->pos_gen;
   CHK(hipGetLastError());
   return FLARE_OK;
 }

@@ -90,15 +90,7 @@ __global__ __launch_bounds__(NTG) void k_disp(int n, const int* __restrict__ inv
                                               float4* __restrict__ dlt, double lim2, int* __restrict__ status) {
   const int a = blockIdx.x * NTG + threadIdx.x;
   if (a >= n) return;
-  const double d0 = x[a] - xb[a];
-  const double d1 = y[a] - xb[(size_t)n + a];
-  const double d2 = z[a] - xb[2 * (size_t)n + a];
-  dlt[inv_perm[a]] = make_float4((float)d0, (float)d1, (float)d2, 0.f);
-  const double d2s = d0 * d0 + d1 * d1 + d2 * d2;
-  if (!(d2s <= lim2)) {
-    if (!isfinite(d2s)) atomicOr(status, FLARE_FLAG_NONFINITE);
-    else atomicOr(status, FLARE_FLAG_DISPLACED);
-  }
+  store_displacement(a, n, x[a], y[a], z[a], xb, inv_perm, dlt, lim2, status);
 }
 
 // Per-step geometry of every listed pair (slot_geom). The pair vector is split as

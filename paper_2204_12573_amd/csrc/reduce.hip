@@ -289,6 +289,67 @@ __global__ __launch_bounds__(NT) void k_md_first(int n, double* __restrict__ x, 
   z[a] += dt * uz;
 }
 
+// The first half and drift of a step (as k_md_first) with, when the list stays, the
+// displacement of each new position since the list build (as k_disp).
+__global__ __launch_bounds__(NT) void k_md_first_drift(int n, double* __restrict__ x, double* __restrict__ y,
+                                                       double* __restrict__ z, double* __restrict__ vx,
+                                                       double* __restrict__ vy, double* __restrict__ vz,
+                                                       const float* __restrict__ fx, const float* __restrict__ fy,
+                                                       const float* __restrict__ fz,
+                                                       const int32_t* __restrict__ species, double h0, double h1,
+                                                       double dt, int disp, const double* __restrict__ xb,
+                                                       const int* __restrict__ inv_perm, float4* __restrict__ dlt,
+                                                       double lim2, int* __restrict__ status) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n) return;
+  const double h = species[a] == 0 ? h0 : h1;    // dt/2 * KAPPA / m
+  const double ux = vx[a] + h * (double)fx[a];
+  const double uy = vy[a] + h * (double)fy[a];
+  const double uz = vz[a] + h * (double)fz[a];
+  vx[a] = ux;
+  vy[a] = uy;
+  vz[a] = uz;
+  const double px = x[a] + dt * ux, py = y[a] + dt * uy, pz = z[a] + dt * uz;
+  x[a] = px;
+  y[a] = py;
+  z[a] = pz;
+  if (disp) store_displacement(a, n, px, py, pz, xb, inv_perm, dlt, lim2, status);
+}
+
+// The caller-order outputs (as k_outputs_atoms) and the second half of the step with the
+// new forces (as k_md_second).
+__global__ __launch_bounds__(NT) void k_outputs_second_half(int n, const int* __restrict__ row_caller,
+                                                            const float4* __restrict__ row_out,
+                                                            const float* __restrict__ v_row,
+                                                            float* __restrict__ e_atom, float* __restrict__ fx,
+                                                            float* __restrict__ fy, float* __restrict__ fz,
+                                                            float* __restrict__ var_atom,
+                                                            float* __restrict__ sigma_atom,
+                                                            double* __restrict__ vx, double* __restrict__ vy,
+                                                            double* __restrict__ vz,
+                                                            const int32_t* __restrict__ species, double h0,
+                                                            double h1) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n) return;
+  const int R = row_caller[a];
+  float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+  float v = 0.f;
+  if (R >= 0) {
+    o = row_out[R];
+    if (var_atom || sigma_atom) v = v_row[R];
+  }
+  if (e_atom) e_atom[a] = o.w;
+  fx[a] = o.x;
+  fy[a] = o.y;
+  fz[a] = o.z;
+  if (var_atom) var_atom[a] = v;
+  if (sigma_atom) sigma_atom[a] = sqrtf(fmaxf(v, 0.f));
+  const double h = species[a] == 0 ? h0 : h1;
+  vx[a] += h * (double)o.x;
+  vy[a] += h * (double)o.y;
+  vz[a] += h * (double)o.z;
+}
+
 __global__ __launch_bounds__(NT) void k_md_second(int n, double* __restrict__ vx,
                                                   double* __restrict__ vy, double* __restrict__ vz,
                                                   const float* __restrict__ fx,
@@ -346,6 +407,34 @@ void md_first(flare_state* s, double* x, double* y, double* z, double* vx, doubl
   if (n == 0) return;
   const double h0 = 0.5 * dt * KAPPA * inv_m0, h1 = 0.5 * dt * KAPPA * inv_m1;
   k_md_first<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, x, y, z, vx, vy, vz, fx, fy, fz, species, h0, h1, dt);
+}
+
+void md_first_drift(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                    const float* fx, const float* fy, const float* fz, const int32_t* species, double inv_m0,
+                    double inv_m1, double dt, bool displacements) {
+  const int n = s->n_atoms;
+  if (n == 0) return;
+  const double h0 = 0.5 * dt * KAPPA * inv_m0, h1 = 0.5 * dt * KAPPA * inv_m1;
+  const double lim = 0.5 * s->skin;
+  k_md_first_drift<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, x, y, z, vx, vy, vz, fx, fy, fz, species, h0, h1,
+                                                            dt, displacements ? 1 : 0, s->xb, s->inv_perm, s->dlt,
+                                                            lim * lim, s->d_status);
+}
+
+void outputs_second_half(flare_state* s, float* e_atom, float* fx, float* fy, float* fz, float* var_atom,
+                         float* sigma_atom, double* vx, double* vy, double* vz, const int32_t* species,
+                         double inv_m0, double inv_m1, double dt) {
+  const int n = s->n_atoms;
+  if (n == 0) return;
+  const int rows = s->rows1 + s->rowsx;
+  if (rows > 0)
+    k_outputs_rows<<<(rows + NT - 1) / NT, NT, 0, s->stream>>>(rows, 1, s->slice_base, s->f_own, s->w_in,
+                                                              s->cnt_row, s->sid_row, nullptr, s->e_row,
+                                                              s->row_out);
+  const double h0 = 0.5 * dt * KAPPA * inv_m0, h1 = 0.5 * dt * KAPPA * inv_m1;
+  k_outputs_second_half<<<(n + NT - 1) / NT, NT, 0, s->stream>>>(n, s->row_caller, s->row_out, s->v_row, e_atom,
+                                                                 fx, fy, fz, var_atom, sigma_atom, vx, vy, vz,
+                                                                 species, h0, h1);
 }
 
 void md_second(flare_state* s, double* vx, double* vy, double* vz, const float* fx, const float* fy,

@@ -252,6 +252,22 @@ struct StageTimer {
   StageTimer(flare_state* st, int stg);
   ~StageTimer();
 };
+// Displacement of caller atom a since the list build, d = (x, y, z) - xb in FP64, stored in
+// FP32 at its internal index; it must stay within half the skin (lim2 = (skin/2)^2), else a
+// status bit is raised. Shared by the standalone kernel and the integrator's drift.
+__device__ __forceinline__ void store_displacement(int a, int n, double x, double y, double z,
+                                                   const double* __restrict__ xb, const int* __restrict__ inv_perm,
+                                                   float4* __restrict__ dlt, double lim2, int* __restrict__ status) {
+  const double d0 = x - xb[a];
+  const double d1 = y - xb[(size_t)n + a];
+  const double d2 = z - xb[2 * (size_t)n + a];
+  dlt[inv_perm[a]] = make_float4((float)d0, (float)d1, (float)d2, 0.f);
+  const double d2s = d0 * d0 + d1 * d1 + d2 * d2;
+  if (!(d2s <= lim2)) {
+    if (!isfinite(d2s)) atomicOr(status, FLARE_FLAG_NONFINITE);
+    else atomicOr(status, FLARE_FLAG_DISPLACED);
+  }
+}
 // list-build constants for the capacities of a state (nlist.hip)
 int list_key_count();      // sort keys of the row order (per 256-atom block)
 int list_pair_cache();     // pairs per atom kept by the counting pass
@@ -289,6 +305,14 @@ void virial_cells(flare_state* s, double* virial_struct, double* red_w);
 void md_first(flare_state* s, double* x, double* y, double* z, double* vx, double* vy,
               double* vz, const float* fx, const float* fy, const float* fz,
               const int32_t* species, double inv_m0, double inv_m1, double dt);
+// one NVE step's kernels: first half and drift with the displacements of the new positions
+// (when the list stays), and the caller-order outputs with the second half
+void md_first_drift(flare_state* s, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                    const float* fx, const float* fy, const float* fz, const int32_t* species, double inv_m0,
+                    double inv_m1, double dt, bool displacements);
+void outputs_second_half(flare_state* s, float* e_atom, float* fx, float* fy, float* fz, float* var_atom,
+                         float* sigma_atom, double* vx, double* vy, double* vz, const int32_t* species,
+                         double inv_m0, double inv_m1, double dt);
 void md_second(flare_state* s, double* vx, double* vy, double* vz, const float* fx,
                const float* fy, const float* fz, const int32_t* species, double inv_m0,
                double inv_m1, double dt);

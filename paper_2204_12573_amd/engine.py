@@ -247,6 +247,17 @@ class Evaluator:
                                                   B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species),
                                                   B.ptr(MASSES), float(dt)))
 
+    def md_step(self, pos, vel, out, dt, rebuild, want_var=True):
+        """One NVE step in one call (flare_md_step): out["f"] holds the forces at the current
+        positions on entry and at the new ones on return; e, E (and var, sigma) are refreshed."""
+        f = out["f"]
+        with torch.cuda.stream(self.stream):
+            B.check(self.lib.flare_md_step(
+                self.handle, B.ptr(pos[0]), B.ptr(pos[1]), B.ptr(pos[2]), B.ptr(vel[0]), B.ptr(vel[1]),
+                B.ptr(vel[2]), B.ptr(f[0]), B.ptr(f[1]), B.ptr(f[2]), B.ptr(self.species), B.ptr(MASSES),
+                float(dt), 1 if rebuild else 0, B.ptr(out["e"]), B.ptr(out["E"]),
+                B.ptr(out["var"]) if want_var else None, B.ptr(out["sigma"]) if want_var else None))
+
     # ---- Nose-Hoover NVT and coordination (production runs) ----
     def new_thermostat(self, vel):
         """Per-cell thermostat state (zeta, eta, K) on the device, zeta = eta = 0 and K of vel."""
@@ -337,6 +348,17 @@ class MD:
         self.out = ev.compute(pos, want_var)
 
     def step(self):
+        ev = self.ev
+        self.nstep += 1
+        rebuild = self.nstep % self.rebuild == 0
+        ev.md_step(self.pos, self.vel, self.out, self.dt, rebuild, self.want_var)
+        if rebuild:
+            check_interval(ev)
+        return self.out
+
+    def step_in_calls(self):
+        """The same step through the separate calls (first half, list, descriptors, energies and
+        forces, second half); bit for bit the result of step()."""
         ev = self.ev
         ev.md_first_half(self.pos, self.vel, self.out["f"], self.dt)
         self.nstep += 1
