@@ -132,39 +132,40 @@ __device__ __forceinline__ void adjoint_pairs_half(const SlotView& v, int R, int
   const int base = v.slice_base[S];
   const int len = v.slice_base[S + 1] - base;
   const size_t s0 = (size_t)base * 32 + (R & 31);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  // lane h takes slots k = h, h + 2, ...; the geometry and reverse index of its next two
-  // slots are in flight while one is evaluated (ring of two, unrolled)
-  float4 gb[2];
-  int rb[2];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int k = h + 2 * e;
-    gb[e] = k < len ? v.geom[s0 + (size_t)k * 32] : zero;
-    rb[e] = k < len ? v.rev[s0 + (size_t)k * 32] : 0;
-  }
   float sx = 0.f, sy = 0.f, sz = 0.f;
-  for (int k0 = h; k0 < len; k0 += 4) {
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int k = k0 + 2 * e;
-      const float4 gk = gb[e];
-      const int rk = rb[e];
-      const int kn = k + 4;
-      if (kn < len) {
-        gb[e] = v.geom[s0 + (size_t)kn * 32];
-        rb[e] = v.rev[s0 + (size_t)kn * 32];
-      }
-      if (k < len) {
-        PairGeom pg;
-        int sp;
-        float wx = 0.f, wy = 0.f, wz = 0.f;
-        if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
-        v.w_in[rk] = make_float4(wx, wy, wz, 0.f);
-        sx += wx;
-        sy += wy;
-        sz += wz;
-      }
+  // lane h takes slots k = h, h + 2, ...: the geometry and reverse index of its next two
+  // slots are in flight while two are evaluated, in two register groups that take turns
+  // (as in for_each_slot: unconditional loads, past the slice re-reading its last slot)
+  auto load = [&](int k, float4& g, int& r) {
+    const size_t sl = s0 + (size_t)min(k, len - 1) * 32;
+    g = v.geom[sl];
+    r = v.rev[sl];
+  };
+  auto term = [&](int k, const float4& gk, int rk) {
+    if (k >= len) return;
+    PairGeom pg;
+    int sp;
+    float wx = 0.f, wy = 0.f, wz = 0.f;
+    if (unpack_geom(gk, pg, sp)) pair_force(pg, v.rc, [&](int n, int lm) { return u[n][lm]; }, wx, wy, wz);
+    v.w_in[rk] = make_float4(wx, wy, wz, 0.f);
+    sx += wx;
+    sy += wy;
+    sz += wz;
+  };
+  if (len > 0) {
+    float4 ga[2], gb[2];
+    int ra[2], rb[2];
+    load(h, ga[0], ra[0]);
+    load(h + 2, ga[1], ra[1]);
+    for (int k0 = h; k0 < len; k0 += 8) {
+      load(k0 + 4, gb[0], rb[0]);
+      load(k0 + 6, gb[1], rb[1]);
+      term(k0, ga[0], ra[0]);
+      term(k0 + 2, ga[1], ra[1]);
+      load(k0 + 8, ga[0], ra[0]);
+      load(k0 + 10, ga[1], ra[1]);
+      term(k0 + 4, gb[0], rb[0]);
+      term(k0 + 6, gb[1], rb[1]);
     }
   }
   sx += xor1(sx);

@@ -566,11 +566,15 @@ __device__ __forceinline__ TileModel tile_model(const FusedArgs& a, int row0) {
   return m;
 }
 
-// Per-row scalars of the tile: |d~| (FP32), |d~|^2 in FP64 (split forms), the FP8 row scale.
+// Per-row scalars of the tile (LDS): |d~| (FP32), |d~|^2 in FP64 (split forms), the FP8 row
+// scale, the row's atom (-1: padding) and 1/|d~|^2, set by the descriptor phase so that the
+// later phases read them from LDS instead of global memory.
 struct RowScalars {
   float* nrm;
   double* nrm2;
   float* rsc;
+  int* atom;
+  float* inv2;
 };
 
 // 1. descriptors of the tile's rows into the LDS tile (thread t of 256: row t/2, half t&1);
@@ -631,6 +635,8 @@ __device__ __forceinline__ void desc_phase(const FusedArgs& a, float* As, const 
   }
   if (h == 0) {
     rs.nrm[rl] = nrm;
+    rs.atom[rl] = i;
+    rs.inv2[rl] = nrm > 0.f ? 1.f / (nrm * nrm) : 0.f;
     if (PREC != FLARE_FP32) rs.nrm2[rl] = (double)nrm2;
     if (i >= 0) a.nrm[i] = nrm;
   }
@@ -659,7 +665,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int rl = wave * 32 + i * 16 + grp + 4 * r;     // FP64 accumulator layout
-          const int atom = atom_of<GIVEN>(a, row0 + rl);
+          const int atom = rs.atom[rl];
           const double n2 = rs.nrm2[rl];
           if (atom >= 0) {
             const float v = n2 > 0.0 ? (float)(vv[i][r] / n2) : 0.f;
@@ -683,7 +689,7 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int rl = wave * 32 + i * 16 + 4 * grp + r;
-          const int atom = atom_of<GIVEN>(a, row0 + rl);
+          const int atom = rs.atom[rl];
           const float nv = nrm_s[rl];
           if (atom >= 0) {
             const float v = nv > 0.f ? dots[i][r] / (nv * nv) : 0.f;
@@ -718,9 +724,8 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rl = wave * 32 + i * 16 + 4 * grp + r;
-        const int atom = atom_of<GIVEN>(a, row0 + rl);
-        const float nv = nrm_s[rl];
-        const float inv2 = nv > 0.f ? 1.f / (nv * nv) : 0.f;
+        const int atom = rs.atom[rl];
+        const float inv2 = rs.inv2[rl];
         const float e = dots[i][r] * inv2;        // e = Y~ . d~ / |d~|^2
         if (l16 == 0 && atom >= 0) {
           a.e_int[atom] = e;
@@ -738,10 +743,10 @@ __device__ __forceinline__ void forms_phase(const FusedArgs& a, float* As, const
 // 4. adjoint in place: u = G^ c from the gradient tile, then the per-pair terms. The
 // densities c come from the descriptor phase of the same rows, kept in registers through
 // the forms phase (no second pass over the pairs, no round trip through memory).
-__device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, int row0, int t,
-                                              float (&c)[NR][NQ]) {
+__device__ __forceinline__ void adjoint_phase(const FusedArgs& a, const float* As, const RowScalars& rs, int row0,
+                                              int t, float (&c)[NR][NQ]) {
   const int rl = t >> 1, h = t & 1;
-  if (atom_of<false>(a, row0 + rl) < 0) return;     // descriptor rows only
+  if (rs.atom[rl] < 0) return;     // descriptor rows only
   u_transform_half(As + rl * AS, 1, h, c);
   adjoint_pairs_half(a.v, row0 + rl, h, c, a.f_own);
 }
@@ -754,7 +759,9 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   __shared__ float nrm_s[FR];
   __shared__ double nrm2_s[FR];   // split forms: |d~|^2 in FP64
   __shared__ float rsc_s[FR];     // FP8 split form: power-of-two row scale s_r
-  const RowScalars rs{nrm_s, nrm2_s, rsc_s};
+  __shared__ int atom_s[FR];
+  __shared__ float inv2_s[FR];
+  const RowScalars rs{nrm_s, nrm2_s, rsc_s, atom_s, inv2_s};
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = tile * FR;
   const int t = threadIdx.x;
@@ -767,7 +774,7 @@ __global__ __launch_bounds__(FT, 2) void k_fused144(FusedArgs a) {
   if (!GIVEN && a.D_out) {
     for (int idx = t; idx < FR * ND1; idx += FT) {
       const int r = idx / ND1, k = idx % ND1;
-      const int i = atom_of<false>(a, row0 + r);
+      const int i = atom_s[r];
       const float nv = nrm_s[r];
       if (i >= 0) a.D_out[(size_t)a.perm[i] * ND + tm.dstart + k] = nv > 0.f ? As[r * AS + k] / nv : 0.f;
     }
@@ -810,11 +817,13 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
   __shared__ float nrm_s[WW][WR];
   __shared__ double nrm2_s[WW][WR];
   __shared__ float rsc_s[WW][WR];
+  __shared__ int atom_s[WW][WR];
+  __shared__ float inv2_s[WW][WR];
   // the wave index is uniform over the wave: scalar, and with it the sub-tile loop and rows
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int nw = gridDim.x * WW;
   float* A = As[wv];
-  const RowScalars rs{nrm_s[wv], nrm2_s[wv], rsc_s[wv]};
+  const RowScalars rs{nrm_s[wv], nrm2_s[wv], rsc_s[wv], atom_s[wv], inv2_s[wv]};
   for (int st = blockIdx.x * WW + wv; st < nsub; st += nw) {
     const int row0 = st * WR;
     float c[NR][NQ];
@@ -826,7 +835,7 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
     forms_phase<PREC, V64, false>(a, A, rs, row0, lane, tile_model(a, row0));
     __builtin_amdgcn_s_setprio(0);
     wave_phase_fence();
-    adjoint_phase(a, A, row0, lane, c);
+    adjoint_phase(a, A, rs, row0, lane, c);
     wave_phase_fence();
   }
 }

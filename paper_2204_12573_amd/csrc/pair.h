@@ -16,27 +16,32 @@ struct PairGeom {
 __device__ __forceinline__ int wave_slice(int R) { return __builtin_amdgcn_readfirstlane(R >> 5); }
 
 // Visit the geometry of row R's slots in order, f(g, k), with the loads PD slots ahead of
-// their use: the loop body is unrolled PD times over a ring of PD registers, so no value
-// moves between registers. All rows of a wave share one slice (and its length), so the
-// trip count is uniform across the wave (a scalar loop).
+// their use, in two register groups that take turns (group b loads while group a is used,
+// then a while b is): every value is used from the register it was loaded into, and each
+// wait covers only the older group. Loads are unconditional: past the slice they re-read
+// its last slot (unused), so that no test or register move sits between a load and its
+// use. All rows of a wave share one slice (and its length): a scalar loop.
 template <int PD, class F>
 __device__ __forceinline__ void for_each_slot(const SlotView& v, int R, F f) {
   const int S = wave_slice(R);
   const int base = v.slice_base[S];
   const int len = v.slice_base[S + 1] - base;
+  if (len <= 0) return;
   const float4* p = v.geom + (size_t)base * 32 + (R & 31);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 buf[PD];
+  float4 a[PD], b[PD];
 #pragma unroll
-  for (int u = 0; u < PD; ++u) buf[u] = u < len ? p[(size_t)u * 32] : zero;
-  for (int k0 = 0; k0 < len; k0 += PD) {
+  for (int u = 0; u < PD; ++u) a[u] = p[(size_t)min(u, len - 1) * 32];
+  for (int k0 = 0; k0 < len; k0 += 2 * PD) {
 #pragma unroll
-    for (int u = 0; u < PD; ++u) {
-      const float4 g = buf[u];
-      const int kn = k0 + PD + u;
-      buf[u] = kn < len ? p[(size_t)kn * 32] : zero;
-      if (k0 + u < len) f(g, k0 + u);
-    }
+    for (int u = 0; u < PD; ++u) b[u] = p[(size_t)min(k0 + PD + u, len - 1) * 32];
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+      if (k0 + u < len) f(a[u], k0 + u);
+#pragma unroll
+    for (int u = 0; u < PD; ++u) a[u] = p[(size_t)min(k0 + 2 * PD + u, len - 1) * 32];
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+      if (k0 + PD + u < len) f(b[u], k0 + PD + u);
   }
 }
 
