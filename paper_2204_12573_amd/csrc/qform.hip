@@ -160,35 +160,42 @@ __global__ __launch_bounds__(NTQ, 3) void k_qform(QArgs q) {
   else main_loop(std::false_type{});
 
   // ---- epilogue: lane holds Y[row = 4*grp + r][col = 16*j + l16] of each block ----
+  // A tile lies wholly in the beta part or wholly in the Sigma / L part (272 divides 544).
+  // The D values of a row dot are loaded together before they are used (no test between a
+  // load and its use); the factor's part needs none (a sum of squares).
   const bool has_e = q.mode & 1;
   const int col_base = ntile * NC;
+  const bool beta_tile = has_e && col_base < KD;
+  const bool squares = !beta_tile && q.sumsq;
+  const int kbase = beta_tile ? col_base : col_base - (has_e ? KD : 0);   // the tile's first column of D
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
-    float pe[4] = {0.f, 0.f, 0.f, 0.f}, pv[4] = {0.f, 0.f, 0.f, 0.f};
+    float ps[4] = {0.f, 0.f, 0.f, 0.f};
+    if (squares) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wave * RB * 16 + i * 16 + 4 * grp + r;
-      const float* drow = D + (size_t)row * KD;
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const int col = col_base + j * 16 + l16;
-        const bool beta_col = has_e && col < KD;
-        const int kcol = beta_col ? col : (has_e ? col - KD : col);
-        const float y = acc[i][j][r];
-        if (beta_col) pe[r] += y * drow[kcol];
-        else pv[r] += q.sumsq ? y * y : y * drow[kcol];
+        for (int j = 0; j < CB; ++j) ps[r] += acc[i][j][r] * acc[i][j][r];
+    } else {
+      float dv[4][CB];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float* drow = D + (size_t)(row0 + wave * RB * 16 + i * 16 + 4 * grp + r) * KD + kbase + l16;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) dv[r][j] = drow[j * 16];
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) ps[r] += acc[i][j][r] * dv[r][j];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      pe[r] = sum16(pe[r]);
-      pv[r] = sum16(pv[r]);
-    }
+    for (int r = 0; r < 4; ++r) ps[r] = sum16(ps[r]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row0 + wave * RB * 16 + i * 16 + 4 * grp + r;
-      if (l16 == 0) q.P[(size_t)row * 4 + ntile] = has_e && col_base < KD ? pe[r] : pv[r];
-      if (has_e && col_base < KD) {
+      if (l16 == 0) q.P[(size_t)row * 4 + ntile] = ps[r];
+      if (beta_tile) {
         float* yrow = q.Y + (size_t)row * KD;
 #pragma unroll
         for (int j = 0; j < CB; ++j) yrow[col_base + j * 16 + l16] = acc[i][j][r];
