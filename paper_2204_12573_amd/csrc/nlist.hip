@@ -579,6 +579,28 @@ __global__ void k_layout_status(int* __restrict__ status, int* __restrict__ layo
   }
 }
 
+// The fills of a build in one launch: up to ten (array, count, value) segments, every
+// work-item striding over each of them.
+struct ClearSeg {
+  int* p;
+  long long n;
+  int v;
+};
+struct ClearArgs {
+  ClearSeg seg[10];
+  int nseg;
+};
+__global__ __launch_bounds__(NT) void k_clear(ClearArgs a) {
+  const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+  const long long stride = (long long)gridDim.x * NT;
+  for (int k = 0; k < a.nseg; ++k) {
+    int* __restrict__ p = a.seg[k].p;
+    const long long n = a.seg[k].n;
+    const int v = a.seg[k].v;
+    for (long long i = t; i < n; i += stride) p[i] = v;
+  }
+}
+
 inline int grid_of(long long n) { return (int)((n + NT - 1) / NT); }
 
 #define HIPCHK(call)                                                     \
@@ -633,10 +655,25 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   // the build checks its inputs in a word of its own (d_status[1]); the caller-visible
   // word d_status[0] keeps what the per-step calls raised until k_layout_status moves it
   int* bst = s->d_status + 1;
-  HIPCHK(hipMemsetAsync(bst, 0, sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->d_layout, 0, LY_N * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->bin_count, 0, ((size_t)nbins + 1) * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->bin_fill, 0, ((size_t)nbins + 1) * sizeof(int), st));
+  {
+    // everything the build starts from: its status word and layout record, the bin
+    // counters, no atom in any row, zero energies, variances and norms (atoms without a
+    // listed pair keep them)
+    ClearArgs c{};
+    auto seg = [&](int* p, long long cnt, int v) { c.seg[c.nseg++] = ClearSeg{p, cnt, v}; };
+    seg(bst, 1, 0);
+    seg(s->d_layout, LY_N, 0);
+    seg(s->bin_count, (long long)nbins + 1, 0);
+    seg(s->bin_fill, (long long)nbins + 1, 0);
+    seg(s->atom_of_row1, (long long)s->row_cap + 1, -1);
+    seg(s->atom_of_rowx, (long long)s->row_cap + 1, -1);
+    seg(reinterpret_cast<int*>(s->e_int), n, 0);
+    seg(reinterpret_cast<int*>(s->v_int), n, 0);
+    seg(reinterpret_cast<int*>(s->nrm), n, 0);
+    long long longest = 1;
+    for (int k = 0; k < c.nseg; ++k) longest = std::max(longest, c.seg[k].n);
+    k_clear<<<(int)std::min<long long>(grid_of(longest), 2048), NT, 0, st>>>(c);
+  }
   if (n > 0)
     k_wrap_bin<<<grid_of(n), NT, 0, st>>>(n, x, y, z, species, s->d_struct_off, nc, s->d_grids, s->crec, s->xb,
                                           s->bin_count, bst);
@@ -674,8 +711,6 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   scan_exclusive(s->blk_bucket, s->blk_bucket_scan, NKEY * nblk, s->scan_scratch, st);
   k_off_check<<<grid_of(n + 1), NT, 0, st>>>(n, s->nl_off, bst);
   k_layout_rows<<<1, 64, 0, st>>>(n, s->nl_off, s->blk_bucket_scan, nblk, s->max_pairs, bst, s->d_layout);
-  HIPCHK(hipMemsetAsync(s->atom_of_row1, 0xff, ((size_t)s->row_cap + 1) * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(s->atom_of_rowx, 0xff, ((size_t)s->row_cap + 1) * sizeof(int), st));
   if (n > 0) {
     k_pairs<true><<<nblk, NT, 0, st>>>(n, s->d_grids, s->sid, s->bin, s->w, s->wf, s->bin_start, rl2, lo2, hi2,
                                         nullptr,
@@ -737,9 +772,6 @@ int build_list(flare_state* s, const double* x, const double* y, const double* z
   s->rowsx = L[LY_ROWSX];
   s->n_slices = L[LY_SLICES];
   s->n_slots = 32LL * L[LY_SLOTS32];
-  HIPCHK(hipMemsetAsync(s->e_int, 0, (size_t)n * sizeof(float), st));
-  HIPCHK(hipMemsetAsync(s->v_int, 0, (size_t)n * sizeof(float), st));
-  HIPCHK(hipMemsetAsync(s->nrm, 0, (size_t)n * sizeof(float), st));
   return FLARE_OK;
 }
 

@@ -1,6 +1,7 @@
 // Device-wide exclusive prefix sum of int32 counts (bin counts, pair counts, bucket
-// counts). Three phases per level: block scans with block totals, a recursive scan of
-// the totals, and the add-back. Deterministic (integer, fixed order).
+// counts), out[0..n-1] and the total out[n], in two launches: the totals of 1024-element
+// blocks, then each block's scan from the sum of the totals before it (at most a few
+// thousand, read by every block). Deterministic (integer).
 #include "common.h"
 
 namespace flare {
@@ -21,83 +22,86 @@ __device__ inline int wave_incl_scan(int v) {
   return v;
 }
 
-// Exclusive scan of one 1024-element block; writes block total to sums[blockIdx].
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_block(const int* __restrict__ in,
-                                                              int* __restrict__ out, int n,
+// Phase 1: the total of every 1024-element block.
+__global__ __launch_bounds__(SCAN_THREADS) void k_block_sums(const int* __restrict__ in, int n,
                                                               int* __restrict__ sums) {
   __shared__ int wsum[SCAN_THREADS / 64];
+  const long long base = (long long)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER_THREAD; ++k) tot += base + k < n ? in[base + k] : 0;
+  const int incl = wave_incl_scan(tot);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) t += wsum[k];
+    sums[blockIdx.x] = t;
+  }
+}
+
+// Phase 2: every block adds up the totals of the blocks before it (nb of them at most),
+// scans its own elements from there and writes them; the block holding element n - 1
+// (block 0 when n == 0) also writes the total out[n].
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_blocks(const int* __restrict__ in, int* __restrict__ out,
+                                                               int n, const int* __restrict__ sums) {
+  __shared__ int wsum[SCAN_THREADS / 64];
+  __shared__ int pre_s;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int pre = 0;
+  for (int k = threadIdx.x; k < (int)blockIdx.x; k += SCAN_THREADS) pre += sums[k];
+  pre = wave_incl_scan(pre);
+  if (lane == 63) wsum[w] = pre;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) t += wsum[k];
+    pre_s = t;
+  }
+  __syncthreads();
+  const int block_pre = pre_s;
   const long long base = (long long)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
   int v[SCAN_PER_THREAD];
   int tot = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-    long long idx = base + k;
-    v[k] = idx < n ? in[idx] : 0;
+    v[k] = base + k < n ? in[base + k] : 0;
     tot += v[k];
   }
-  int incl = wave_incl_scan(tot);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int incl = wave_incl_scan(tot);
+  __syncthreads();                       // wsum is reused
   if (lane == 63) wsum[w] = incl;
   __syncthreads();
   int woff = 0;
   for (int k = 0; k < w; ++k) woff += wsum[k];
-  int run = woff + incl - tot;
+  int run = block_pre + woff + incl - tot;
 #pragma unroll
   for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-    long long idx = base + k;
-    if (idx < n) out[idx] = run;
+    if (base + k < n) out[base + k] = run;
     run += v[k];
   }
-  if (threadIdx.x == SCAN_THREADS - 1) sums[blockIdx.x] = woff + incl;
-}
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(int* __restrict__ out, int n,
-                                                            const int* __restrict__ offs) {
-  const long long base = (long long)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
-  const int add = offs[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-    long long idx = base + k;
-    if (idx < n) out[idx] += add;
+  // the total: written by the thread that holds element n - 1 (its running sum has passed
+  // it; the elements past n counted as zeros), or by thread 0 when n == 0
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+  } else if (base <= (long long)n - 1 && (long long)n - 1 < base + SCAN_PER_THREAD) {
+    out[n] = run;
   }
-}
-
-__global__ void k_scan_total(int* __restrict__ out, int n, const int* __restrict__ in) {
-  // out[n] = out[n-1] + in[n-1]  (n >= 1), or 0 when n == 0
-  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
 }
 
 int nblocks(long long n) { return (int)((n + SCAN_BLOCK - 1) / SCAN_BLOCK); }
 
-// out[0..n-1] exclusive scan (no total)
-void scan_level(const int* in, int* out, int n, int* scratch, hipStream_t st) {
-  if (n <= 0) return;
-  const int nb = nblocks(n);
-  int* sums = scratch;
-  int* sums_scan = scratch + nb;
-  int* next = scratch + 2 * nb;
-  k_scan_block<<<nb, SCAN_THREADS, 0, st>>>(in, out, n, sums);
-  if (nb > 1) {
-    scan_level(sums, sums_scan, nb, next, st);
-    k_scan_add<<<nb, SCAN_THREADS, 0, st>>>(out, n, sums_scan);
-  }
-}
-
 }  // namespace
 
-size_t scan_scratch_ints(long long n) {
-  size_t tot = 0;
-  while (n > 1) {
-    long long nb = nblocks(n);
-    tot += 2 * nb;
-    n = nb;
-  }
-  return tot + 64;
-}
+size_t scan_scratch_ints(long long n) { return (size_t)nblocks(n) + 64; }
 
+// Two launches (one when n fits one block): block totals, then every block's scan from
+// the sum of the totals before it.
 void scan_exclusive(const int* in, int* out, int n, int* scratch, hipStream_t st) {
-  scan_level(in, out, n, scratch, st);
-  k_scan_total<<<1, 64, 0, st>>>(out, n, in);
+  const int nb = n > 0 ? nblocks(n) : 1;
+  if (nb > 1) k_block_sums<<<nb, SCAN_THREADS, 0, st>>>(in, n, scratch);
+  k_scan_blocks<<<nb, SCAN_THREADS, 0, st>>>(in, out, n, scratch);
 }
 
 }  // namespace flare
