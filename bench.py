@@ -34,6 +34,8 @@ PEAK_FP32_VALU = 78.6e12       # FP32 vector FMA without packed instructions
 # (8 x 8 x 16 multiply-adds = 2048).
 VALU_FLOP_DENS, VALU_FLOP_ADJ = 320, 830
 VALU_FLOP_B2, VALU_FLOP_NORM, VALU_FLOP_EPI, VALU_FLOP_U = 1152, 288, 1000, 2048
+# dense matrix peaks of the split forms' instruction types (FLOP/s, MI355X)
+PEAK_BF16_MFMA, PEAK_FP8_MFMA, PEAK_FP64_MFMA = 2.5e15, 5.0e15, 78.6e12
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_fused144_w_h2_pt111_1M_fp32.txt")
@@ -212,6 +214,33 @@ def production_nvt(engine, torch, st, beta, sigma, steps, warmup, every=10):
             "note": "Nose-Hoover NVT 450 K, dt 0.1 fs, tau 10 fs, list every 10 steps (skin 0.25 A); coordination, "
                     "reaction events and max-sigma monitor every 10 steps (synthetic random-weight model: "
                     "sigma values are not physical)"}
+
+
+def form_roofline(prec, fused_work, t_launch):
+    """Bound of the fused kernel of the 144-wide rows in a split form: its matrix work at the
+    peak of each instruction type plus its vector work at the FP32 vector peak (the matrix
+    and vector instructions share the SIMD datapath). Per row: the energy pass takes
+    `products` part products of 2*144^2 flop (BF16 x3: 3, FP8 x3: 3, BF16 x6: 6) on the
+    form's matrix type; the variance |L^T d|^2 takes 144*145 flop on FP64 matrix cores, or on
+    FP32 ones with FLARE_VAR_FP32."""
+    from paper_2204_12573_amd import binding as B
+    base = prec & ~B.VAR_FP32
+    products, peak, kind = {B.BF16_SPLIT: (3, PEAK_BF16_MFMA, "bf16"), B.FP8_SPLIT: (3, PEAK_FP8_MFMA, "fp8"),
+                            B.BF16X6_SPLIT: (6, PEAK_BF16_MFMA, "bf16")}[base]
+    var_peak = PEAK_FP32_MFMA if prec & B.VAR_FP32 else PEAK_FP64_MFMA
+    n144 = fused_work["n144"]
+    e_flops = n144 * products * 2 * 144 * 144
+    v_flops = n144 * (144 * 145 if fused_work["vchol"] else 2 * 144 * 144)
+    parts = {"energy_pass_us": e_flops / peak * 1e6, "variance_pass_us": v_flops / var_peak * 1e6,
+             "vector_us": fused_work["valu_flops"] / PEAK_FP32_VALU * 1e6}
+    t_min = sum(parts.values()) * 1e-6
+    return {"bound": "alu", "t_min_us": round(t_min * 1e6, 1), "avg_launch_us": round(t_launch * 1e6, 1),
+            "frac": round(t_min / t_launch, 3), "parts_us": {k: round(v, 1) for k, v in parts.items()},
+            "peak_derivation": f"energy pass {products} products on {kind} matrix cores "
+                               f"({peak / 1e12:.0f} TFLOP/s), variance on "
+                               f"{'FP32' if prec & B.VAR_FP32 else 'FP64'} matrix cores "
+                               f"({var_peak / 1e12:.1f} TFLOP/s), vector work at 78.6 TFLOP/s, summed "
+                               f"(one datapath)"}
 
 
 def valu_work(engine, st):
@@ -445,6 +474,7 @@ def main():
     valu_flops = work["pairs144"] * (VALU_FLOP_DENS + VALU_FLOP_ADJ) + n144 * (
         VALU_FLOP_B2 + VALU_FLOP_NORM + VALU_FLOP_EPI + VALU_FLOP_U)
     t_min = flops_per_launch / PEAK_FP32_MFMA + valu_flops / PEAK_FP32_VALU
+    fused_work = {"n144": n144, "valu_flops": valu_flops, "vchol": vchol}
     total = flops_per_launch + valu_flops
     roofline = {"bound": "alu", "achieved": total / t_launch / 1e12, "peak": total / t_min / 1e12,
                 "unit": "TFLOP/s", "frac": t_min / t_launch, "traffic": profiled_traffic(),
@@ -532,18 +562,21 @@ def main():
             "value": round(n * args.steps / el2 / 1e6, 3), "ms_per_step": round(el2 / args.steps * 1e3, 4),
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.BF16_SPLIT, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm2.items() if c},
+            "roofline": form_roofline(binding.BF16_SPLIT, fused_work, tm2["qform144"][0] / tm2["qform144"][1] * 1e-3),
             "note": "energy pass BF16 x3 (d and beta split hi/lo), variance |L^T d|^2 with the FP64 factor "
                     "on FP64 matrix cores, FP64 sums; mixed-environment rows: FP32 energy, FP64 variance"}
         out["mixed_fp8_split"] = {
             "value": round(n * args.steps / el3 / 1e6, 3), "ms_per_step": round(el3 / args.steps * 1e3, 4),
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.FP8_SPLIT, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm3.items() if c},
+            "roofline": form_roofline(binding.FP8_SPLIT, fused_work, tm3["qform144"][0] / tm3["qform144"][1] * 1e-3),
             "note": "energy pass OCP e4m3 x3 with power-of-two row and block scales (d and beta split "
                     "hi/lo'), variance as in the BF16 form (FP64); mixed-environment rows: FP32 energy"}
         out["mixed_bf16x6_split"] = {
             "value": round(n * args.steps / el6 / 1e6, 3), "ms_per_step": round(el6 / args.steps * 1e3, 4),
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma, binding.BF16X6_SPLIT, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm6.items() if c},
+            "roofline": form_roofline(binding.BF16X6_SPLIT, fused_work, tm6["qform144"][0] / tm6["qform144"][1] * 1e-3),
             "note": "energy pass on BF16 matrix cores with d and beta split into three BF16 parts "
                     "(x0 + x1 + x2 = the FP32 value), six of the nine part products, FP32 accumulation "
                     "(FP32-level error); variance |L^T d|^2 with the FP64 factor on FP64 matrix cores; FP64 "
@@ -553,6 +586,7 @@ def main():
             "err_vs_fp64_oracle": sample_errors(engine, torch, st, beta, sigma,
                                                 binding.BF16X6_SPLIT | binding.VAR_FP32, tg, ref),
             "stage_us_per_launch": {k: round(ms / max(c, 1) * 1e3, 1) for k, (ms, c) in tm7.items() if c},
+            "roofline": form_roofline(binding.BF16X6_SPLIT | binding.VAR_FP32, fused_work, tm7["qform144"][0] / tm7["qform144"][1] * 1e-3),
             "note": "the three-way BF16 energy pass with the variance through the FP32 factor on FP32 "
                     "matrix cores (FLARE_VAR_FP32: the plain form's variance error, not FP64)"}
         if not args.no_huge:
