@@ -148,6 +148,39 @@ def test_isolated_atom_and_empty_environment(model):
     assert np.all(res["f"][2:] == 0.0)
 
 
+def test_empty_system_and_empty_cell(model):
+    """No atoms at all, and an empty cell between two copies of the 80-atom cell: the
+    empty parts give zero energy and raise no flag, the copies give the same bits as each
+    other and the oracle's values."""
+    from paper_2204_12573_amd import engine
+    beta, sigma = model
+    print("case: empty system", flush=True)
+    m = engine.Model(beta, sigma)
+    ev = engine.Evaluator(m, max_atoms=16, max_pairs=1024)
+    p, s = engine.to_device(np.zeros((0, 3)), np.zeros(0, np.int32))
+    ev.neighbors(p, s, [0, 0], np.array([10.0, 10.0, 10.0]), 0.2)
+    ev.descriptors(p)
+    out = ev.energy_forces(want_var=True)
+    torch.cuda.synchronize()
+    assert out["E"].cpu().numpy()[0] == 0.0
+    assert ev.status() == 0
+    print("case: empty cell inside a batch", flush=True)
+    st = S.config_tiny()
+    pos = np.concatenate([st.pos, st.pos])
+    sp = np.concatenate([st.species, st.species])
+    offsets = np.array([0, st.n, st.n, 2 * st.n], np.int32)
+    boxes = np.stack([st.box, np.array([12.0, 12.0, 12.0]), st.box])
+    res = gpu_eval(pos, sp, boxes, beta, sigma, offsets=offsets)
+    assert res["status"] == 0
+    assert res["E"][1] == 0.0 and res["E"][0] == res["E"][2]
+    for key in ["e", "f", "var", "sigma"]:
+        np.testing.assert_array_equal(res[key][:st.n], res[key][st.n:], err_msg=key)
+    ref = oev.evaluate(st.pos, st.species, st.box, beta, sigma)
+    _compare({k: (v[:st.n] if isinstance(v, np.ndarray) and v.ndim >= 1 and len(v) == 2 * st.n else v)
+              for k, v in res.items()}, ref)
+    assert abs(res["E"][0] - ref.energy) <= TOL * abs(ref.energy)
+
+
 def test_error_paths(model):
     from paper_2204_12573_amd import binding as Bd, engine
     beta, sigma = model
