@@ -84,24 +84,26 @@ def test_state_memory_fixed_across_rebuilds():
     assert ev.status() == 0
 
 
-def test_md_step_matches_the_separate_calls():
+@pytest.mark.parametrize("prec", [pytest.param(Bd.FP32, id="fp32"), pytest.param(Bd.BF16X6_SPLIT, id="bf16x6")])
+def test_md_step_matches_the_separate_calls(prec):
     """flare_md_step (one call per step, fused drift/displacement and output/second-half
     kernels) against the same steps through the separate calls: bit for bit, over 25 steps
-    with two list rebuilds, in a batch of three cells."""
+    with two list rebuilds, in a batch of three cells, in the plain and the three-way BF16
+    form."""
     b = S.config_cells(n_cells=3, seed=5)
     beta, sigma = S.random_model(DEFAULT.n_desc)
     v0 = S.maxwell_boltzmann(b.species, 450.0, seed=3)
     runs = []
     for fused in (True, False):
-        model = engine.Model(beta, sigma)
+        model = engine.Model(beta, sigma, precision=prec)
         ev = engine.Evaluator(model, max_atoms=b.n, max_pairs=64 * b.n)
         p, s = engine.to_device(b.pos, b.species)
         v = torch.from_numpy(np.ascontiguousarray(v0.T)).cuda()
         # skin 1 A: at 450 K and 0.5 fs the fastest H atoms move up to about 0.4 A per
         # 10-step interval (the rebuild would rightly raise with a thinner skin)
         md = engine.MD(ev, p, v, s, b.offsets, b.boxes, dt=0.5, skin=1.0, rebuild=10)
-        print(f"case: {b.n} atoms in 3 cells, 25 NVE steps, {'one call' if fused else 'separate calls'}",
-              flush=True)
+        how = "one call" if fused else "separate calls"
+        print(f"case: {b.n} atoms in 3 cells, 25 NVE steps, precision {prec}, {how}", flush=True)
         for _ in range(25):
             out = md.step() if fused else md.step_in_calls()
         torch.cuda.synchronize()
