@@ -34,6 +34,15 @@ def test_large_list_rows_bit_exact(large):
         m = i0 == a
         np.testing.assert_array_equal(j[off[a]:off[a + 1]], j0[m], err_msg=f"atom {a}")
         np.testing.assert_array_equal(s[off[a]:off[a + 1]], s0[m], err_msg=f"atom {a}")
+    # 10,000 more seeded rows through the oracle's k-d tree route (pinned to brute force on
+    # the CPU), bit for bit: neighbour, image shift and order
+    rows2 = np.sort(np.random.default_rng(13).choice(st.n, 10_000, replace=False))
+    i1, j1, s1 = onl.kdtree(st.pos, st.box, 4.7, rows2)
+    counts = off[rows2 + 1] - off[rows2]
+    idx = np.concatenate([np.arange(off[a], off[a + 1]) for a in rows2])
+    np.testing.assert_array_equal(np.repeat(rows2, counts), i1)
+    np.testing.assert_array_equal(j[idx], j1)
+    np.testing.assert_array_equal(s[idx], s1)
 
 
 def test_large_sampled_energy_sigma_forces(large):
