@@ -134,6 +134,28 @@ def test_batch_of_cells(model):
         assert abs(res["E"][k] - ref.energy) <= TOL * abs(ref.energy)
 
 
+def test_lists_of_all_256_cells(model):
+    """The list of the 256-cell batch (the differentiation workload), every cell entirely,
+    against brute force: offsets, neighbours, image shifts and order."""
+    from paper_2204_12573_amd import engine
+    beta, sigma = model
+    b = S.config_cells(n_cells=256, seed=0)
+    print(f"case: lists of 256 cells, {b.n} atoms", flush=True)
+    ev = engine.Evaluator(engine.Model(beta, sigma), max_atoms=b.n, max_pairs=64 * b.n)
+    p, s = engine.to_device(b.pos, b.species)
+    ev.neighbors(p, s, b.offsets, b.boxes, 0.2)
+    off, j, sh = ev.export_list()
+    assert ev.status() == 0
+    for k in range(256):
+        st = b.structure(k)
+        lo, hi = b.offsets[k], b.offsets[k + 1]
+        i0, j0, s0 = onl.brute_force(st.pos, st.box, 4.7)
+        off0 = np.concatenate([[0], np.cumsum(np.bincount(i0, minlength=st.n))])
+        np.testing.assert_array_equal(off[lo:hi + 1] - off[lo], off0, err_msg=f"cell {k}")
+        np.testing.assert_array_equal(j[off[lo]:off[hi]], j0 + lo, err_msg=f"cell {k}")
+        np.testing.assert_array_equal(sh[off[lo]:off[hi]], s0, err_msg=f"cell {k}")
+
+
 def test_isolated_atom_and_empty_environment(model):
     beta, sigma = model
     box = np.array([30.0, 30.0, 30.0])
