@@ -243,6 +243,42 @@ def form_roofline(prec, fused_work, t_launch):
                                f"(one datapath)"}
 
 
+def measured_ceilings(torch):
+    """Ceilings reached on this device by plain library work, beside the published peaks the
+    roofline uses: a 1 GiB device-to-device copy (read + write bytes) and a 8192^3 FP32
+    matrix product through torch (the ROCm BLAS library, no reduced-precision modes),
+    each the best of five after a warm-up."""
+    x = torch.empty(2**28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    a = torch.randn(8192, 8192, dtype=torch.float32, device="cuda")
+    b = torch.randn(8192, 8192, dtype=torch.float32, device="cuda")
+    torch.backends.cuda.matmul.allow_tf32 = False
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts)
+
+    t_copy = best(lambda: y.copy_(x))
+    t_mm = best(lambda: torch.matmul(a, b))
+    out = {"hbm_copy_TBps": round(2 * x.numel() * 4 / t_copy / 1e12, 2),
+           "sgemm_fp32_TFLOPs": round(2 * 8192**3 / t_mm / 1e12, 1),
+           "note": "best of 5: 1 GiB device copy (read + write), torch FP32 8192^3 matmul; the roofline "
+                   "fractions use the published peaks (HBM 8 TB/s, FP32 matrix 157.3 TFLOP/s)"}
+    del x, y, a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def valu_work(engine, st):
     """Pairs inside the cutoff whose centre has a single-species environment (the rows of
     the fused kernel), from the library's own list of the initial positions."""
@@ -311,6 +347,12 @@ def precision_16m(engine, torch, small, beta, sigma, half_width=13.1, evals=5):
     t_oracle = time.perf_counter() - t0
     rows = ref.row_of(tg)
     atoms = rng.integers(0, 16, len(tg)) * n1 + tg
+    # environment class of each sampled atom from the oracle's descriptor blocks: (H,H)
+    # components only, (Pt,Pt) only, or some in the cross block (mixed)
+    dref = ref.d[rows]
+    hh, cross, ptpt = (np.abs(dref[:, :144]).max(1) > 0, np.abs(dref[:, 144:400]).max(1) > 0,
+                       np.abs(dref[:, 400:]).max(1) > 0)
+    classes = {"h_only": hh & ~cross & ~ptpt, "pt_only": ptpt & ~cross & ~hh, "mixed": cross}
     p, s = engine.to_device(big.pos, big.species)
     forms = {}
     for name, prec in (("plain_fp32", 0), ("mixed_bf16_split", binding.BF16_SPLIT),
@@ -331,13 +373,17 @@ def precision_16m(engine, torch, small, beta, sigma, half_width=13.1, evals=5):
         e = out["e"].cpu().numpy()[atoms]
         f = out["f"].cpu().numpy().T[atoms]
         sg = out["sigma"].cpu().numpy()[atoms]
+        def errs(m):
+            return {"atoms": int(m.sum()),
+                    "e": float(np.abs(e[m] - ref.e[rows][m]).max() / np.abs(ref.e[rows][m]).max()),
+                    "f": float(np.linalg.norm(f[m] - ref.f[m], axis=1).max()
+                               / np.linalg.norm(ref.f[m], axis=1).max()),
+                    "sigma": float(np.abs(sg[m] - ref.sigma[rows][m]).max() / np.abs(ref.sigma[rows][m]).max())}
         forms[name] = {
             "M_atom_evals_per_s": round(n / el / 1e6, 1), "ms_per_eval": round(el * 1e3, 3),
             "status_flags": status,
-            "err_vs_fp64_oracle": {
-                "e": float(np.abs(e - ref.e[rows]).max() / np.abs(ref.e[rows]).max()),
-                "f": float(np.linalg.norm(f - ref.f, axis=1).max() / np.linalg.norm(ref.f, axis=1).max()),
-                "sigma": float(np.abs(sg - ref.sigma[rows]).max() / np.abs(ref.sigma[rows]).max())}}
+            "err_vs_fp64_oracle": {k: v for k, v in errs(np.ones(len(tg), bool)).items() if k != "atoms"},
+            "err_by_class": {c: errs(m) for c, m in classes.items() if m.any()}}
         del out, ev, model
         torch.cuda.synchronize()
     return {"atoms": n, "cell": "1 M-atom cell tiled 4 x 4 (400 x 400 x 24 Pt(111) + H2 gas)",
@@ -531,6 +577,7 @@ def main():
                    "n_desc": 544, "r_cut": 4.5, "skin": 0.2, "precision": args.precision},
         "roofline": roofline,
         "step_roofline": step_roofline,
+        "measured_ceilings": measured_ceilings(torch),
         "stage_us_per_launch": stage_us,
         "status_flags": status,
     }
