@@ -15,6 +15,15 @@ device. Latency is measured from a request's arrival to its results being on the
 Per-cell results do not depend on the batch composition (the library computes each row
 independently and gathers forces in a fixed order), so a structure gives the same bits
 alone and in any mix.
+
+Large requests (more atoms than `chunk_atoms`) are split by atom ranges: along the longer
+lateral axis into equal slabs, each evaluated with a halo of 2 r_c (plus a margin) on both
+sides in a box widened so that no periodic image reaches across the cut. An atom's energy
+and uncertainty depend on its neighbours within r_c, and its force on the energies of
+those neighbours, i.e. on atoms within 2 r_c; so every atom of a slab's own range gets the
+values of the whole structure (up to the order of FP32 sums), and the request's results
+are those atoms' values put back in its order, its energy their FP64 sum. The slabs of one
+request are batched like any other requests, on any lane.
 """
 from __future__ import annotations
 
@@ -39,6 +48,11 @@ class Request:
     f: np.ndarray | None = None
     sigma: np.ndarray | None = None
     energy: float | None = None
+    # a slab of a chunked request: the request, the slab atoms' indices in it, and which
+    # slab atoms are the slab's own (their results are kept)
+    parent: "Request | None" = None
+    index: np.ndarray | None = None
+    own: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -47,6 +61,49 @@ class Request:
     @property
     def latency(self) -> float:
         return self.t_done - self.arrival
+
+
+def split_request(r: Request, chunk_atoms: int, r_cut: float, margin: float = 0.5):
+    """Slabs of request r along its longer lateral axis, about chunk_atoms own atoms each,
+    with a halo of 2 r_cut + margin on both sides; each slab's box along that axis is its
+    width plus r_cut + margin, so that no pair crosses the cut through a periodic image."""
+    axis = 0 if r.box[0] >= r.box[1] else 1
+    L = float(r.box[axis])
+    m = int(np.ceil(r.n / chunk_atoms))
+    halo = 2.0 * r_cut + margin
+    width = L / m
+    if m < 2 or width < halo:
+        return [r]
+    x = np.mod(r.pos[:, axis], L)
+    owner = np.minimum((x / width).astype(np.int64), m - 1)     # each atom's own slab
+    slabs = []
+    for k in range(m):
+        # coordinate measured from the slab's lower halo edge, wrapped into [0, L)
+        u = np.mod(x - (k * width - halo), L)
+        keep = np.nonzero((u < width + 2.0 * halo) | (owner == k))[0]
+        pos = r.pos[keep].copy()
+        pos[:, axis] = u[keep]
+        box = r.box.astype(np.float64).copy()
+        box[axis] = width + 2.0 * halo + r_cut + margin
+        slabs.append(Request(r.rid, r.arrival, pos, r.species[keep], box, parent=r, index=keep,
+                             own=owner[keep] == k))
+    return slabs
+
+
+def join_slabs(r: Request, slabs) -> None:
+    """The request's results from its slabs' own atoms (each atom owned by exactly one)."""
+    r.e = np.zeros(r.n, np.float32)
+    r.f = np.zeros((r.n, 3), np.float32)
+    r.sigma = np.zeros(r.n, np.float32) if slabs[0].sigma is not None else None
+    for c in slabs:
+        idx = c.index[c.own]
+        r.e[idx] = c.e[c.own]
+        r.f[idx] = c.f[c.own]
+        if r.sigma is not None:
+            r.sigma[idx] = c.sigma[c.own]
+    r.energy = float(np.sum(r.e.astype(np.float64)))
+    r.t_start = min(c.t_start for c in slabs)
+    r.t_done = max(c.t_done for c in slabs)
 
 
 class Footprint:
@@ -195,10 +252,14 @@ class Scheduler:
     max_batch: cap on requests per batch (1 = one at a time).
     """
 
-    def __init__(self, executor, clock=time.perf_counter, max_batch=10**9, spin=None):
+    def __init__(self, executor, clock=time.perf_counter, max_batch=10**9, spin=None, chunk_atoms=None,
+                 r_cut=4.5):
         self.ex = executor
         self.clock = clock
         self.max_batch = max_batch
+        # requests above chunk_atoms are split by atom ranges (None: never)
+        self.chunk_atoms = chunk_atoms
+        self.r_cut = r_cut
         # called when nothing is ready: tests advance a fake clock; by default a short sleep
         # that lets the lane threads run
         self.spin = spin if spin is not None else (lambda: time.sleep(2e-5))
@@ -225,10 +286,18 @@ class Scheduler:
         t0 = self.clock()
         stats = {"batches": 0, "batch_atoms": []}
         total = len(pending)
+        open_slabs = {}          # chunked request -> [its slabs, slabs still out]
         while len(done) < total:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
-                queue.append(pending.popleft())
+                r = pending.popleft()
+                if self.chunk_atoms is not None and r.n > self.chunk_atoms:
+                    slabs = split_request(r, self.chunk_atoms, self.r_cut)
+                    if len(slabs) > 1:
+                        open_slabs[id(r)] = [slabs, len(slabs)]
+                    queue.extend(slabs)
+                else:
+                    queue.append(r)
             progressed = False
             for k in range(self.ex.n_lanes):
                 fin = self.ex.poll(k)
@@ -236,7 +305,15 @@ class Scheduler:
                     t = self.clock() - t0
                     for r in fin:
                         r.t_done = t
-                    done.extend(fin)
+                        if r.parent is None:
+                            done.append(r)
+                            continue
+                        entry = open_slabs[id(r.parent)]
+                        entry[1] -= 1
+                        if entry[1] == 0:
+                            join_slabs(r.parent, entry[0])
+                            del open_slabs[id(r.parent)]
+                            done.append(r.parent)
                     progressed = True
             for k in range(self.ex.n_lanes):
                 if queue and self.ex.idle(k):

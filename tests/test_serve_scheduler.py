@@ -109,3 +109,60 @@ def test_oversized_request_rejected():
     sched = serve.Scheduler(ex, clock=clock, spin=clock.advance)
     with pytest.raises(ValueError):
         sched.run(_reqs([500, 5000], [0.0, 0.0]))
+
+
+def _slab_request(n_target=6000, seed=4):
+    from paper_2204_12573_amd import structures as S
+    for t, st in S.serving_requests(40, lo=n_target, hi=n_target + 1, seed=seed):
+        return serve.Request(0, t, st.pos, st.species.astype(np.int32), st.box)
+
+
+def test_split_owns_every_atom_once_and_keeps_two_cutoffs_of_neighbours():
+    """Each atom is owned by exactly one slab, and in its slab every atom within 2 r_c of it
+    (as in the whole periodic structure: same atoms, same pair vectors) is present."""
+    from oracle.neighbors import neighbor_list
+    r = _slab_request()
+    slabs = serve.split_request(r, 1500, 4.5)
+    assert len(slabs) == int(np.ceil(r.n / 1500))
+    owned = np.concatenate([c.index[c.own] for c in slabs])
+    np.testing.assert_array_equal(np.sort(owned), np.arange(r.n))
+    reach = 2 * 4.5
+    i0, j0, s0 = neighbor_list(r.pos, r.box, reach)
+    d0 = r.pos[j0] + s0 * r.box - r.pos[i0]
+    for c in slabs:
+        i1, j1, s1 = neighbor_list(c.pos, c.box, reach)
+        d1 = c.pos[j1] + s1 * c.box - c.pos[i1]
+        for a in np.nonzero(c.own)[0][::7]:
+            want = sorted((int(j), tuple(np.round(d, 6))) for j, d in zip(j0[i0 == c.index[a]], d0[i0 == c.index[a]]))
+            got = sorted((int(c.index[j]), tuple(np.round(d, 6))) for j, d in zip(j1[i1 == a], d1[i1 == a]))
+            assert got == want, f"atom {c.index[a]}"
+
+
+class SlabExecutor(FakeExecutor):
+    """Results that name each atom of the request: e = f = sigma = its index in the request."""
+
+    def poll(self, k):
+        batch = super().poll(k)
+        if batch:
+            for r in batch:
+                idx = (r.index if r.parent is not None else np.arange(r.n)).astype(np.float32)
+                r.e, r.sigma = idx.copy(), idx.copy()
+                r.f = np.repeat(idx[:, None], 3, axis=1)
+        return batch
+
+
+def test_chunked_requests_are_joined_in_order():
+    clock = FakeClock()
+    ex = SlabExecutor(clock, lane_atoms=4000)
+    big = _slab_request()
+    reqs = _reqs([500, 700], [0.0, 0.0005])
+    reqs.append(serve.Request(2, 0.0002, big.pos, big.species, big.box))
+    done, stats = serve.Scheduler(ex, clock=clock, spin=clock.advance, chunk_atoms=2000).run(reqs)
+    assert sorted(r.rid for r in done) == [0, 1, 2] and stats["requests"] == 3
+    joined = next(r for r in done if r.rid == 2)
+    np.testing.assert_array_equal(joined.e, np.arange(big.n, dtype=np.float32))
+    np.testing.assert_array_equal(joined.f[:, 1], np.arange(big.n, dtype=np.float32))
+    assert joined.energy == float(np.sum(np.arange(big.n, dtype=np.float64)))
+    assert joined.t_done >= joined.t_start >= joined.arrival
+    # the slabs went through the lanes as requests of their own
+    assert sum(len(b) for b in ex.launched) == 2 + int(np.ceil(big.n / 2000))
