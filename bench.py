@@ -402,8 +402,8 @@ def serving(engine, torch, beta, sigma, n_req, rate, warmup=1000, pool=2000):
     _sys.setswitchinterval(1e-4)       # quick hand-offs between the scheduler and lane threads
     out = {}
     reqs_proto = serve.poisson_requests(warmup + n_req, rate=rate, seed=7, pool=pool)
-    for name, prec, lanes, mb in [("batched_split", binding.BF16_SPLIT, 2, 10**9),
-                                  ("one_at_a_time_fp32", binding.FP32, 1, 1)]:
+    for name, prec, lanes, mb, chunk in [("batched_split", binding.BF16_SPLIT, 2, 10**9, None),
+                                         ("one_at_a_time_fp32", binding.FP32, 1, 1, None)]:
         reqs = [serve.Request(r.rid, r.arrival, r.pos, r.species, r.box) for r in reqs_proto]
         model = engine.Model(beta, sigma, precision=prec)
         ex = serve.GpuExecutor(model, n_lanes=lanes, lane_atoms=400_000)
@@ -411,8 +411,9 @@ def serving(engine, torch, beta, sigma, n_req, rate, warmup=1000, pool=2000):
         serve.Scheduler(ex, max_batch=mb).run([serve.Request(-1 - k, 0.0, r.pos, r.species, r.box)
                                                for k, r in enumerate(reqs[:4])])
         torch.cuda.synchronize()
-        _, stats = serve.Scheduler(ex, max_batch=mb).run(reqs, warmup=warmup)
+        _, stats = serve.Scheduler(ex, max_batch=mb, chunk_atoms=chunk).run(reqs, warmup=warmup)
         stats = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+        stats["chunk_atoms"] = chunk
         stats["lanes"] = lanes
         stats["lane_state_bytes"] = int(ex.lane_bytes)
         out[name] = stats

@@ -16,7 +16,8 @@ Per-cell results do not depend on the batch composition (the library computes ea
 independently and gathers forces in a fixed order), so a structure gives the same bits
 alone and in any mix.
 
-Large requests (more atoms than `chunk_atoms`) are split by atom ranges: along the longer
+Requests larger than a lane, and optionally all above `chunk_atoms`, are split by atom
+ranges: along the longer
 lateral axis into equal slabs, each evaluated with a halo of 2 r_c (plus a margin) on both
 sides in a box widened so that no periodic image reaches across the cut. An atom's energy
 and uncertainty depend on its neighbours within r_c, and its force on the energies of
@@ -63,13 +64,23 @@ class Request:
         return self.t_done - self.arrival
 
 
-def split_request(r: Request, chunk_atoms: int, r_cut: float, margin: float = 0.5):
+def split_request(r: Request, chunk_atoms: int, r_cut: float, margin: float = 0.5, max_atoms: int | None = None):
     """Slabs of request r along its longer lateral axis, about chunk_atoms own atoms each,
     with a halo of 2 r_cut + margin on both sides; each slab's box along that axis is its
-    width plus r_cut + margin, so that no pair crosses the cut through a periodic image."""
+    width plus r_cut + margin, so that no pair crosses the cut through a periodic image.
+    With max_atoms, more slabs are taken until each (with its halo) holds at most that many
+    atoms. The request itself comes back when the slabs would be thinner than the halo."""
+    m = max(int(np.ceil(r.n / chunk_atoms)), 1)
+    while True:
+        slabs = _slabs(r, m, r_cut, margin)
+        if max_atoms is None or len(slabs) == 1 or max(c.n for c in slabs) <= max_atoms:
+            return slabs
+        m += 1
+
+
+def _slabs(r: Request, m: int, r_cut: float, margin: float):
     axis = 0 if r.box[0] >= r.box[1] else 1
     L = float(r.box[axis])
-    m = int(np.ceil(r.n / chunk_atoms))
     halo = 2.0 * r_cut + margin
     width = L / m
     if m < 2 or width < halo:
@@ -257,7 +268,8 @@ class Scheduler:
         self.ex = executor
         self.clock = clock
         self.max_batch = max_batch
-        # requests above chunk_atoms are split by atom ranges (None: never)
+        # requests above chunk_atoms are split by atom ranges; a request larger than a lane
+        # always is (into slabs of at most a lane each, about half a lane of own atoms)
         self.chunk_atoms = chunk_atoms
         self.r_cut = r_cut
         # called when nothing is ready: tests advance a fake clock; by default a short sleep
@@ -291,8 +303,10 @@ class Scheduler:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
-                if self.chunk_atoms is not None and r.n > self.chunk_atoms:
-                    slabs = split_request(r, self.chunk_atoms, self.r_cut)
+                lane = self.ex.lane_atoms
+                if r.n > lane or (self.chunk_atoms is not None and r.n > self.chunk_atoms):
+                    target = min(self.chunk_atoms or lane // 2, lane // 2)
+                    slabs = split_request(r, target, self.r_cut, max_atoms=lane)
                     if len(slabs) > 1:
                         open_slabs[id(r)] = [slabs, len(slabs)]
                     queue.extend(slabs)

@@ -36,7 +36,8 @@ def test_served_equals_alone_and_oracle():
 
 
 def test_chunked_requests_equal_whole_evaluation():
-    """Requests above the chunk size are served as slabs with halos (serve.split_request);
+    """Requests larger than a lane (6,000 atoms here) are served as slabs with halos
+    (serve.split_request), the others whole;
     the joined energies, forces and uncertainties agree with the whole structure evaluated
     alone to FP32 rounding: the slabs sum each atom's pair terms in another order, so the
     two FP32 results differ by about their own error against the FP64 values (forces
@@ -44,10 +45,10 @@ def test_chunked_requests_equal_whole_evaluation():
     beta, sigma = S.random_model(DEFAULT.n_desc)
     model = engine.Model(beta, sigma)
     reqs = serve.poisson_requests(12, rate=2000.0, sizes=(3000, 12000), seed=9)
-    print(f"case: serving 12 requests of {min(r.n for r in reqs)}..{max(r.n for r in reqs)} atoms in slabs of "
-          f"2,500", flush=True)
-    ex = serve.GpuExecutor(model, n_lanes=2, lane_atoms=40_000)
-    done, stats = serve.Scheduler(ex, chunk_atoms=2500).run(reqs)
+    print(f"case: serving 12 requests of {min(r.n for r in reqs)}..{max(r.n for r in reqs)} atoms on lanes of "
+          f"6,000", flush=True)
+    ex = serve.GpuExecutor(model, n_lanes=2, lane_atoms=6000)
+    done, stats = serve.Scheduler(ex).run(reqs)
     print(stats)
     assert stats["requests"] == len(reqs)
     for r in done:

@@ -166,3 +166,14 @@ def test_chunked_requests_are_joined_in_order():
     assert joined.t_done >= joined.t_start >= joined.arrival
     # the slabs went through the lanes as requests of their own
     assert sum(len(b) for b in ex.launched) == 2 + int(np.ceil(big.n / 2000))
+
+
+def test_request_larger_than_a_lane_is_split_to_fit():
+    clock = FakeClock()
+    ex = SlabExecutor(clock, lane_atoms=2500)
+    big = _slab_request()
+    done, stats = serve.Scheduler(ex, clock=clock, spin=clock.advance).run(
+        [serve.Request(0, 0.0, big.pos, big.species, big.box)])
+    assert len(done) == 1 and stats["requests"] == 1
+    np.testing.assert_array_equal(done[0].e, np.arange(big.n, dtype=np.float32))
+    assert len(ex.launched) >= int(np.ceil(big.n / 1250))     # slabs of about half a lane each
