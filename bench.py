@@ -463,6 +463,8 @@ def main():
     ap.add_argument("--no-huge", action="store_true", help="skip the ~16 M-atom precision leg")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "bf16x6", "bf16x6-var32"],
                     help="arithmetic form of the main MD leg (default fp32; the others for profiling)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured ceilings (library copy and GEMM), e.g. under a profiler")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy, a kernel of known traffic for counter scaling")
     args = ap.parse_args()
@@ -578,7 +580,7 @@ def main():
                    "n_desc": 544, "r_cut": 4.5, "skin": 0.2, "precision": args.precision},
         "roofline": roofline,
         "step_roofline": step_roofline,
-        "measured_ceilings": measured_ceilings(torch),
+        "measured_ceilings": None if args.no_ceilings else measured_ceilings(torch),
         "stage_us_per_launch": stage_us,
         "status_flags": status,
     }

@@ -827,11 +827,16 @@ __global__ __launch_bounds__(WW * 64, 1) void k_fused144_w(FusedArgs a, int nsub
   for (int st = blockIdx.x * WW + wv; st < nsub; st += nw) {
     const int row0 = st * WR;
     float c[NR][NQ];
+    // wave priorities by phase, for when both waves of a SIMD can issue: the matrix-core
+    // phase first (its MFMAs keep the shared datapath busy 32 cycles each and the other
+    // wave fills the gaps), then the descriptor phase (its pair loads start early), the
+    // adjoint phase last; measured 811 -> 786 us against the matrix phase alone raised,
+    // no gain with the adjoint level with the descriptors, a loss with the descriptors
+    // above the matrix phase
+    __builtin_amdgcn_s_setprio(1);
     desc_phase<PREC, false>(a, A, rs, row0, lane, c);
     wave_phase_fence();
-    // the matrix-core phase issues first when both waves of a SIMD are ready: its MFMAs
-    // keep the shared datapath busy for 32 cycles each, the other wave fills the gaps
-    __builtin_amdgcn_s_setprio(1);
+    __builtin_amdgcn_s_setprio(2);
     forms_phase<PREC, V64, false>(a, A, rs, row0, lane, tile_model(a, row0));
     __builtin_amdgcn_s_setprio(0);
     wave_phase_fence();
