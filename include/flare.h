@@ -159,7 +159,10 @@ int flare_descriptor_dim(const flare_model* model, int* n_d);
  * processed in chunks of that many). No later call allocates device memory, except the
  * first flare_virial (its task sums; flare_virial_noalloc allocates nothing).
  * flare_memory_bytes reports the total. One state serves one stream; calls on one state
- * must not overlap.
+ * must not overlap. The state also creates one internal stream (default priority, on the
+ * current device) and two events: with forces, the 544-wide rows run on it beside the
+ * single-species kernel, forked from and joined back into the caller's stream inside the
+ * call, so the caller's stream alone orders every result, as with one stream.
  */
 int flare_state_create(flare_state** out, const flare_model* model, int max_atoms,
                        long long max_pairs, void* stream);

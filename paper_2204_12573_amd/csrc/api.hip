@@ -502,6 +502,9 @@ static void free_state(flare_state* s) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   });
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->side) (void)hipStreamDestroy(s->side);
   if (s->h_info) (void)hipHostFree(s->h_info);
   if (s->h_stage) (void)hipHostFree(s->h_stage);
   s->red_w.release();
@@ -538,6 +541,9 @@ int flare_state_create(flare_state** out, const flare_model* model, int max_atom
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_info, 256, hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_stage, s->h_stage_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(s->d_status, 0, 64, s->stream);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     set_error(std::string("state allocation: ") + hipGetErrorString(e));
     free_state(s);
@@ -745,19 +751,39 @@ int flare_descriptors(flare_state* s, const double* x, const double* y, const do
 
 // Energies (and gradients), forces and variances of the positions staged last, up to the
 // per-row results (row_out is formed by the output kernels).
-static void evaluate_forms(flare_state* s, bool want_f, bool want_v) {
+static int evaluate_forms(flare_state* s, bool want_f, bool want_v) {
+  // With forces the mixed rows run on a second stream beside the fused kernel: both read
+  // the step's pair geometry and write disjoint rows and disjoint slots of w_in, so the
+  // mixed rows' kernels fill the fused kernel's tail. The main stream waits for them
+  // before anything that reads their results. With the stage timers on, everything runs
+  // in order on the one stream.
+  const bool beside = want_f && s->rowsx > 0 && !s->timers.on;
+  if (beside) {
+    CHK(hipEventRecord(s->ev_fork, s->stream));
+    CHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  }
   {
     // with forces, the fused kernel also runs the adjoint of the 144-wide rows in place
     StageTimer tm(s, FLARE_T_QFORM1);
     fused_quadratic_forms(s, 1 | (want_v ? 2 : 0) | (want_f ? 4 : 0), nullptr);
   }
-  mixed_rows(s, nullptr, true, want_v, want_f);
+  if (beside) {
+    hipStream_t main = s->stream;
+    s->stream = s->side;
+    mixed_rows(s, nullptr, true, want_v, want_f);
+    s->stream = main;
+    CHK(hipEventRecord(s->ev_join, s->side));
+    CHK(hipStreamWaitEvent(s->stream, s->ev_join, 0));
+  } else {
+    mixed_rows(s, nullptr, true, want_v, want_f);
+  }
   if (want_f) {
     s->w_gen = s->pos_gen;
     s->g_gen = -1;          // the 144-wide gradients stayed on chip
   } else {
     s->g_gen = s->pos_gen;
   }
+  return FLARE_OK;
 }
 
 int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, float* fz, double* e_struct,
@@ -770,7 +796,10 @@ int flare_energy_forces(flare_state* s, float* e_atom, float* fx, float* fy, flo
   const bool want_f = fx || fy || fz;
   ARG(!want_f || (fx && fy && fz), "pass all three force arrays or none");
   const bool want_v = var_atom || sigma_atom;
-  evaluate_forms(s, want_f, want_v);
+  {
+    const int rc = evaluate_forms(s, want_f, want_v);
+    if (rc != FLARE_OK) return rc;
+  }
   {
     StageTimer tm(s, FLARE_T_OUT);
     finalize_outputs(s, e_atom, fx, fy, fz, var_atom, sigma_atom);
@@ -955,7 +984,10 @@ int flare_md_step(flare_state* s, double* x, double* y, double* z, double* vx, d
   s->have_desc = true;
   s->pos_gen += 1;
   const bool want_v = var_atom || sigma_atom;
-  evaluate_forms(s, true, want_v);
+  {
+    const int rc = evaluate_forms(s, true, want_v);
+    if (rc != FLARE_OK) return rc;
+  }
   {
     StageTimer tm(s, FLARE_T_OUT);
     outputs_second_half(s, e_atom, fx, fy, fz, var_atom, sigma_atom, vx, vy, vz, species, im0, im1, dt);

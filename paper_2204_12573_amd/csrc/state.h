@@ -114,6 +114,8 @@ struct flare_model {
 struct flare_state {
   const flare_model* model = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;         // the mixed rows beside the fused kernel (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
   int max_atoms = 0;
   long long max_pairs = 0;
